@@ -1,0 +1,183 @@
+/*
+ * nxgraph.h -- C ABI of the MI355X (gfx950) DSSS graph-iteration library.
+ *
+ * The library stores a directed graph as Destination-Sorted Sub-Shards
+ * (DSSS; Chi et al., "NXgraph", Sec. II-A and Sec. III-A): the vertex ids
+ * [0, n) are cut into P equal intervals of size I (the last may be shorter);
+ * sub-shard SS_{i.j} holds the edges whose source lies in interval i and whose
+ * destination lies in interval j; inside a sub-shard edges are sorted by
+ * destination, then by source. One iteration (Alg. 1, Alg. 5) streams every
+ * sub-shard, gathers the source interval's values, reduces them by destination
+ * into the destination interval and applies the vertex update of the chosen
+ * program (PageRank, BFS, WCC).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers on the current HIP device; all
+ *    others are host pointers. Sizes are element counts unless named *_bytes.
+ *  - Vertex ids are 0-based int32 (the paper numbers vertices from 1).
+ *  - Calls are asynchronous on the given stream unless they say they
+ *    synchronise. Input buffers are borrowed for the duration of the call
+ *    only; nothing is retained.
+ *  - Every call returns an nxg_status. On failure a message is available
+ *    from nxg_last_error() (thread-local) and no output handle is created.
+ *    No C++ exception crosses this boundary.
+ */
+#ifndef NXGRAPH_H
+#define NXGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NXG_ABI_VERSION 1
+
+typedef enum nxg_status {
+    NXG_OK = 0,
+    NXG_EINVAL = 1,       /* invalid argument: null pointer, size, id out of range, flags */
+    NXG_ENOMEM = 2,       /* a device allocation failed; nothing was leaked */
+    NXG_EDEVICE = 3,      /* the HIP runtime reported an error */
+    NXG_ENOTCONV = 4,     /* tolerance not reached within max_iters; results are written */
+    NXG_EUNSUPPORTED = 5  /* a valid request that this library does not implement */
+} nxg_status;
+
+typedef struct nxg_dsss nxg_dsss; /* opaque graph handle */
+
+/* ------------------------------------------------------------------------- */
+/* Library state                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Device allocator used for every buffer the library owns. alloc returns a
+ * device pointer of at least `bytes` bytes (NULL = failure, reported as
+ * NXG_ENOMEM) usable on `stream`; free releases it. Passing NULL for both
+ * restores the default (hipMalloc / hipFree). Process-wide; set it before
+ * creating handles and keep it until they are destroyed. */
+typedef void* (*nxg_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*nxg_free_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
+nxg_status nxg_set_allocator(nxg_alloc_fn alloc_fn, nxg_free_fn free_fn, void* ctx);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* nxg_last_error(void);
+
+/* NXG_ABI_VERSION of the loaded library. */
+int nxg_abi_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* DSSS construction (Sec. III-A: intervals and sub-shards from an edge list)  */
+/* ------------------------------------------------------------------------- */
+
+#define NXG_BUILD_KEEP_PERM 0x1u  /* keep the map from stored edge to input edge index */
+#define NXG_BUILD_TRANSPOSE 0x2u  /* also store the reversed graph (source-sorted view) */
+#define NXG_BUILD_SYMMETRIZE 0x4u /* store E and reverse(E); implies NXG_BUILD_DEDUP */
+#define NXG_BUILD_DEDUP 0x8u      /* store each distinct (src, dst) pair once */
+
+typedef struct nxg_build_desc {
+    int32_t n;              /* vertices, >= 1 */
+    int64_t m;              /* input edges, >= 0 (< 2^31, and < 2^30 with SYMMETRIZE) */
+    const int32_t* d_src;   /* [m] source ids in [0, n) */
+    const int32_t* d_dst;   /* [m] destination ids in [0, n) */
+    const float* d_weight;  /* [m] edge weights, or NULL (unweighted) */
+    int32_t interval;       /* I, interval size; P = ceil(n / I). 0 = planner's choice */
+    int32_t tile;           /* destination tile, a power of two; 0 = planner's choice */
+    int32_t chunk;          /* edge-stream words per work chunk, power of two in
+                               [256, 65536]; 0 = planner's choice */
+    int32_t value_bytes;    /* bytes of one destination accumulator the tile must hold
+                               in LDS: 4 (FP32, int32), 8 (FP64), 4*B (batched B); 0 = 4 */
+    uint32_t flags;         /* NXG_BUILD_* */
+} nxg_build_desc;
+
+/* Builds the DSSS of the graph on `stream` and synchronises it once (to read
+ * the device error word and the sizes). Ids outside [0, n) give NXG_EINVAL.
+ * Weights require NXG_BUILD_KEEP_PERM semantics internally and are stored in
+ * DSSS order; they may not be combined with NXG_BUILD_SYMMETRIZE. On success
+ * *out owns every buffer; on failure *out is NULL. */
+nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** out);
+
+/* Releases every buffer of the handle. NULL is accepted. */
+nxg_status nxg_dsss_destroy(nxg_dsss* g);
+
+typedef struct nxg_dsss_info {
+    int32_t n;           /* vertices */
+    int64_t m;           /* stored edges (after DEDUP / SYMMETRIZE) */
+    int32_t interval;    /* I */
+    int32_t P;           /* number of intervals */
+    int32_t tile;        /* destination tile size T (T <= I) */
+    int32_t n_tiles;     /* destination tiles */
+    int32_t chunk;       /* words per chunk */
+    int64_t n_chunks;    /* chunks in the edge stream */
+    int64_t n_words;     /* 32-bit words in the edge stream (edges + markers + padding) */
+    int64_t device_bytes;/* bytes held on the device by the handle */
+    int64_t max_tile_edges; /* edges of the heaviest destination tile */
+    int32_t has_perm, has_weights, has_transpose;
+} nxg_dsss_info;
+
+nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
+
+/* Copies the stored graph back out, for structure checks. All outputs are
+ * device buffers the caller owns; any may be NULL.
+ *   d_offsets [P*P + 1]  first edge of SS_{i.j} at index j*P + i, in the order
+ *                         of Sec. II-A (shards of increasing j, sub-shards of
+ *                         increasing i) -- counts follow the paper's layout;
+ *   d_src, d_dst [m]     edges in stream order: destination tile, then source
+ *                         interval, then destination, then source. When the
+ *                         tile equals the interval this is exactly the DSSS
+ *                         order of Sec. II-A/III-A;
+ *   d_perm [m]           input index of each stored edge (needs KEEP_PERM).
+ * transposed != 0 exports the reversed graph instead (needs TRANSPOSE).
+ * Synchronises the stream. */
+nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets,
+                           int32_t* d_src, int32_t* d_dst, int32_t* d_perm, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Iterations (Alg. 1 update model, synchronous per Sec. II-B)                */
+/* ------------------------------------------------------------------------- */
+
+typedef enum nxg_program {
+    NXG_PAGERANK = 0,          /* x' = d (W x + delta/n) + (1-d) t, W = 1/outdeg */
+    NXG_PAGERANK_WEIGHTED = 1, /* same with the stored edge weights as W */
+    NXG_BFS = 2,               /* Algs. 2-4: levels from a root, INT32_MAX = unreached */
+    NXG_WCC = 3                /* min-label propagation; needs a SYMMETRIZE build */
+} nxg_program;
+
+typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
+
+#define NXG_RUN_WARM_START 0x1u /* d_values holds x^0 on entry (PageRank) */
+
+typedef struct nxg_run_desc {
+    nxg_program program;
+    nxg_dtype dtype;        /* F32 or F64 for PageRank, I32 for BFS/WCC */
+    int32_t batch;          /* B >= 1 value columns (PageRank only; B > 1 = batched PPR) */
+    double damping;         /* d in [0, 1) */
+    int32_t max_iters;      /* upper bound on iterations (>= 0) */
+    double tol;             /* PageRank: stop when ||x^{k+1}-x^k||_1 <= tol (per column);
+                               <= 0 runs exactly max_iters. BFS/WCC ignore it and stop
+                               when a round changes nothing (bounded by max_iters). */
+    const void* d_teleport; /* [n, B] row-major, dtype of the run; NULL = uniform 1/n */
+    const int32_t* roots;   /* BFS: host [B] root ids */
+    void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC label) */
+    uint32_t flags;         /* NXG_RUN_* */
+} nxg_run_desc;
+
+typedef struct nxg_run_stats {
+    int32_t iterations;     /* iterations (rounds) run */
+    int32_t converged;      /* PageRank: tol reached; BFS/WCC: fixed point reached */
+    double residual;        /* last ||x^{k+1}-x^k||_1 (max over columns) */
+    int32_t max_level;      /* BFS: largest finite level (Alg. 4) */
+    int32_t changed_rounds; /* BFS/WCC: rounds that changed at least one value */
+    int64_t reached_edges;  /* BFS: sum of out-degrees of reached vertices */
+    double device_ms;       /* time between the first and last launch, HIP events */
+} nxg_run_stats;
+
+/* Runs the program on the stored graph. With stats == NULL the call is fully
+ * asynchronous (PageRank with tol <= 0 only); otherwise it synchronises the
+ * stream and fills *stats. Returns NXG_ENOTCONV when tol > 0 was not reached
+ * (values are still written). */
+nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NXGRAPH_H */

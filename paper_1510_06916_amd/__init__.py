@@ -1,0 +1,197 @@
+"""MI355X DSSS graph-iteration library: Python binding of include/nxgraph.h.
+
+Every step of the graph method runs in the HIP library (libnxgraph.so); this
+module only marshals torch tensors (device memory, streams) into the C ABI. It
+raises if the library is not built or no GPU is visible -- there is no CPU path.
+
+    g = DSSS.build(src, dst, n, P=32)          # int32 device tensors
+    x, st = g.pagerank(iters=20, dtype=torch.float32)
+    lev, st = g.bfs(root)
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import NxgError  # noqa: F401
+
+__all__ = ["DSSS", "NxgError", "abi_version", "install_torch_allocator"]
+
+_alloc_refs = None
+
+
+def abi_version():
+    return _lib.lib().nxg_abi_version()
+
+
+def install_torch_allocator():
+    """Routes every device allocation of the library through torch's caching
+    allocator, so all device memory is torch's (idempotent)."""
+    global _alloc_refs
+    if _alloc_refs is not None:
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      int(stream or 0))
+        except Exception:  # reported to the caller as NXG_ENOMEM
+            return None
+
+    def _free(ptr, nbytes, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    _lib.check(_lib.lib().nxg_set_allocator(refs[0], refs[1], None), "nxg_set_allocator")
+    _alloc_refs = refs
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dtype != torch.int32:
+        raise ValueError("%s must be int32" % name)
+    return t.contiguous()
+
+
+_DT = {torch.float32: _lib.NXG_F32, torch.float64: _lib.NXG_F64}
+
+
+class DSSS:
+    """A graph stored as destination-sorted sub-shards on one GPU."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+        self._info = None
+
+    # ---- construction ---------------------------------------------------
+    @classmethod
+    def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
+              value_bytes=4, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
+              stream=None):
+        install_torch_allocator()
+        src = _dev_i32(src, "src")
+        dst = _dev_i32(dst, "dst")
+        if src.numel() != dst.numel():
+            raise ValueError("src and dst differ in length")
+        n = int(n)
+        if interval is None:
+            interval = 0 if P is None else -(-n // int(P))
+        w = None
+        if weights is not None:
+            w = weights.to(device=src.device, dtype=torch.float32).contiguous()
+            if w.numel() != src.numel():
+                raise ValueError("weights must have one entry per edge")
+        flags = ((_lib.NXG_BUILD_KEEP_PERM if keep_perm else 0) |
+                 (_lib.NXG_BUILD_TRANSPOSE if transpose else 0) |
+                 (_lib.NXG_BUILD_SYMMETRIZE if symmetrize else 0) |
+                 (_lib.NXG_BUILD_DEDUP if dedup else 0))
+        d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
+                           d_dst=dst.data_ptr() if dst.numel() else None,
+                           d_weight=w.data_ptr() if w is not None else None,
+                           interval=int(interval), tile=int(tile), chunk=int(chunk),
+                           value_bytes=int(value_bytes), flags=flags)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(src.device):
+            _lib.check(_lib.lib().nxg_dsss_build(ctypes.byref(d), _stream_handle(stream),
+                                                 ctypes.byref(h)), "nxg_dsss_build")
+        return cls(h, src.device)
+
+    def close(self):
+        if self._h:
+            _lib.lib().nxg_dsss_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        if self._info is None:
+            inf = _lib.DsssInfo()
+            _lib.check(_lib.lib().nxg_dsss_info_get(self._h, ctypes.byref(inf)), "nxg_dsss_info_get")
+            self._info = {k: getattr(inf, k) for k, _ in inf._fields_}
+        return self._info
+
+    @property
+    def n(self):
+        return self.info()["n"]
+
+    @property
+    def m(self):
+        return self.info()["m"]
+
+    def export(self, transposed=False, perm=False):
+        """Offsets [P*P+1] (paper order j*P+i) and the stored edges in stream order."""
+        inf = self.info()
+        P, m = inf["P"], inf["m"]
+        dev = self.device
+        off = torch.empty(P * P + 1, dtype=torch.int64, device=dev)
+        s = torch.empty(m, dtype=torch.int32, device=dev)
+        t = torch.empty(m, dtype=torch.int32, device=dev)
+        pm = torch.empty(m, dtype=torch.int32, device=dev) if perm else None
+        _lib.check(_lib.lib().nxg_dsss_export(
+            self._h, 1 if transposed else 0, off.data_ptr(), s.data_ptr() if m else None,
+            t.data_ptr() if m else None, pm.data_ptr() if (pm is not None and m) else None,
+            _stream_handle()), "nxg_dsss_export")
+        out = {"offsets": off, "src": s, "dst": t}
+        if perm:
+            out["perm"] = pm
+        return out
+
+    # ---- programs -------------------------------------------------------
+    def _run(self, desc, allow=()):
+        st = _lib.RunStats()
+        with torch.cuda.device(self.device):
+            rc = _lib.check(_lib.lib().nxg_run(self._h, ctypes.byref(desc), _stream_handle(),
+                                               ctypes.byref(st)), "nxg_run", allow=allow)
+        out = st.as_dict()
+        out["status"] = rc
+        return out
+
+    def pagerank(self, iters, damping=0.85, dtype=torch.float32, tol=0.0, teleport=None,
+                 x0=None, weighted=False, out=None):
+        n = self.n
+        if dtype not in _DT:
+            raise ValueError("dtype must be float32 or float64")
+        x = out if out is not None else torch.empty(n, dtype=dtype, device=self.device)
+        flags = 0
+        if x0 is not None:
+            x.copy_(x0)
+            flags |= _lib.NXG_RUN_WARM_START
+        tp = None
+        if teleport is not None:
+            tp = teleport.to(device=self.device, dtype=dtype).contiguous()
+        d = _lib.RunDesc(program=_lib.NXG_PAGERANK_WEIGHTED if weighted else _lib.NXG_PAGERANK,
+                         dtype=_DT[dtype], batch=1, damping=float(damping),
+                         max_iters=int(iters), tol=float(tol),
+                         d_teleport=tp.data_ptr() if tp is not None else None, roots=None,
+                         d_values=x.data_ptr(), flags=flags)
+        st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
+        return x, st
+
+    def bfs(self, root, max_rounds=None):
+        n = self.n
+        lev = torch.empty(n, dtype=torch.int32, device=self.device)
+        roots = (ctypes.c_int32 * 1)(int(root))
+        d = _lib.RunDesc(program=_lib.NXG_BFS, dtype=_lib.NXG_I32, batch=1, damping=0.0,
+                         max_iters=int(max_rounds if max_rounds is not None else n + 1), tol=0.0,
+                         d_teleport=None, roots=ctypes.cast(roots, ctypes.c_void_p),
+                         d_values=lev.data_ptr(), flags=0)
+        return lev, self._run(d)
+
+    def wcc(self, max_rounds=None):
+        n = self.n
+        lab = torch.empty(n, dtype=torch.int32, device=self.device)
+        d = _lib.RunDesc(program=_lib.NXG_WCC, dtype=_lib.NXG_I32, batch=1, damping=0.0,
+                         max_iters=int(max_rounds if max_rounds is not None else n + 1), tol=0.0,
+                         d_teleport=None, roots=None, d_values=lab.data_ptr(), flags=0)
+        return lab, self._run(d)

@@ -1,0 +1,105 @@
+"""ctypes declarations of include/nxgraph.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnxgraph.so")
+
+NXG_OK, NXG_EINVAL, NXG_ENOMEM, NXG_EDEVICE, NXG_ENOTCONV, NXG_EUNSUPPORTED = range(6)
+STATUS_NAMES = {0: "NXG_OK", 1: "NXG_EINVAL", 2: "NXG_ENOMEM", 3: "NXG_EDEVICE",
+                4: "NXG_ENOTCONV", 5: "NXG_EUNSUPPORTED"}
+
+NXG_BUILD_KEEP_PERM = 0x1
+NXG_BUILD_TRANSPOSE = 0x2
+NXG_BUILD_SYMMETRIZE = 0x4
+NXG_BUILD_DEDUP = 0x8
+
+NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
+NXG_F32, NXG_F64, NXG_I32 = range(3)
+NXG_RUN_WARM_START = 0x1
+
+
+class BuildDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("d_src", ctypes.c_void_p),
+                ("d_dst", ctypes.c_void_p), ("d_weight", ctypes.c_void_p),
+                ("interval", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("value_bytes", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class DsssInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("interval", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("tile", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("n_chunks", ctypes.c_int64),
+                ("n_words", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("max_tile_edges", ctypes.c_int64), ("has_perm", ctypes.c_int32),
+                ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32)]
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [("program", ctypes.c_int), ("dtype", ctypes.c_int), ("batch", ctypes.c_int32),
+                ("damping", ctypes.c_double), ("max_iters", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("d_teleport", ctypes.c_void_p),
+                ("roots", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("max_level", ctypes.c_int32),
+                ("changed_rounds", ctypes.c_int32), ("reached_edges", ctypes.c_int64),
+                ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                           ctypes.c_void_p)
+
+# name -> (restype, argtypes); every symbol the header declares
+SIGNATURES = {
+    "nxg_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, ctypes.c_void_p]),
+    "nxg_last_error": (ctypes.c_char_p, []),
+    "nxg_abi_version": (ctypes.c_int, []),
+    "nxg_dsss_build": (ctypes.c_int, [ctypes.POINTER(BuildDesc), ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "nxg_dsss_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nxg_dsss_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DsssInfo)]),
+    "nxg_dsss_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "nxg_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunDesc), ctypes.c_void_p,
+                               ctypes.POINTER(RunStats)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libnxgraph.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnxgraph.so is not built: run paper_1510_06916_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class NxgError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().nxg_last_error().decode()
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def check(status, where, allow=()):
+    if status != NXG_OK and status not in allow:
+        raise NxgError(status, where)
+    return status

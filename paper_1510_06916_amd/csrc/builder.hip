@@ -1,0 +1,736 @@
+// DSSS construction on the GPU (Sec. III-A "Sharding"): every edge is placed in
+// its sub-shard, sub-shards are destination-sorted (ties by source), shards are
+// stored contiguously, and the offset tables are derived. The sort is a
+// hand-written LSD radix sort over 64-bit keys whose bit fields are, from the
+// top: destination tile, source interval, destination within the tile, source
+// within the interval. The edge word is the key's low L + t bits.
+#include <algorithm>
+#include <cstring>
+
+#include "nxg_internal.h"
+
+namespace nxg {
+namespace {
+
+constexpr int kRsBlock = 256;  // threads of the radix-sort kernels (4 wavefronts)
+constexpr int kRsItems = 8;    // keys per thread per step
+constexpr uint32_t kPad = 0xFFFFFFFFu;
+constexpr uint32_t kMarker = 0x80000000u;
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Lanes of the wavefront holding the same 8-bit digit as this lane.
+__device__ inline uint64_t match_digit(uint32_t digit, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        uint32_t bit = (digit >> b) & 1u;
+        uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+struct KeyGeom {
+    int32_t n, I, T, tpi, P, L, t;
+};
+
+// Validates ids and forms keys; payload = input edge index. With sym != 0 the
+// input is E followed by reverse(E) (2m keys). rev != 0 swaps src and dst.
+__global__ void k_make_keys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                            int64_t m, int sym, int rev, KeyGeom g, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals, int32_t* __restrict__ err) {
+    const int64_t total = sym ? 2 * m : m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = e < m ? e : e - m;
+        int32_t s = src[k], d = dst[k];
+        if ((e >= m) != (rev != 0)) {
+            int32_t x = s;
+            s = d;
+            d = x;
+        }
+        if (s < 0 || s >= g.n || d < 0 || d >= g.n) {
+            atomicOr(err, 1);
+            s = 0;
+            d = 0;
+        }
+        uint32_t j = (uint32_t)d / (uint32_t)g.I;
+        uint32_t dj = (uint32_t)d - j * (uint32_t)g.I;
+        uint32_t q = dj >> g.t;
+        uint32_t dt = dj & ((1u << g.t) - 1u);
+        uint32_t i = (uint32_t)s / (uint32_t)g.I;
+        uint32_t sl = (uint32_t)s - i * (uint32_t)g.I;
+        uint64_t grp = ((uint64_t)j * g.tpi + q) * (uint64_t)g.P + i;
+        keys[e] = (grp << (g.t + g.L)) | ((uint64_t)dt << g.L) | sl;
+        if (vals) vals[e] = (uint32_t)k;
+    }
+}
+
+// ---- LSD radix sort, 8-bit digits ---------------------------------------
+
+__global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint64_t* __restrict__ keys,
+                                                        int64_t m, int64_t per_block, int shift,
+                                                        uint32_t* __restrict__ hist, int nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = min(m, b0 + per_block);
+    for (int64_t e0 = b0; e0 < b1; e0 += kRsBlock) {
+        int64_t e = e0 + threadIdx.x;
+        bool valid = e < b1;
+        uint32_t dig = valid ? (uint32_t)(keys[e] >> shift) & 255u : 0u;
+        uint64_t peers = match_digit(dig, __ballot(valid));
+        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of N uint32 counts into int64 offsets, one block of 1024.
+__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t* __restrict__ in,
+                                                   int64_t* __restrict__ out, int64_t N,
+                                                   int64_t* __restrict__ total) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (N + 1023) / 1024;
+    const int64_t a = threadIdx.x * per, b = min(N, a + per);
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += in[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = a; i < b; ++i) {
+        uint32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (total && threadIdx.x == 1023) *total = part[1023];
+}
+
+// Stable scatter: inside a block keys are ranked in input order (step, thread).
+template <bool kVal>
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t m, int64_t per_block,
+    int shift, const int64_t* __restrict__ offs, int nb) {
+    __shared__ int64_t run[256];
+    __shared__ uint32_t wc[4][256];
+    __shared__ int64_t wo[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = min(m, b0 + per_block);
+    for (int64_t s0 = b0; s0 < b1; s0 += (int64_t)kRsBlock * kRsItems) {
+        uint64_t key[kRsItems];
+        uint32_t val[kRsItems];
+#pragma unroll
+        for (int k = 0; k < kRsItems; ++k) {
+            int64_t e = s0 + (int64_t)k * kRsBlock + tid;
+            key[k] = e < b1 ? kin[e] : 0ull;
+            val[k] = (kVal && e < b1) ? vin[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kRsItems; ++k) {
+            int64_t e = s0 + (int64_t)k * kRsBlock + tid;
+            bool valid = e < b1;
+            uint32_t dig = (uint32_t)(key[k] >> shift) & 255u;
+            uint64_t peers = match_digit(dig, __ballot(valid));
+            uint64_t lower = peers & lanemask_lt();
+            if (valid && lower == 0) wc[wave][dig] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            {
+                int64_t r = run[tid];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    wo[w][tid] = r;
+                    r += wc[w][tid];
+                    wc[w][tid] = 0;
+                }
+                run[tid] = r;
+            }
+            __syncthreads();
+            if (valid) {
+                int64_t pos = wo[wave][dig] + __popcll(lower);
+                kout[pos] = key[k];
+                if (kVal) vout[pos] = val[k];
+            }
+        }
+    }
+}
+
+// ---- de-duplication of a sorted key array (stable compaction) -----------
+
+__global__ __launch_bounds__(kRsBlock) void k_uniq_count(const uint64_t* __restrict__ keys,
+                                                          int64_t m, int64_t per_block,
+                                                          uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t c;
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = min(m, b0 + per_block);
+    uint32_t mine = 0;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kRsBlock)
+        mine += (e == 0 || keys[e] != keys[e - 1]) ? 1u : 0u;
+    atomicAdd(&c, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+template <bool kVal>
+__global__ __launch_bounds__(kRsBlock) void k_uniq_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t m, int64_t per_block,
+    const int64_t* __restrict__ boff) {
+    __shared__ uint32_t wsum[4];
+    __shared__ int64_t run;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    if (tid == 0) run = boff[blockIdx.x];
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = min(m, b0 + per_block);
+    for (int64_t e0 = b0; e0 < b1; e0 += kRsBlock) {
+        int64_t e = e0 + tid;
+        bool keep = e < b1 && (e == 0 || kin[e] != kin[e - 1]);
+        uint64_t bal = __ballot(keep);
+        if (lane_id() == 0) wsum[wave] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        int64_t before = run;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (keep) {
+            int64_t pos = before + __popcll(bal & lanemask_lt());
+            kout[pos] = kin[e];
+            if (kVal) vout[pos] = vin[e];
+        }
+        __syncthreads();
+        if (tid == 0) run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+}
+
+// ---- layout ---------------------------------------------------------------
+
+__global__ void k_outdeg(const uint64_t* __restrict__ keys, int64_t m, KeyGeom g,
+                         int32_t* __restrict__ deg) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = keys[e];
+        uint32_t i = (uint32_t)((k >> (g.t + g.L)) % (uint64_t)g.P);
+        uint32_t s = i * (uint32_t)g.I + (uint32_t)(k & ((1ull << g.L) - 1ull));
+        atomicAdd(&deg[s], 1);
+    }
+}
+
+// group_edge[g] = first sorted index whose group is >= g, for g in [0, G].
+__global__ void k_group_bounds(const uint64_t* __restrict__ keys, int64_t m, int64_t G, int sh,
+                               int64_t* __restrict__ gbeg) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(keys[mid] >> sh) < g)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        gbeg[g] = lo;
+    }
+}
+
+// One block per tile: word offsets of the tile's groups (relative to the
+// tile), the tile's word count and its edge count.
+__global__ __launch_bounds__(1024) void k_tile_words(const int64_t* __restrict__ gbeg, int P,
+                                                     int64_t* __restrict__ gword,
+                                                     int64_t* __restrict__ tile_words,
+                                                     int64_t* __restrict__ tile_edges) {
+    __shared__ int64_t part[1024];
+    const int64_t tau = blockIdx.x;
+    const int64_t g0 = tau * P;
+    const int per = (P + 1023) / 1024;
+    const int a = threadIdx.x * per, b = min(P, a + per);
+    int64_t s = 0;
+    for (int i = a; i < b; ++i) {
+        int64_t c = gbeg[g0 + i + 1] - gbeg[g0 + i];
+        s += c ? c + 1 : 0;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = a; i < b; ++i) {
+        int64_t c = gbeg[g0 + i + 1] - gbeg[g0 + i];
+        gword[g0 + i] = run;
+        run += c ? c + 1 : 0;
+    }
+    if (threadIdx.x == 1023) {
+        tile_words[tau] = part[1023];
+        tile_edges[tau] = gbeg[g0 + P] - gbeg[g0];
+    }
+}
+
+__global__ void k_group_word_abs(int64_t* __restrict__ gword, const int64_t* __restrict__ tchunk,
+                                 int64_t G, int P, int C, int64_t total_words) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (g == G)
+            gword[g] = total_words;
+        else
+            gword[g] += tchunk[g / P] * (int64_t)C;
+    }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_scatter_words(const uint64_t* __restrict__ keys,
+                                const uint32_t* __restrict__ vals, int64_t m, int sh, int P,
+                                const int64_t* __restrict__ gbeg,
+                                const int64_t* __restrict__ gword, uint32_t* __restrict__ words,
+                                int32_t* __restrict__ perm, const float* __restrict__ win,
+                                float* __restrict__ wout) {
+    const uint64_t low = (1ull << sh) - 1ull;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = keys[e];
+        int64_t g = (int64_t)(k >> sh);
+        int64_t pos = gword[g] + 1 + (e - gbeg[g]);
+        words[pos] = (uint32_t)(k & low);
+        if (perm) perm[pos] = (int32_t)vals[e];
+        if (wout) wout[pos] = win[vals[e]];
+    }
+}
+
+__global__ void k_markers(const int64_t* __restrict__ gbeg, const int64_t* __restrict__ gword,
+                          int64_t G, int P, uint32_t* __restrict__ words) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (gbeg[g + 1] > gbeg[g]) words[gword[g]] = kMarker | (uint32_t)(g % P);
+    }
+}
+
+// Largest group g in [g0, g0 + P) with gword[g] <= pos (gword is monotone).
+__device__ inline int64_t last_group_at(const int64_t* gword, int64_t g0, int P, int64_t pos) {
+    int64_t lo = g0, hi = g0 + P;  // answer in [g0, g0+P)
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (gword[mid] <= pos)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_chunk_rows(const int64_t* __restrict__ tchunk,
+                             const int64_t* __restrict__ twords, int n_tiles,
+                             const int64_t* __restrict__ gword, int P, int C,
+                             int64_t n_chunks, int32_t* __restrict__ crow,
+                             int32_t* __restrict__ crow_last) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        // tile owning chunk c: last tau with tchunk[tau] <= c
+        int lo = 0, hi = n_tiles;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tchunk[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t g0 = (int64_t)lo * P;
+        const int64_t first = c * (int64_t)C;
+        // end of the tile's real words (markers + edges, before padding); trailing
+        // empty groups sit exactly there, so searching strictly below it only ever
+        // lands on non-empty groups
+        const int64_t real_end = tchunk[lo] * (int64_t)C + twords[lo];
+        crow[c] = (int32_t)(last_group_at(gword, g0, P, first) - g0);
+        int64_t last = min(first + C - 1, real_end - 1);
+        crow_last[c] = (int32_t)(last_group_at(gword, g0, P, last) - g0);
+    }
+}
+
+// Decodes the stream back to edges (one thread per chunk), for export.
+__global__ void k_decode(const uint32_t* __restrict__ words, const int64_t* __restrict__ tchunk,
+                         int n_tiles, const int32_t* __restrict__ crow,
+                         const int64_t* __restrict__ gbeg, const int64_t* __restrict__ gword,
+                         KeyGeom g, int C, int64_t n_chunks, const int32_t* __restrict__ perm_in,
+                         int32_t* __restrict__ osrc, int32_t* __restrict__ odst,
+                         int32_t* __restrict__ operm) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_tiles;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tchunk[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int tau = lo;
+        const int64_t g0 = (int64_t)tau * g.P;
+        const int j = tau / g.tpi, q = tau - j * g.tpi;
+        const int64_t tbase = (int64_t)j * g.I + (int64_t)q * g.T;
+        int64_t row = crow[c];
+        for (int64_t pos = c * (int64_t)C; pos < (c + 1) * (int64_t)C; ++pos) {
+            uint32_t w = words[pos];
+            if (w & kMarker) {
+                row = w & ~kMarker;
+                continue;
+            }
+            int64_t grp = g0 + row;
+            int64_t e = gbeg[grp] + (pos - gword[grp] - 1);
+            if (osrc) osrc[e] = (int32_t)(row * g.I + (w & ((1u << g.L) - 1u)));
+            if (odst) odst[e] = (int32_t)(tbase + ((w >> g.L) & ((1u << g.t) - 1u)));
+            if (operm) operm[e] = perm_in[pos];
+        }
+    }
+}
+
+__global__ void k_logical_counts(const int64_t* __restrict__ gbeg, KeyGeom g,
+                                 int64_t* __restrict__ cnt) {
+    // cnt[j*P + i] += edges of group ((j*tpi + q)*P + i)
+    const int64_t G = (int64_t)g.P * g.tpi * g.P;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < G;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        int64_t tau = x / g.P, i = x - tau * g.P;
+        int64_t j = tau / g.tpi;
+        int64_t c = gbeg[x + 1] - gbeg[x];
+        if (c) atomicAdd((unsigned long long*)&cnt[j * g.P + i], (unsigned long long)c);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_i64_inplace_excl(int64_t* __restrict__ a,
+                                                                int64_t N) {
+    // a[0..N) counts -> a[0..N] exclusive offsets (a[N] = total); one block.
+    __shared__ int64_t part[1024];
+    const int64_t per = (N + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = min(N, lo + per);
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a[N] = part[1023];
+}
+
+inline int grid_for(int64_t work, int threads = 256) {
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (int)b;
+}
+
+int ceil_log2(int64_t x) {
+    int b = 0;
+    while ((int64_t(1) << b) < x) ++b;
+    return b;
+}
+
+// Sorts keys (and optional payload) in place; returns which buffer holds the result.
+int radix_sort(DevBuf* kb, DevBuf* vb, int64_t m, int bits, hipStream_t s) {
+    if (m <= 1 || bits <= 0) return 0;
+    const int64_t tile = (int64_t)kRsBlock * kRsItems;
+    int64_t nb64 = std::min<int64_t>(2048, (m + tile - 1) / tile);
+    const int nb = (int)std::max<int64_t>(1, nb64);
+    int64_t per_block = (m + nb - 1) / nb;
+    per_block = (per_block + tile - 1) / tile * tile;
+    DevBuf hist, offs;
+    hist.alloc(sizeof(uint32_t) * 256 * nb, s);
+    offs.alloc(sizeof(int64_t) * 256 * nb, s);
+    int cur = 0;
+    const bool hv = vb[0].p != nullptr;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_count, dim3(nb), dim3(kRsBlock), 0, s, kb[cur].as<uint64_t>(), m,
+                           per_block, shift, hist.as<uint32_t>(), nb);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist.as<uint32_t>(),
+                           offs.as<int64_t>(), (int64_t)256 * nb, (int64_t*)nullptr);
+        NXG_CHECK_LAUNCH();
+        if (hv)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kRsBlock), 0, s,
+                               kb[cur].as<uint64_t>(), vb[cur].as<uint32_t>(),
+                               kb[cur ^ 1].as<uint64_t>(), vb[cur ^ 1].as<uint32_t>(), m,
+                               per_block, shift, offs.as<int64_t>(), nb);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(kRsBlock), 0, s,
+                               kb[cur].as<uint64_t>(), (const uint32_t*)nullptr,
+                               kb[cur ^ 1].as<uint64_t>(), (uint32_t*)nullptr, m, per_block,
+                               shift, offs.as<int64_t>(), nb);
+        NXG_CHECK_LAUNCH();
+        cur ^= 1;
+    }
+    return cur;
+}
+
+// Stable de-duplication of sorted keys from buffer `cur` into `cur ^ 1`.
+int64_t dedup(DevBuf* kb, DevBuf* vb, int cur, int64_t m, hipStream_t s) {
+    if (m == 0) return 0;
+    const int64_t tile = kRsBlock * 16;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (m + tile - 1) / tile));
+    int64_t per_block = (m + nb - 1) / nb;
+    DevBuf cnt, off;
+    cnt.alloc(sizeof(uint32_t) * nb, s);
+    off.alloc(sizeof(int64_t) * (nb + 1), s);
+    hipLaunchKernelGGL(k_uniq_count, dim3(nb), dim3(kRsBlock), 0, s, kb[cur].as<uint64_t>(), m,
+                       per_block, cnt.as<uint32_t>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, cnt.as<uint32_t>(),
+                       off.as<int64_t>(), (int64_t)nb, off.as<int64_t>() + nb);
+    NXG_CHECK_LAUNCH();
+    if (vb[0].p)
+        hipLaunchKernelGGL(k_uniq_scatter<true>, dim3(nb), dim3(kRsBlock), 0, s,
+                           kb[cur].as<uint64_t>(), vb[cur].as<uint32_t>(),
+                           kb[cur ^ 1].as<uint64_t>(), vb[cur ^ 1].as<uint32_t>(), m, per_block,
+                           off.as<int64_t>());
+    else
+        hipLaunchKernelGGL(k_uniq_scatter<false>, dim3(nb), dim3(kRsBlock), 0, s,
+                           kb[cur].as<uint64_t>(), (const uint32_t*)nullptr,
+                           kb[cur ^ 1].as<uint64_t>(), (uint32_t*)nullptr, m, per_block,
+                           off.as<int64_t>());
+    NXG_CHECK_LAUNCH();
+    int64_t mu = 0;
+    NXG_HIP(hipMemcpyAsync(&mu, off.as<int64_t>() + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    return mu;
+}
+
+}  // namespace
+
+void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
+    const int64_t n = d.n;
+    int vb = d.value_bytes ? d.value_bytes : 4;
+    if (vb < 1 || vb > 65536) fail(NXG_EINVAL, "value_bytes out of range");
+    const int budget = lds_budget_bytes(device);
+    int64_t tmax = 1;
+    while (tmax * 2 * vb <= budget && tmax * 2 <= (1 << 20)) tmax *= 2;
+    if (tmax * vb > budget) fail(NXG_EINVAL, "value_bytes too large for the LDS of one workgroup");
+    int64_t I = d.interval;
+    if (I < 0) fail(NXG_EINVAL, "interval must be >= 0");
+    if (I == 0) {
+        // square DSSS with the interval equal to the largest tile that fits in LDS,
+        // but never fewer than ~sqrt(n) vertices per interval (keeps P <= I)
+        I = tmax;
+        while (I * I < n) I *= 2;
+        if (I > n) I = n;
+    }
+    if (I > n) I = n;
+    L.n = (int32_t)n;
+    L.I = (int32_t)I;
+    L.P = (int32_t)((n + I - 1) / I);
+    L.L = ceil_log2(I);
+    if (L.L > 30) fail(NXG_EINVAL, "interval too large");
+    int64_t T = d.tile;
+    if (T < 0 || (T & (T - 1))) fail(NXG_EINVAL, "tile must be 0 or a power of two");
+    if (T == 0) T = tmax;
+    if (T * vb > budget) fail(NXG_EINVAL, "tile * value_bytes exceeds the LDS of one workgroup");
+    int64_t Ip2 = int64_t(1) << L.L;
+    if (T > Ip2) T = Ip2;
+    while (L.L + ceil_log2(T) > 31) T >>= 1;
+    if (T < 1) T = 1;
+    L.T = (int32_t)T;
+    L.t = ceil_log2(T);
+    L.tpi = (int32_t)((I + T - 1) / T);
+    int64_t nt = (int64_t)L.P * L.tpi;
+    if (nt > (int64_t)1 << 24) fail(NXG_EINVAL, "too many destination tiles");
+    int64_t G = nt * L.P;
+    if (G > (int64_t)1 << 28) fail(NXG_EINVAL, "too many sub-shard groups (P too large)");
+    if (ceil_log2(G) + L.t + L.L > 64) fail(NXG_EINVAL, "key does not fit in 64 bits");
+    L.n_tiles = (int32_t)nt;
+    int64_t C = d.chunk;
+    if (C == 0) {
+        int64_t per_tile = (d.m + nt - 1) / std::max<int64_t>(nt, 1);
+        C = per_tile >= 65536 ? 2048 : (per_tile >= 8192 ? 1024 : 256);
+    }
+    if (C < 256 || C > 65536 || (C & (C - 1))) fail(NXG_EINVAL, "chunk must be a power of two in [256, 65536]");
+    L.C = (int32_t)C;
+}
+
+void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& L) {
+    int device = 0;
+    NXG_HIP(hipGetDevice(&device));
+    plan_geometry(d, device, L);
+    const bool sym = (d.flags & NXG_BUILD_SYMMETRIZE) != 0;
+    const bool dedup_req = sym || (d.flags & NXG_BUILD_DEDUP);
+    const bool want_perm = (d.flags & NXG_BUILD_KEEP_PERM) != 0;
+    const bool want_w = d.d_weight != nullptr;
+    const bool payload = want_perm || want_w;
+    const int64_t mt = sym ? 2 * d.m : d.m;
+
+    KeyGeom g{L.n, L.I, L.T, L.tpi, L.P, L.L, L.t};
+    const int64_t G = (int64_t)L.n_tiles * L.P;
+    const int sh = L.t + L.L;
+    const int bits = ceil_log2(std::max<int64_t>(G, 2)) + sh;
+
+    DevBuf kb[2], vb[2], err;
+    kb[0].alloc(sizeof(uint64_t) * std::max<int64_t>(mt, 1), s);
+    kb[1].alloc(sizeof(uint64_t) * std::max<int64_t>(mt, 1), s);
+    if (payload) {
+        vb[0].alloc(sizeof(uint32_t) * std::max<int64_t>(mt, 1), s);
+        vb[1].alloc(sizeof(uint32_t) * std::max<int64_t>(mt, 1), s);
+    }
+    err.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    if (mt > 0) {
+        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(mt)), dim3(256), 0, s, d.d_src, d.d_dst,
+                           d.m, sym ? 1 : 0, reversed ? 1 : 0, g, kb[0].as<uint64_t>(),
+                           payload ? vb[0].as<uint32_t>() : nullptr, err.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    int32_t herr = 0;
+    NXG_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    if (herr) fail(NXG_EINVAL, "edge id outside [0, n)");
+
+    int cur = radix_sort(kb, vb, mt, bits, s);
+    int64_t m = mt;
+    if (dedup_req && mt > 0) {
+        m = dedup(kb, vb, cur, mt, s);
+        cur ^= 1;
+    }
+    L.m = m;
+    const uint64_t* keys = kb[cur].as<uint64_t>();
+    const uint32_t* vals = payload ? vb[cur].as<uint32_t>() : nullptr;
+
+    // out-degree of the stored graph
+    L.outdeg.alloc(sizeof(int32_t) * L.n, s);
+    NXG_HIP(hipMemsetAsync(L.outdeg.p, 0, sizeof(int32_t) * L.n, s));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_outdeg, dim3(grid_for(m)), dim3(256), 0, s, keys, m, g,
+                           L.outdeg.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    // groups
+    L.group_edge.alloc(sizeof(int64_t) * (G + 1), s);
+    L.group_word.alloc(sizeof(int64_t) * (G + 1), s);
+    hipLaunchKernelGGL(k_group_bounds, dim3(grid_for(G + 1)), dim3(256), 0, s, keys, m, G, sh,
+                       L.group_edge.as<int64_t>());
+    NXG_CHECK_LAUNCH();
+    DevBuf twords, tedges;
+    twords.alloc(sizeof(int64_t) * L.n_tiles, s);
+    tedges.alloc(sizeof(int64_t) * L.n_tiles, s);
+    hipLaunchKernelGGL(k_tile_words, dim3(L.n_tiles), dim3(1024), 0, s,
+                       L.group_edge.as<int64_t>(), L.P, L.group_word.as<int64_t>(),
+                       twords.as<int64_t>(), tedges.as<int64_t>());
+    NXG_CHECK_LAUNCH();
+    std::vector<int64_t> hw(L.n_tiles), he(L.n_tiles);
+    NXG_HIP(hipMemcpyAsync(hw.data(), twords.p, sizeof(int64_t) * L.n_tiles, hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipMemcpyAsync(he.data(), tedges.p, sizeof(int64_t) * L.n_tiles, hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    L.h_tile_chunk.assign(L.n_tiles + 1, 0);
+    L.h_tile_edges = he;
+    L.max_tile_edges = 0;
+    for (int tau = 0; tau < L.n_tiles; ++tau) {
+        L.h_tile_chunk[tau + 1] = L.h_tile_chunk[tau] + (hw[tau] + L.C - 1) / L.C;
+        L.max_tile_edges = std::max(L.max_tile_edges, he[tau]);
+    }
+    L.n_chunks = L.h_tile_chunk[L.n_tiles];
+    L.n_words = L.n_chunks * L.C;
+    L.tile_chunk.alloc(sizeof(int64_t) * (L.n_tiles + 1), s);
+    NXG_HIP(hipMemcpyAsync(L.tile_chunk.p, L.h_tile_chunk.data(), sizeof(int64_t) * (L.n_tiles + 1),
+                           hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_group_word_abs, dim3(grid_for(G + 1)), dim3(256), 0, s,
+                       L.group_word.as<int64_t>(), L.tile_chunk.as<int64_t>(), G, L.P, L.C,
+                       L.n_words);
+    NXG_CHECK_LAUNCH();
+    // words
+    L.words.alloc(sizeof(uint32_t) * std::max<int64_t>(L.n_words, 1), s);
+    if (L.n_words > 0) {
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(L.n_words)), dim3(256), 0, s,
+                           L.words.as<uint32_t>(), L.n_words, kPad);
+        NXG_CHECK_LAUNCH();
+    }
+    if (want_perm) {
+        L.perm.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_words, 1), s);
+        hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(L.n_words)), dim3(256), 0, s,
+                           L.perm.as<int32_t>(), L.n_words, (int32_t)-1);
+        NXG_CHECK_LAUNCH();
+        L.has_perm = true;
+    }
+    if (want_w) {
+        L.weight.alloc(sizeof(float) * std::max<int64_t>(L.n_words, 1), s);
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(L.n_words)), dim3(256), 0, s,
+                           L.weight.as<float>(), L.n_words, 0.0f);
+        NXG_CHECK_LAUNCH();
+        L.has_weight = true;
+    }
+    if (m > 0) {
+        hipLaunchKernelGGL(k_scatter_words, dim3(grid_for(m)), dim3(256), 0, s, keys, vals, m, sh,
+                           L.P, L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(),
+                           L.words.as<uint32_t>(), want_perm ? L.perm.as<int32_t>() : nullptr,
+                           d.d_weight, want_w ? L.weight.as<float>() : nullptr);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_markers, dim3(grid_for(G)), dim3(256), 0, s,
+                           L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(), G, L.P,
+                           L.words.as<uint32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    L.chunk_row.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
+    L.chunk_row_last.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
+    if (L.n_chunks > 0) {
+        hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(L.n_chunks)), dim3(256), 0, s,
+                           L.tile_chunk.as<int64_t>(), twords.as<int64_t>(), L.n_tiles,
+                           L.group_word.as<int64_t>(), L.P,
+                           L.C, L.n_chunks, L.chunk_row.as<int32_t>(),
+                           L.chunk_row_last.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipStreamSynchronize(s));
+}
+
+void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
+                   int32_t* d_perm, hipStream_t s) {
+    KeyGeom g{L.n, L.I, L.T, L.tpi, L.P, L.L, L.t};
+    if (d_perm && !L.has_perm) fail(NXG_EINVAL, "export of perm needs NXG_BUILD_KEEP_PERM");
+    if (d_offsets) {
+        const int64_t PP = (int64_t)L.P * L.P;
+        NXG_HIP(hipMemsetAsync(d_offsets, 0, sizeof(int64_t) * (PP + 1), s));
+        hipLaunchKernelGGL(k_logical_counts, dim3(grid_for((int64_t)L.n_tiles * L.P)), dim3(256), 0,
+                           s, L.group_edge.as<int64_t>(), g, d_offsets);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scan_i64_inplace_excl, dim3(1), dim3(1024), 0, s, d_offsets, PP);
+        NXG_CHECK_LAUNCH();
+    }
+    if ((d_src || d_dst || d_perm) && L.n_chunks > 0) {
+        hipLaunchKernelGGL(k_decode, dim3(grid_for(L.n_chunks, 64)), dim3(64), 0, s,
+                           L.words.as<uint32_t>(), L.tile_chunk.as<int64_t>(), L.n_tiles,
+                           L.chunk_row.as<int32_t>(), L.group_edge.as<int64_t>(),
+                           L.group_word.as<int64_t>(), g, L.C, L.n_chunks,
+                           L.has_perm ? L.perm.as<int32_t>() : nullptr, d_src, d_dst, d_perm);
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace nxg

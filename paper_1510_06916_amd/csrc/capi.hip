@@ -1,0 +1,173 @@
+// The C ABI (include/nxgraph.h): argument checks, the allocator hook, error
+// text, and handle lifetime. Every entry point converts failures into a status.
+#include <cstring>
+#include <new>
+
+#include "nxg_internal.h"
+
+namespace nxg {
+namespace {
+thread_local std::string g_last_error;
+nxg_alloc_fn g_alloc = nullptr;
+nxg_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+}  // namespace
+
+void fail(nxg_status s, const std::string& msg) { throw Error{s, msg}; }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    void* p = nullptr;
+    if (g_alloc) {
+        p = g_alloc(bytes, (void*)s, g_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (!p) fail(NXG_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+}
+
+void dev_free(void* p, size_t bytes, hipStream_t s) {
+    if (!p) return;
+    if (g_free)
+        g_free(p, bytes, (void*)s, g_ctx);
+    else
+        (void)hipFree(p);
+}
+
+template <class F>
+nxg_status guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return NXG_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return NXG_EDEVICE;
+    }
+}
+
+}  // namespace nxg
+
+nxg_dsss::~nxg_dsss() {
+    for (nxg::Plan* p : plans) delete p;
+}
+
+using namespace nxg;
+
+extern "C" {
+
+nxg_status nxg_set_allocator(nxg_alloc_fn alloc_fn, nxg_free_fn free_fn, void* ctx) {
+    return guarded([&]() {
+        if ((alloc_fn == nullptr) != (free_fn == nullptr))
+            fail(NXG_EINVAL, "alloc_fn and free_fn must both be set or both be NULL");
+        g_alloc = alloc_fn;
+        g_free = free_fn;
+        g_ctx = ctx;
+        return NXG_OK;
+    });
+}
+
+const char* nxg_last_error(void) { return g_last_error.c_str(); }
+
+int nxg_abi_version(void) { return NXG_ABI_VERSION; }
+
+nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** out) {
+    return guarded([&]() {
+        if (!out) fail(NXG_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!desc) fail(NXG_EINVAL, "desc is NULL");
+        const nxg_build_desc& d = *desc;
+        if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
+        if (d.m < 0) fail(NXG_EINVAL, "m must be >= 0");
+        const bool sym = (d.flags & NXG_BUILD_SYMMETRIZE) != 0;
+        if (d.m >= ((int64_t)1 << 31) || (sym && d.m >= ((int64_t)1 << 30)))
+            fail(NXG_EINVAL, "too many edges");
+        if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
+        if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
+                                  NXG_BUILD_DEDUP))
+            fail(NXG_EINVAL, "unknown build flag");
+        if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
+            fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
+        if (d.interval < 0 || d.interval > d.n) fail(NXG_EINVAL, "interval outside [0, n]");
+        hipStream_t s = (hipStream_t)stream;
+        nxg_dsss* g = new nxg_dsss();
+        try {
+            NXG_HIP(hipGetDevice(&g->device));
+            g->value_bytes = d.value_bytes ? d.value_bytes : 4;
+            g->flags = d.flags;
+            build_layout(d, false, s, g->fwd);
+            if (d.flags & NXG_BUILD_TRANSPOSE) {
+                build_layout(d, true, s, g->rev);
+                g->has_rev = true;
+            }
+        } catch (...) {
+            delete g;
+            throw;
+        }
+        *out = g;
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_dsss_destroy(nxg_dsss* g) {
+    return guarded([&]() {
+        delete g;
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
+    return guarded([&]() {
+        if (!g || !info) fail(NXG_EINVAL, "NULL argument");
+        const Layout& L = g->fwd;
+        memset(info, 0, sizeof(*info));
+        info->n = L.n;
+        info->m = L.m;
+        info->interval = L.I;
+        info->P = L.P;
+        info->tile = L.T;
+        info->n_tiles = L.n_tiles;
+        info->chunk = L.C;
+        info->n_chunks = L.n_chunks;
+        info->n_words = L.n_words;
+        info->max_tile_edges = L.max_tile_edges;
+        int64_t bytes = 0;
+        for (const Layout* x : {&g->fwd, &g->rev}) {
+            for (const DevBuf* b : {&x->words, &x->chunk_row, &x->chunk_row_last, &x->tile_chunk,
+                                    &x->group_edge, &x->group_word, &x->perm, &x->weight, &x->outdeg})
+                bytes += (int64_t)b->bytes;
+        }
+        info->device_bytes = bytes;
+        info->has_perm = L.has_perm;
+        info->has_weights = L.has_weight;
+        info->has_transpose = g->has_rev;
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets, int32_t* d_src,
+                           int32_t* d_dst, int32_t* d_perm, void* stream) {
+    return guarded([&]() {
+        if (!g) fail(NXG_EINVAL, "handle is NULL");
+        if (transposed && !g->has_rev) fail(NXG_EINVAL, "handle has no transposed graph");
+        export_layout(transposed ? g->rev : g->fwd, d_offsets, d_src, d_dst, d_perm,
+                      (hipStream_t)stream);
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats) {
+    return guarded([&]() {
+        if (!g || !desc) fail(NXG_EINVAL, "NULL argument");
+        return run_program(g, *desc, (hipStream_t)stream, stats);
+    });
+}
+
+}  // extern "C"

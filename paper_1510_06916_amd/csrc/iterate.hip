@@ -1,0 +1,920 @@
+// One DSSS iteration on the GPU (Alg. 1 with the single-phase update of Alg. 5
+// and, for destination tiles split over several workgroups, the two-phase
+// update of Alg. 6).
+//
+// A workgroup owns one piece of one destination tile: its accumulators live in
+// LDS, and its wavefronts stream the tile's edge words chunk by chunk. Inside a
+// chunk every lane loads four consecutive words (one 16-byte load), follows the
+// source-interval markers, gathers the source values, merges runs of equal
+// destination and adds (PageRank) or min-reduces (BFS, WCC) into LDS -- the
+// write-conflict-free destination ownership of Sec. III-D. A tile handled by one
+// workgroup applies the vertex update straight from LDS (single phase). A tile
+// split into k pieces writes k partial arrays (the hub of Sec. III-B2); the last
+// piece to finish sums them in piece order and applies the update (two phase).
+// The last tile to finish reduces the per-iteration scalars (dangling mass,
+// residual, activity) in tile order, so they are independent of scheduling.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "nxg_internal.h"
+
+namespace nxg {
+namespace {
+
+constexpr uint32_t kMarker = 0x80000000u;
+constexpr int32_t kInf = INT32_MAX;
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
+struct Geo {
+    const uint32_t* words;
+    const int32_t* chunk_row;
+    const int32_t* chunk_row_last;
+    const Item* items;
+    const int32_t* deg;
+    int32_t n, I, P, L, T, t, tpi, n_tiles, C;
+    // two-phase partials
+    void* partial;
+    int32_t* tile_ctr;
+    int32_t* all_ctr;
+    double* tile_s;      // [n_tiles * 2]
+    int32_t* tile_flag;  // [n_tiles]
+    // compacted active chunk lists (BFS/WCC), nullable
+    const int64_t* clist;
+    const int32_t* ccount;
+};
+
+// Per-iteration control block in device memory.
+struct Ctl {
+    double* stats;        // [4 * (max_iters + 1)]: [k*4+0] scalar entering iteration k,
+                          // [k*4+1] residual of iteration k, [k*4+2] norm, [k*4+3] changed
+    int32_t* done;        // set once the tolerance is met (PageRank) / nothing changed
+    int32_t k;            // iteration index
+    double tol;
+};
+
+// ---------------------------------------------------------------------------
+// Programs
+// ---------------------------------------------------------------------------
+
+// PageRank with W = 1/outdeg. The gathered array holds x_u / outdeg_u (x_u for
+// dangling u, which is never gathered), so no separate x vector is kept.
+template <typename V>
+struct ProgPR {
+    using acc_t = V;
+    static constexpr bool kSum = true, kWeights = false, kActivity = false;
+    const V* cur;
+    V* nxt;
+    const V* tele;   // nullable: uniform
+    V* xout;         // nullable: write x on this iteration
+    double d;
+    __device__ acc_t identity() const { return (acc_t)0; }
+    __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
+    __device__ bool row_active(uint32_t) const { return true; }
+    // s0: dangling mass of x^{k+1}; s1: |x^{k+1} - x^k|
+    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
+                          double& s1, int&) const {
+        double xo = dg ? (double)cur[v] * dg : (double)cur[v];
+        double tv = tele ? (double)tele[v] : 1.0 / n;
+        double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
+        V xr = (V)xn;
+        s1 += fabs((double)xr - xo);
+        if (dg == 0) s0 += (double)xr;
+        nxt[v] = dg ? (V)((double)xr / dg) : xr;
+        if (xout) xout[v] = xr;
+    }
+    __device__ void pass(int64_t v, int32_t dg) const {
+        nxt[v] = cur[v];
+        if (xout) xout[v] = dg ? (V)((double)cur[v] * dg) : cur[v];
+    }
+};
+
+// PageRank with the stored edge weights: gathers x_u and multiplies by w_e.
+template <typename V>
+struct ProgPRW {
+    using acc_t = V;
+    static constexpr bool kSum = true, kWeights = true, kActivity = false;
+    const V* cur;
+    V* nxt;
+    const V* tele;
+    V* xout;
+    const float* w;  // [n_words] weights in stream order
+    double d;
+    __device__ acc_t identity() const { return (acc_t)0; }
+    __device__ acc_t gather(uint32_t src, float we) const { return (acc_t)we * cur[src]; }
+    __device__ bool row_active(uint32_t) const { return true; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
+                          double& s1, int&) const {
+        double xo = (double)cur[v];
+        double tv = tele ? (double)tele[v] : 1.0 / n;
+        double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
+        V xr = (V)xn;
+        s1 += fabs((double)xr - xo);
+        if (dg == 0) s0 += (double)xr;
+        nxt[v] = xr;
+        if (xout) xout[v] = xr;
+    }
+    __device__ void pass(int64_t v, int32_t) const {
+        nxt[v] = cur[v];
+        if (xout) xout[v] = cur[v];
+    }
+};
+
+// BFS (Alg. 3): a reached source offers level + 1; min-reduce.
+struct ProgBFS {
+    using acc_t = int32_t;
+    static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    const int32_t* cur;
+    int32_t* nxt;
+    const uint8_t* act;  // [P] source intervals updated in the previous round
+    int32_t P;
+    __device__ acc_t identity() const { return kInf; }
+    __device__ acc_t gather(uint32_t src, float) const {
+        int32_t l = cur[src];
+        return l == kInf ? kInf : l + 1;
+    }
+    __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double&, double&,
+                          int& flag) const {
+        int32_t o = cur[v];
+        int32_t nv = acc < o ? acc : o;
+        nxt[v] = nv;
+        if (nv != o) flag = 1;
+    }
+    __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
+// WCC by min-label propagation on the symmetrised graph.
+struct ProgWCC {
+    using acc_t = int32_t;
+    static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    const int32_t* cur;
+    int32_t* nxt;
+    const uint8_t* act;
+    int32_t P;
+    __device__ acc_t identity() const { return kInf; }
+    __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
+    __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double&, double&,
+                          int& flag) const {
+        int32_t o = cur[v];
+        int32_t nv = acc < o ? acc : o;
+        nxt[v] = nv;
+        if (nv != o) flag = 1;
+    }
+    __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
+__device__ inline void lds_combine(float* p, float v, bool) { atomicAdd(p, v); }
+__device__ inline void lds_combine(double* p, double v, bool) { atomicAdd(p, v); }
+__device__ inline void lds_combine(int32_t* p, int32_t v, bool sum) {
+    if (sum)
+        atomicAdd(p, v);
+    else
+        atomicMin(p, v);
+}
+
+template <bool kSum, typename A>
+__device__ inline A combine(A a, A b) {
+    if constexpr (kSum)
+        return a + b;
+    else
+        return b < a ? b : a;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// The edge kernel
+// ---------------------------------------------------------------------------
+template <class Prog, int WG>
+__global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
+    using acc_t = typename Prog::acc_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    acc_t* acc = reinterpret_cast<acc_t*>(smem);
+    __shared__ double red[2][WG / 64];
+    __shared__ int sflag;
+    __shared__ int slast;
+
+    const Item it = g.items[blockIdx.x];
+    const int tile = it.tile;
+    const int j = tile / g.tpi, q = tile - j * g.tpi;
+    const int64_t base = (int64_t)j * g.I + (int64_t)q * g.T;
+    int64_t len = min((int64_t)g.T, (int64_t)g.I - (int64_t)q * g.T);
+    len = min(len, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+
+    // Once converged (tolerance met) the remaining iterations only carry the
+    // vector over so the final buffer is the one the caller expects.
+    if (*ctl.done) {
+        if (it.piece == 0)
+            for (int64_t x = threadIdx.x; x < len; x += WG) prog.pass(base + x, g.deg[base + x]);
+        return;
+    }
+
+    for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
+    if (threadIdx.x == 0) sflag = 0;
+    __syncthreads();
+
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t lmask = (1u << g.L) - 1u;
+    const uint32_t tmask = (1u << g.t) - 1u;
+    const int steps = g.C >> 8;
+
+    // chunk source: explicit range, or this piece's share of the tile's compacted list
+    int64_t c_lo = it.c0, c_hi = it.c1;
+    const int64_t* list = nullptr;
+    if (g.clist) {
+        const int64_t lbeg = g.items[blockIdx.x].c0;  // tile's first chunk = list origin
+        const int64_t cnt = g.ccount[tile];
+        list = g.clist + lbeg;
+        c_lo = cnt * it.piece / it.npieces;
+        c_hi = cnt * (it.piece + 1) / it.npieces;
+    }
+
+    for (int64_t ci = c_lo + wave; ci < c_hi; ci += WG / 64) {
+        const int64_t c = list ? list[ci] : ci;
+        uint32_t row = (uint32_t)g.chunk_row[c];
+        const uint4* wp = reinterpret_cast<const uint4*>(g.words + c * (int64_t)g.C);
+        const float4* wwp = nullptr;
+        if constexpr (Prog::kWeights) wwp = reinterpret_cast<const float4*>(prog.w + c * (int64_t)g.C);
+        for (int s = 0; s < steps; ++s) {
+            const uint4 w4 = wp[s * 64 + lane];
+            float wv[4] = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (Prog::kWeights) {
+                const float4 f = wwp[s * 64 + lane];
+                wv[0] = f.x;
+                wv[1] = f.y;
+                wv[2] = f.z;
+                wv[3] = f.w;
+            }
+            const uint32_t wd[4] = {w4.x, w4.y, w4.z, w4.w};
+            // source interval in effect at this lane's first word
+            uint32_t r = row;
+            const uint32_t has = (wd[0] | wd[1] | wd[2] | wd[3]) >> 31;
+            const uint64_t mm = __ballot(has);
+            if (mm) {
+                uint32_t last = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (wd[k] & kMarker) last = wd[k] & ~kMarker;
+                const uint64_t prev = mm & lt;
+                const int from = prev ? 63 - __clzll(prev) : lane;
+                const uint32_t got = __shfl(last, from);
+                r = prev ? got : row;
+                row = __shfl(last, 63 - __clzll(mm));
+            }
+            uint32_t rb = r * (uint32_t)g.I;
+            bool on = prog.row_active(r);
+            uint32_t pd = 0xFFFFFFFFu;
+            acc_t pv = prog.identity();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t w = wd[k];
+                if (w & kMarker) {
+                    r = w & ~kMarker;
+                    rb = r * (uint32_t)g.I;
+                    on = prog.row_active(r);
+                    continue;
+                }
+                if (!on) continue;
+                const uint32_t dst = (w >> g.L) & tmask;
+                const acc_t v = prog.gather(rb + (w & lmask), wv[k]);
+                if (dst == pd) {
+                    pv = combine<Prog::kSum>(pv, v);
+                } else {
+                    if (pd != 0xFFFFFFFFu && (Prog::kSum || pv != prog.identity()))
+                        lds_combine(&acc[pd], pv, Prog::kSum);
+                    pd = dst;
+                    pv = v;
+                }
+            }
+            if (pd != 0xFFFFFFFFu && (Prog::kSum || pv != prog.identity()))
+                lds_combine(&acc[pd], pv, Prog::kSum);
+        }
+    }
+    __syncthreads();
+
+    // ---- two-phase: publish the partial, the last piece combines ---------
+    if (it.npieces > 1) {
+        acc_t* part = reinterpret_cast<acc_t*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T;
+        for (int64_t x = threadIdx.x; x < len; x += WG) part[x] = acc[x];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int old = __hip_atomic_fetch_add(&g.tile_ctr[tile], 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            slast = (old == it.npieces - 1);
+        }
+        __syncthreads();
+        if (!slast) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
+        for (int64_t x = threadIdx.x; x < len; x += WG) {
+            acc_t s = prog.identity();
+            for (int p = 0; p < it.npieces; ++p)
+                s = combine<Prog::kSum>(s, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
+            acc[x] = s;
+        }
+        if (threadIdx.x == 0) g.tile_ctr[tile] = 0;
+        __syncthreads();
+    }
+
+    // ---- apply ------------------------------------------------------------
+    const double scal = ctl.stats[ctl.k * 4 + 0];
+    double s0 = 0.0, s1 = 0.0;
+    int flag = 0;
+    for (int64_t x = threadIdx.x; x < len; x += WG)
+        prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, s0, s1, flag);
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+        red[0][wave] = s0;
+        red[1][wave] = s1;
+    }
+    if (flag) sflag = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < WG / 64; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+        }
+        g.tile_s[2 * tile + 0] = a;
+        g.tile_s[2 * tile + 1] = b;
+        g.tile_flag[tile] = sflag;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int old = __hip_atomic_fetch_add(g.all_ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        slast = (old == g.n_tiles - 1);
+    }
+    __syncthreads();
+    if (!slast) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // ---- last tile: per-iteration scalars in tile order ---------------------
+    double a = 0.0, b = 0.0;
+    int f = 0;
+    for (int x = threadIdx.x; x < g.n_tiles; x += WG) {
+        a += __builtin_nontemporal_load(&g.tile_s[2 * x + 0]);
+        b += __builtin_nontemporal_load(&g.tile_s[2 * x + 1]);
+        f |= __builtin_nontemporal_load(&g.tile_flag[x]);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+    }
+    if (f) sflag = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int w = 0; w < WG / 64; ++w) {
+            ta += red[0][w];
+            tb += red[1][w];
+        }
+        ctl.stats[(ctl.k + 1) * 4 + 0] = ta;
+        ctl.stats[ctl.k * 4 + 1] = tb;
+        ctl.stats[ctl.k * 4 + 3] = sflag ? 1.0 : 0.0;
+        if (Prog::kSum) {
+            if (ctl.tol > 0.0 && tb <= ctl.tol) *ctl.done = 1;
+        }
+        *g.all_ctr = 0;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Initialisation, activity and end-of-run kernels
+// ---------------------------------------------------------------------------
+
+// x^0 = t (or the caller's x^0), gathered array = x^0 / outdeg; per-block
+// partial dangling mass.
+template <typename V>
+__global__ __launch_bounds__(256) void k_init_pr(int32_t n, const int32_t* __restrict__ deg,
+                                                 const V* __restrict__ tele,
+                                                 const V* __restrict__ x0, int divide,
+                                                 V* __restrict__ cur, double* __restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        V x = x0 ? x0[v] : (tele ? tele[v] : (V)(1.0 / n));
+        int32_t dg = deg[v];
+        if (dg == 0) s += (double)x;
+        cur[v] = (divide && dg) ? (V)((double)x / dg) : x;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b];
+        *out = s;
+    }
+}
+
+__global__ void k_init_bfs(int32_t n, int32_t root, int32_t* __restrict__ lev,
+                           int32_t* __restrict__ tile_flag, int n_tiles, int tpi, int I) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        lev[v] = v == root ? 0 : kInf;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_tiles;
+         x += (int64_t)gridDim.x * blockDim.x)
+        tile_flag[x] = (x / tpi) == (root / I) ? 1 : 0;
+}
+
+__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, int32_t* __restrict__ tile_flag,
+                           int n_tiles) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        lab[v] = (int32_t)v;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_tiles;
+         x += (int64_t)gridDim.x * blockDim.x)
+        tile_flag[x] = 1;
+}
+
+// Interval activity (Sec. II-B): interval i is active in this round iff one of
+// its vertices changed in the previous round; apref = prefix count of actives.
+__global__ __launch_bounds__(1024) void k_activity(const int32_t* __restrict__ tile_flag, int P,
+                                                   int tpi, uint8_t* __restrict__ act,
+                                                   int32_t* __restrict__ apref) {
+    __shared__ int32_t part[1024];
+    const int per = (P + 1023) / 1024;
+    const int a = threadIdx.x * per, b = min(P, a + per);
+    int32_t s = 0;
+    for (int i = a; i < b; ++i) {
+        int f = 0;
+        for (int q = 0; q < tpi; ++q) f |= tile_flag[(int64_t)i * tpi + q];
+        act[i] = (uint8_t)(f != 0);
+        s += f != 0;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = a; i < b; ++i) {
+        apref[i] = run;
+        run += act[i];
+    }
+    if (threadIdx.x == 1023) apref[P] = part[1023];
+}
+
+// Frontier compaction: per tile, the chunks that touch at least one active
+// source interval, in stream order, stored from the tile's first chunk on.
+__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tchunk,
+                                                 const int32_t* __restrict__ crow,
+                                                 const int32_t* __restrict__ crow_last,
+                                                 const int32_t* __restrict__ apref,
+                                                 int64_t* __restrict__ clist,
+                                                 int32_t* __restrict__ ccount) {
+    __shared__ int32_t wsum[4];
+    __shared__ int32_t run;
+    const int tile = blockIdx.x;
+    const int64_t c0 = tchunk[tile], c1 = tchunk[tile + 1];
+    if (threadIdx.x == 0) run = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    for (int64_t b = c0; b < c1; b += 256) {
+        int64_t c = b + threadIdx.x;
+        bool keep = false;
+        if (c < c1) keep = apref[crow_last[c] + 1] - apref[crow[c]] > 0;
+        uint64_t bal = __ballot(keep);
+        if (lane_id() == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int32_t before = run;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (keep) clist[c0 + before + __popcll(bal & ((1ull << lane_id()) - 1ull))] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ccount[tile] = run;
+}
+
+// BFS output (Alg. 4) plus the reached-edge count used for TEPS.
+__global__ __launch_bounds__(256) void k_bfs_final(int32_t n, const int32_t* __restrict__ lev,
+                                                   const int32_t* __restrict__ deg,
+                                                   int32_t* __restrict__ maxlev,
+                                                   unsigned long long* __restrict__ reached) {
+    int32_t mx = 0;
+    unsigned long long r = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        int32_t l = lev[v];
+        if (l != kInf) {
+            mx = l > mx ? l : mx;
+            r += (unsigned long long)deg[v];
+        }
+    }
+    atomicMax(maxlev, mx);
+    atomicAdd(reached, r);
+}
+
+template <typename V>
+__global__ void k_copy(const V* __restrict__ a, V* __restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+inline int grid_for(int64_t work, int threads = 256, int cap = 8192) {
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+int num_cus(int device) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1)
+        cu = 256;
+    return cu;
+}
+
+// Splits every tile into pieces of at most piece_chunks chunks; heavy tiles
+// first. With whole_tiles every piece carries the tile's full chunk range (the
+// pieces then split the tile's compacted active list at run time).
+Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s) {
+    for (Plan* p : g->plans)
+        if (p->layout == &L && p->piece_chunks == piece_chunks && p->whole_tiles == whole_tiles)
+            return p;
+    Plan* p = new Plan();
+    p->layout = &L;
+    p->piece_chunks = piece_chunks;
+    p->whole_tiles = whole_tiles;
+    std::vector<Item> items;
+    int slots = 0;
+    for (int tau = 0; tau < L.n_tiles; ++tau) {
+        int64_t c0 = L.h_tile_chunk[tau], c1 = L.h_tile_chunk[tau + 1];
+        int64_t nc = c1 - c0;
+        int np = 1;
+        if (piece_chunks > 0 && nc > piece_chunks) np = (int)((nc + piece_chunks - 1) / piece_chunks);
+        int slot = np > 1 ? slots : -1;
+        if (np > 1) slots += np;
+        for (int pc = 0; pc < np; ++pc) {
+            Item it;
+            it.tile = tau;
+            it.piece = pc;
+            it.npieces = np;
+            it.slot = slot;
+            if (whole_tiles) {
+                it.c0 = c0;
+                it.c1 = c1;
+            } else {
+                it.c0 = c0 + nc * pc / np;
+                it.c1 = c0 + nc * (pc + 1) / np;
+            }
+            items.push_back(it);
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [np_whole = whole_tiles](const Item& a, const Item& b) {
+        int64_t wa = np_whole ? (a.c1 - a.c0) / a.npieces : a.c1 - a.c0;
+        int64_t wb = np_whole ? (b.c1 - b.c0) / b.npieces : b.c1 - b.c0;
+        return wa > wb;
+    });
+    p->h_items = items;
+    p->n_slots = slots;
+    p->items.alloc(sizeof(Item) * std::max<size_t>(items.size(), 1), s);
+    NXG_HIP(hipMemcpyAsync(p->items.p, items.data(), sizeof(Item) * items.size(),
+                           hipMemcpyHostToDevice, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    g->plans.push_back(p);
+    return p;
+}
+
+struct Workspace {
+    DevBuf buf[2], partial, tile_ctr, all_ctr, tile_s, tile_flag, stats, done, act, apref, clist,
+        ccount, part, bfsout;
+};
+
+template <class Prog, int WG>
+void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, int n_items, size_t lds,
+                 hipStream_t s) {
+    static size_t attr_lds = 0;
+    if (lds > attr_lds) {
+        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_lds = lds;
+    }
+    hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
+    NXG_CHECK_LAUNCH();
+}
+
+Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
+    Geo g;
+    g.words = L.words.as<uint32_t>();
+    g.chunk_row = L.chunk_row.as<int32_t>();
+    g.chunk_row_last = L.chunk_row_last.as<int32_t>();
+    g.items = p.items.as<Item>();
+    g.deg = L.outdeg.as<int32_t>();
+    g.n = L.n;
+    g.I = L.I;
+    g.P = L.P;
+    g.L = L.L;
+    g.T = L.T;
+    g.t = L.t;
+    g.tpi = L.tpi;
+    g.n_tiles = L.n_tiles;
+    g.C = L.C;
+    g.partial = w.partial.p;
+    g.tile_ctr = w.tile_ctr.as<int32_t>();
+    g.all_ctr = w.all_ctr.as<int32_t>();
+    g.tile_s = w.tile_s.as<double>();
+    g.tile_flag = w.tile_flag.as<int32_t>();
+    g.clist = nullptr;
+    g.ccount = nullptr;
+    return g;
+}
+
+void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
+                  hipStream_t s) {
+    w.partial.alloc((size_t)std::max(p.n_slots, 1) * L.T * vb, s);
+    w.tile_ctr.alloc(sizeof(int32_t) * L.n_tiles, s);
+    NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
+    w.all_ctr.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(w.all_ctr.p, 0, sizeof(int32_t), s));
+    w.tile_s.alloc(sizeof(double) * 2 * L.n_tiles, s);
+    w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+    w.stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
+    NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * 4 * (size_t)(max_iters + 2), s));
+    w.done.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
+}
+
+template <typename V>
+nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const Layout& L = g->fwd;
+    const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
+    if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
+    const size_t vb = sizeof(V);
+    if ((size_t)L.T * vb > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "destination tile does not fit in LDS for this dtype; rebuild with value_bytes");
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    Plan* p = get_plan(g, L, piece, false, s);
+    Workspace w;
+    const int max_iters = d.max_iters;
+    alloc_common(w, L, *p, vb, max_iters, s);
+    w.buf[0].alloc(vb * L.n, s);
+    w.buf[1].alloc(vb * L.n, s);
+    const int nb = grid_for(L.n, 256, 1024);
+    w.part.alloc(sizeof(double) * nb, s);
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? (const V*)d.d_values : nullptr;
+    hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
+                       (const V*)d.d_teleport, x0, weighted ? 0 : 1, w.buf[0].as<V>(),
+                       w.part.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
+                       w.stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(L, *p, w);
+    const size_t lds = (size_t)L.T * vb;
+    const int n_items = (int)p->h_items.size();
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    int k = 0;
+    int done_h = 0;
+    const int block = d.tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
+    while (k < max_iters) {
+        int kend = std::min(max_iters, k + block);
+        for (; k < kend; ++k) {
+            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
+            const V* cur = w.buf[k & 1].as<V>();
+            V* nxt = w.buf[(k + 1) & 1].as<V>();
+            V* xout = (k == max_iters - 1) ? (V*)d.d_values : nullptr;
+            if (weighted) {
+                ProgPRW<V> pr{cur, nxt, (const V*)d.d_teleport, xout, L.weight.as<float>(), d.damping};
+                launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+            } else {
+                ProgPR<V> pr{cur, nxt, (const V*)d.d_teleport, xout, d.damping};
+                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+            }
+        }
+        if (d.tol > 0 && k < max_iters) {
+            NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (done_h) break;
+        }
+    }
+    if (k < max_iters || max_iters == 0) {
+        // converged early (or no iteration asked): the newest vector is buf[k & 1]
+        const V* cur = w.buf[k & 1].as<V>();
+        if (weighted) {
+            hipLaunchKernelGGL(k_copy<V>, dim3(grid_for(L.n)), dim3(256), 0, s, cur, (V*)d.d_values,
+                               (int64_t)L.n);
+        } else {
+            // x = gathered value * outdeg; reuse the carry-over path of the kernel
+            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
+            ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, (V*)d.d_values, d.damping};
+            NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
+            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+        }
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipEventRecord(e1, s));
+    nxg_status rc = NXG_OK;
+    if (st || d.tol > 0) {
+        std::vector<double> hs(4 * (size_t)(max_iters + 2));
+        NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * hs.size(),
+                               hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        int iters = k;
+        // with early exit the kernels after convergence only carried data over
+        int conv_at = -1;
+        for (int i = 0; i < iters; ++i)
+            if (d.tol > 0 && hs[4 * i + 1] <= d.tol) {
+                conv_at = i;
+                break;
+            }
+        if (conv_at >= 0) iters = conv_at + 1;
+        float ms = 0.f;
+        NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (st) {
+            memset(st, 0, sizeof(*st));
+            st->iterations = iters;
+            st->converged = conv_at >= 0 ? 1 : 0;
+            st->residual = iters > 0 ? hs[4 * (iters - 1) + 1] : 0.0;
+            st->device_ms = ms;
+        }
+        if (d.tol > 0 && conv_at < 0) rc = NXG_ENOTCONV;
+    }
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    if (!st && d.tol <= 0) {
+        // buffers are released through the allocator on the same stream, so
+        // stream-ordered allocators see the frees after the kernels
+    }
+    NXG_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const Layout& L = g->fwd;
+    const bool bfs = d.program == NXG_BFS;
+    if (!bfs && !(g->flags & NXG_BUILD_SYMMETRIZE))
+        fail(NXG_EINVAL, "WCC needs a build with NXG_BUILD_SYMMETRIZE");
+    if (bfs) {
+        if (!d.roots) fail(NXG_EINVAL, "BFS needs roots");
+        if (d.batch != 1) fail(NXG_EUNSUPPORTED, "BFS runs one root per call");
+        if (d.roots[0] < 0 || d.roots[0] >= L.n) fail(NXG_EINVAL, "BFS root outside [0, n)");
+    }
+    if ((size_t)L.T * 4 > (size_t)lds_budget_bytes(g->device)) fail(NXG_EINVAL, "tile does not fit in LDS");
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    Plan* p = get_plan(g, L, -piece, true, s);  // whole-tile ranges; pieces split the active list
+    Workspace w;
+    const int max_iters = d.max_iters;
+    alloc_common(w, L, *p, 4, max_iters, s);
+    w.buf[0].alloc(sizeof(int32_t) * L.n, s);
+    w.buf[1].alloc(sizeof(int32_t) * L.n, s);
+    w.act.alloc(L.P, s);
+    w.apref.alloc(sizeof(int32_t) * (L.P + 1), s);
+    w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
+    w.ccount.alloc(sizeof(int32_t) * L.n_tiles, s);
+    if (bfs)
+        hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(std::max<int64_t>(L.n, L.n_tiles))), dim3(256), 0,
+                           s, L.n, d.roots[0], w.buf[0].as<int32_t>(), w.tile_flag.as<int32_t>(),
+                           L.n_tiles, L.tpi, L.I);
+    else
+        hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.n_tiles))), dim3(256), 0,
+                           s, L.n, w.buf[0].as<int32_t>(), w.tile_flag.as<int32_t>(), L.n_tiles);
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(L, *p, w);
+    geo.clist = w.clist.as<int64_t>();
+    geo.ccount = w.ccount.as<int32_t>();
+    const size_t lds = (size_t)L.T * 4;
+    const int n_items = (int)p->h_items.size();
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    int k = 0;
+    const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
+    std::vector<double> hs(4 * (size_t)(max_iters + 2));
+    bool fixed = false;
+    int last_changed = 0;
+    while (k < max_iters && !fixed) {
+        int kend = std::min(max_iters, k + block);
+        int kb = k;
+        for (; k < kend; ++k) {
+            hipLaunchKernelGGL(k_activity, dim3(1), dim3(1024), 0, s, w.tile_flag.as<int32_t>(), L.P,
+                               L.tpi, w.act.as<uint8_t>(), w.apref.as<int32_t>());
+            NXG_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_compact, dim3(L.n_tiles), dim3(256), 0, s, L.tile_chunk.as<int64_t>(),
+                               L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
+                               w.apref.as<int32_t>(), w.clist.as<int64_t>(), w.ccount.as<int32_t>());
+            NXG_CHECK_LAUNCH();
+            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
+            const int32_t* cur = w.buf[k & 1].as<int32_t>();
+            int32_t* nxt = w.buf[(k + 1) & 1].as<int32_t>();
+            if (bfs) {
+                ProgBFS pr{cur, nxt, w.act.as<uint8_t>(), L.P};
+                launch_iter<ProgBFS, 1024>(geo, ctl, pr, n_items, lds, s);
+            } else {
+                ProgWCC pr{cur, nxt, w.act.as<uint8_t>(), L.P};
+                launch_iter<ProgWCC, 1024>(geo, ctl, pr, n_items, lds, s);
+            }
+        }
+        NXG_HIP(hipMemcpyAsync(hs.data() + 4 * kb, w.stats.as<double>() + 4 * kb,
+                               sizeof(double) * 4 * (k - kb), hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        for (int i = kb; i < k; ++i) {
+            if (hs[4 * i + 3] == 0.0) {
+                fixed = true;
+                break;
+            }
+            last_changed = i + 1;
+        }
+    }
+    // the values after round k live in buf[k & 1]; rounds past the fixed point copy
+    NXG_HIP(hipEventRecord(e1, s));
+    hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s,
+                       w.buf[k & 1].as<int32_t>(), (int32_t*)d.d_values, (int64_t)L.n);
+    NXG_CHECK_LAUNCH();
+    int32_t mx = 0;
+    unsigned long long reached = 0;
+    if (bfs) {
+        w.bfsout.alloc(16, s);
+        NXG_HIP(hipMemsetAsync(w.bfsout.p, 0, 16, s));
+        hipLaunchKernelGGL(k_bfs_final, dim3(grid_for(L.n, 256, 1024)), dim3(256), 0, s, L.n,
+                           w.buf[k & 1].as<int32_t>(), L.outdeg.as<int32_t>(), w.bfsout.as<int32_t>(),
+                           (unsigned long long*)(w.bfsout.as<char>() + 8));
+        NXG_CHECK_LAUNCH();
+        NXG_HIP(hipMemcpyAsync(&mx, w.bfsout.p, 4, hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipMemcpyAsync(&reached, w.bfsout.as<char>() + 8, 8, hipMemcpyDeviceToHost, s));
+    }
+    NXG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = std::min(k, last_changed + 1);
+        st->converged = fixed ? 1 : 0;
+        st->changed_rounds = last_changed;
+        st->max_level = mx;
+        st->reached_edges = (int64_t)reached;
+        st->device_ms = ms;
+    }
+    return fixed ? NXG_OK : NXG_ENOTCONV;
+}
+
+}  // namespace
+
+int lds_budget_bytes(int device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+        v <= 0)
+        v = 65536;
+    // headroom for the kernels' static shared variables
+    return v - 1024;
+}
+
+nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
+    if (d.batch != 1 && d.batch != 0) fail(NXG_EUNSUPPORTED, "batch > 1 is not supported by nxg_run yet");
+    if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    switch (d.program) {
+        case NXG_PAGERANK:
+        case NXG_PAGERANK_WEIGHTED:
+            if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+            if (d.dtype == NXG_F32) return run_pagerank<float>(g, d, s, st);
+            if (d.dtype == NXG_F64) return run_pagerank<double>(g, d, s, st);
+            fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
+        case NXG_BFS:
+        case NXG_WCC:
+            if (d.dtype != NXG_I32) fail(NXG_EINVAL, "BFS/WCC need dtype I32");
+            return run_minprog(g, d, s, st);
+        default:
+            fail(NXG_EINVAL, "unknown program");
+    }
+}
+
+}  // namespace nxg

@@ -1,0 +1,156 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "nxgraph.h"
+
+namespace nxg {
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every entry point catches nxg::Error and turns it into a
+// status plus a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error {
+    nxg_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(nxg_status s, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+#define NXG_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            ::nxg::fail(NXG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define NXG_CHECK_LAUNCH() NXG_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Device memory through the caller-settable allocator.
+// ---------------------------------------------------------------------------
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, size_t bytes, hipStream_t s);
+
+// RAII owner of one device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            reset();
+            p = o.p;
+            bytes = o.bytes;
+            stream = o.stream;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(size_t b, hipStream_t s) {
+        reset();
+        stream = s;
+        bytes = b ? b : 16;
+        p = dev_alloc(bytes, s);
+    }
+    void reset() {
+        if (p) dev_free(p, bytes, stream);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const {
+        return reinterpret_cast<T*>(p);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Physical DSSS layout.
+//
+// The destination range of every interval j is cut into tiles of T vertices
+// (T a power of two; tiles never straddle an interval). Tile tau = j*tpi + q
+// owns destinations [j*I + q*T, j*I + min((q+1)*T, I)). The edge stream lists
+// tiles in increasing tau; inside a tile, the edges of source interval i come
+// before those of interval i+1, and inside one (tile, i) group edges are sorted
+// by destination, then source -- the paper's sub-shard order restricted to the
+// tile. With T >= I the stream is exactly the DSSS order.
+//
+// Each edge is one 32-bit word: bits [0, L) = src - i*I, bits [L, L+t) =
+// dst - tile base, bit 31 clear (needs L + t <= 31). Each non-empty group is
+// preceded by a marker word 0x80000000 | i. A tile's words are padded with
+// 0xFFFFFFFF to a multiple of the chunk size C, so every chunk belongs to one
+// tile; chunk_row[c] is the source interval in effect at the chunk's first
+// word and chunk_row_last[c] the one in effect at its last edge.
+// ---------------------------------------------------------------------------
+struct Layout {
+    int32_t n = 0, I = 0, P = 0, L = 0;
+    int32_t T = 0, t = 0, tpi = 0, n_tiles = 0, C = 0;
+    int64_t m = 0, n_chunks = 0, n_words = 0, max_tile_edges = 0;
+    DevBuf words;          // uint32 [n_words]
+    DevBuf chunk_row;      // int32  [n_chunks]
+    DevBuf chunk_row_last; // int32  [n_chunks]
+    DevBuf tile_chunk;     // int64  [n_tiles + 1] chunk index of each tile's first chunk
+    DevBuf group_edge;     // int64  [n_tiles*P + 1] stream-order index of each group's first edge
+    DevBuf group_word;     // int64  [n_tiles*P + 1] word position of each group's marker
+    DevBuf perm;           // int32  [n_words] input index of the edge in that word, -1 otherwise
+    DevBuf weight;         // float  [n_words] weight of the edge in that word, 0 otherwise
+    DevBuf outdeg;         // int32  [n] out-degree in this (possibly reversed) graph
+    std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
+    std::vector<int64_t> h_tile_edges;  // edges per tile (host)
+    bool has_perm = false, has_weight = false;
+};
+
+// Item of work for the iteration kernels: one piece of one destination tile.
+struct Item {
+    int32_t tile;
+    int32_t piece;
+    int32_t npieces;
+    int32_t slot;   // first partial-buffer slot of the tile (multi-piece tiles), else -1
+    int64_t c0, c1; // chunk range [c0, c1)
+};
+
+struct Layout;
+struct Plan {
+    const Layout* layout = nullptr;
+    bool whole_tiles = false;
+    int32_t piece_chunks = 0;
+    std::vector<Item> h_items;
+    DevBuf items;
+    int32_t n_slots = 0;  // partial-buffer slots (one tile-sized array each)
+};
+
+}  // namespace nxg
+
+struct nxg_dsss {
+    int device = 0;
+    int32_t value_bytes = 4;
+    uint32_t flags = 0;
+    nxg::Layout fwd;
+    nxg::Layout rev;  // reversed graph (NXG_BUILD_TRANSPOSE)
+    bool has_rev = false;
+    // cached iteration plans, keyed by piece size
+    std::vector<nxg::Plan*> plans;
+    ~nxg_dsss();
+};
+
+namespace nxg {
+// builder entry (builder.hip)
+void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& out);
+void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
+                   int32_t* d_perm, hipStream_t s);
+// runtime entry (iterate.hip)
+nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
+int lds_budget_bytes(int device);
+}  // namespace nxg
