@@ -51,7 +51,8 @@ def main():
     ap.add_argument("--interval", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--order", default="dst", choices=["dst", "src"])
+    ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="also check sampled vertices vs FP64")
     args = ap.parse_args()
@@ -72,7 +73,8 @@ def main():
     log("generated R-MAT scale %d ef %d: m=%d in %.1fs" % (args.scale, args.ef, src.numel(),
                                                            time.perf_counter() - t0))
     t0 = time.perf_counter()
-    g = DSSS.build(src, dst, n, interval=args.interval, tile=args.tile, chunk=args.chunk)
+    g = DSSS.build(src, dst, n, interval=args.interval, tile=args.tile, chunk=args.chunk,
+                   order=args.order)
     torch.cuda.synchronize()
     inf = g.info()
     log("built DSSS in %.2fs: %s" % (time.perf_counter() - t0, json.dumps(inf)))
@@ -107,7 +109,8 @@ def main():
         "data": "synthetic R-MAT (a/b/c/d=0.57/0.19/0.19/0.05, Philox seed %d, dedup)" % args.seed,
         "config": {"workload": "pagerank-iteration rmat-s%d-ef%d" % (args.scale, args.ef),
                    "n": n, "m": m, "interval": inf["interval"], "P": inf["P"],
-                   "tile": inf["tile"], "chunk": inf["chunk"], "damping": 0.85},
+                   "tile": inf["tile"], "chunk": inf["chunk"], "damping": 0.85,
+                   "order": args.order},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_iter": b_iter, "kernel_ms": kern_ms},

@@ -73,6 +73,11 @@ int nxg_abi_version(void);
 #define NXG_BUILD_SYMMETRIZE 0x4u /* store E and reverse(E); implies NXG_BUILD_DEDUP */
 #define NXG_BUILD_DEDUP 0x8u      /* store each distinct (src, dst) pair once */
 
+/* Order of the edges inside one sub-shard. */
+#define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */
+#define NXG_ORDER_SRC 1 /* source, then destination: the source-sorted layout the
+                           paper compares against (Sec. IV-B1), kept for ablation */
+
 typedef struct nxg_build_desc {
     int32_t n;              /* vertices, >= 1 */
     int64_t m;              /* input edges, >= 0 (< 2^31, and < 2^30 with SYMMETRIZE) */
@@ -80,12 +85,16 @@ typedef struct nxg_build_desc {
     const int32_t* d_dst;   /* [m] destination ids in [0, n) */
     const float* d_weight;  /* [m] edge weights, or NULL (unweighted) */
     int32_t interval;       /* I, interval size; P = ceil(n / I). 0 = planner's choice */
-    int32_t tile;           /* destination tile, a power of two; 0 = planner's choice */
+    int32_t tile;           /* destination tile size T, a power of two (tiles are the
+                               vertex ranges [k*T, (k+1)*T), any T relative to I);
+                               0 = planner's choice */
     int32_t chunk;          /* edge-stream words per work chunk, power of two in
                                [256, 65536]; 0 = planner's choice */
     int32_t value_bytes;    /* bytes of one destination accumulator the tile must hold
-                               in LDS: 4 (FP32, int32), 8 (FP64), 4*B (batched B); 0 = 4 */
+                               in LDS: 8 for PageRank (FP64 sums for FP32 and FP64
+                               values), 4 for BFS/WCC (int32); 0 = 8 */
     uint32_t flags;         /* NXG_BUILD_* */
+    int32_t order;          /* NXG_ORDER_DST (default) or NXG_ORDER_SRC */
 } nxg_build_desc;
 
 /* Builds the DSSS of the graph on `stream` and synchronises it once (to read
@@ -103,7 +112,7 @@ typedef struct nxg_dsss_info {
     int64_t m;           /* stored edges (after DEDUP / SYMMETRIZE) */
     int32_t interval;    /* I */
     int32_t P;           /* number of intervals */
-    int32_t tile;        /* destination tile size T (T <= I) */
+    int32_t tile;        /* destination tile size T */
     int32_t n_tiles;     /* destination tiles */
     int32_t chunk;       /* words per chunk */
     int64_t n_chunks;    /* chunks in the edge stream */
@@ -111,6 +120,7 @@ typedef struct nxg_dsss_info {
     int64_t device_bytes;/* bytes held on the device by the handle */
     int64_t max_tile_edges; /* edges of the heaviest destination tile */
     int32_t has_perm, has_weights, has_transpose;
+    int32_t order;       /* NXG_ORDER_* */
 } nxg_dsss_info;
 
 nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
@@ -121,9 +131,10 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
  *                         of Sec. II-A (shards of increasing j, sub-shards of
  *                         increasing i) -- counts follow the paper's layout;
  *   d_src, d_dst [m]     edges in stream order: destination tile, then source
- *                         interval, then destination, then source. When the
- *                         tile equals the interval this is exactly the DSSS
- *                         order of Sec. II-A/III-A;
+ *                         interval, then destination, then source (source,
+ *                         then destination with NXG_ORDER_SRC). When the tile
+ *                         equals the interval this is exactly the DSSS order
+ *                         of Sec. II-A/III-A;
  *   d_perm [m]           input index of each stored edge (needs KEEP_PERM).
  * transposed != 0 exports the reversed graph instead (needs TRANSPOSE).
  * Synchronises the stream. */

@@ -73,8 +73,8 @@ class DSSS:
     # ---- construction ---------------------------------------------------
     @classmethod
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
-              value_bytes=4, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
-              stream=None):
+              value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
+              order="dst", stream=None):
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -96,7 +96,8 @@ class DSSS:
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,
                            interval=int(interval), tile=int(tile), chunk=int(chunk),
-                           value_bytes=int(value_bytes), flags=flags)
+                           value_bytes=int(value_bytes), flags=flags,
+                           order={"dst": _lib.NXG_ORDER_DST, "src": _lib.NXG_ORDER_SRC}[order])
         h = ctypes.c_void_p()
         with torch.cuda.device(src.device):
             _lib.check(_lib.lib().nxg_dsss_build(ctypes.byref(d), _stream_handle(stream),

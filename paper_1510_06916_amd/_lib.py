@@ -17,13 +17,15 @@ NXG_BUILD_DEDUP = 0x8
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
 NXG_RUN_WARM_START = 0x1
+NXG_ORDER_DST, NXG_ORDER_SRC = 0, 1
 
 
 class BuildDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("d_src", ctypes.c_void_p),
                 ("d_dst", ctypes.c_void_p), ("d_weight", ctypes.c_void_p),
                 ("interval", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("value_bytes", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("value_bytes", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("order", ctypes.c_int32)]
 
 
 class DsssInfo(ctypes.Structure):
@@ -32,7 +34,8 @@ class DsssInfo(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("n_chunks", ctypes.c_int64),
                 ("n_words", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("max_tile_edges", ctypes.c_int64), ("has_perm", ctypes.c_int32),
-                ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32)]
+                ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
 
 
 class RunDesc(ctypes.Structure):

@@ -2,8 +2,9 @@
 // its sub-shard, sub-shards are destination-sorted (ties by source), shards are
 // stored contiguously, and the offset tables are derived. The sort is a
 // hand-written LSD radix sort over 64-bit keys whose bit fields are, from the
-// top: destination tile, source interval, destination within the tile, source
-// within the interval. The edge word is the key's low L + t bits.
+// top: destination tile, source interval, then destination within the tile and
+// source within the interval (source first for the source-major ablation
+// order). The edge word is the key's low L + t bits.
 #include <algorithm>
 #include <cstring>
 
@@ -33,7 +34,7 @@ __device__ inline uint64_t match_digit(uint32_t digit, uint64_t valid) {
 }
 
 struct KeyGeom {
-    int32_t n, I, T, tpi, P, L, t;
+    int32_t n, I, T, P, L, t, order;
 };
 
 // Validates ids and forms keys; payload = input edge index. With sym != 0 the
@@ -56,14 +57,14 @@ __global__ void k_make_keys(const int32_t* __restrict__ src, const int32_t* __re
             s = 0;
             d = 0;
         }
-        uint32_t j = (uint32_t)d / (uint32_t)g.I;
-        uint32_t dj = (uint32_t)d - j * (uint32_t)g.I;
-        uint32_t q = dj >> g.t;
-        uint32_t dt = dj & ((1u << g.t) - 1u);
+        uint32_t tau = (uint32_t)d >> g.t;
+        uint32_t dt = (uint32_t)d & ((1u << g.t) - 1u);
         uint32_t i = (uint32_t)s / (uint32_t)g.I;
         uint32_t sl = (uint32_t)s - i * (uint32_t)g.I;
-        uint64_t grp = ((uint64_t)j * g.tpi + q) * (uint64_t)g.P + i;
-        keys[e] = (grp << (g.t + g.L)) | ((uint64_t)dt << g.L) | sl;
+        uint64_t grp = (uint64_t)tau * (uint64_t)g.P + i;
+        uint64_t low = g.order == NXG_ORDER_SRC ? (((uint64_t)sl << g.t) | dt)
+                                                : (((uint64_t)dt << g.L) | sl);
+        keys[e] = (grp << (g.t + g.L)) | low;
         if (vals) vals[e] = (uint32_t)k;
     }
 }
@@ -226,8 +227,9 @@ __global__ void k_outdeg(const uint64_t* __restrict__ keys, int64_t m, KeyGeom g
          e += (int64_t)gridDim.x * blockDim.x) {
         uint64_t k = keys[e];
         uint32_t i = (uint32_t)((k >> (g.t + g.L)) % (uint64_t)g.P);
-        uint32_t s = i * (uint32_t)g.I + (uint32_t)(k & ((1ull << g.L) - 1ull));
-        atomicAdd(&deg[s], 1);
+        uint32_t sl = g.order == NXG_ORDER_SRC ? (uint32_t)(k >> g.t) & ((1u << g.L) - 1u)
+                                               : (uint32_t)k & ((1u << g.L) - 1u);
+        atomicAdd(&deg[i * (uint32_t)g.I + sl], 1);
     }
 }
 
@@ -369,13 +371,15 @@ __global__ void k_chunk_rows(const int64_t* __restrict__ tchunk,
     }
 }
 
-// Decodes the stream back to edges (one thread per chunk), for export.
+// Decodes the stream back to edges (one thread per chunk), for export, and
+// counts the edges of every logical sub-shard SS_{i.j} (index j*P + i).
 __global__ void k_decode(const uint32_t* __restrict__ words, const int64_t* __restrict__ tchunk,
                          int n_tiles, const int32_t* __restrict__ crow,
                          const int64_t* __restrict__ gbeg, const int64_t* __restrict__ gword,
                          KeyGeom g, int C, int64_t n_chunks, const int32_t* __restrict__ perm_in,
                          int32_t* __restrict__ osrc, int32_t* __restrict__ odst,
-                         int32_t* __restrict__ operm) {
+                         int32_t* __restrict__ operm, unsigned long long* __restrict__ lcount) {
+    const uint32_t lmask = (1u << g.L) - 1u, tmask = (1u << g.t) - 1u;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
          c += (int64_t)gridDim.x * blockDim.x) {
         int lo = 0, hi = n_tiles;
@@ -386,10 +390,9 @@ __global__ void k_decode(const uint32_t* __restrict__ words, const int64_t* __re
             else
                 hi = mid;
         }
-        const int tau = lo;
-        const int64_t g0 = (int64_t)tau * g.P;
-        const int j = tau / g.tpi, q = tau - j * g.tpi;
-        const int64_t tbase = (int64_t)j * g.I + (int64_t)q * g.T;
+        const int64_t tau = lo;
+        const int64_t g0 = tau * g.P;
+        const int64_t tbase = tau << g.t;
         int64_t row = crow[c];
         for (int64_t pos = c * (int64_t)C; pos < (c + 1) * (int64_t)C; ++pos) {
             uint32_t w = words[pos];
@@ -399,23 +402,14 @@ __global__ void k_decode(const uint32_t* __restrict__ words, const int64_t* __re
             }
             int64_t grp = g0 + row;
             int64_t e = gbeg[grp] + (pos - gword[grp] - 1);
-            if (osrc) osrc[e] = (int32_t)(row * g.I + (w & ((1u << g.L) - 1u)));
-            if (odst) odst[e] = (int32_t)(tbase + ((w >> g.L) & ((1u << g.t) - 1u)));
+            uint32_t sl = g.order == NXG_ORDER_SRC ? (w >> g.t) & lmask : w & lmask;
+            uint32_t dt = g.order == NXG_ORDER_SRC ? w & tmask : (w >> g.L) & tmask;
+            int64_t sv = row * g.I + sl, dv = tbase + dt;
+            if (osrc) osrc[e] = (int32_t)sv;
+            if (odst) odst[e] = (int32_t)dv;
             if (operm) operm[e] = perm_in[pos];
+            if (lcount) atomicAdd(&lcount[(dv / g.I) * g.P + row], 1ull);
         }
-    }
-}
-
-__global__ void k_logical_counts(const int64_t* __restrict__ gbeg, KeyGeom g,
-                                 int64_t* __restrict__ cnt) {
-    // cnt[j*P + i] += edges of group ((j*tpi + q)*P + i)
-    const int64_t G = (int64_t)g.P * g.tpi * g.P;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < G;
-         x += (int64_t)gridDim.x * blockDim.x) {
-        int64_t tau = x / g.P, i = x - tau * g.P;
-        int64_t j = tau / g.tpi;
-        int64_t c = gbeg[x + 1] - gbeg[x];
-        if (c) atomicAdd((unsigned long long*)&cnt[j * g.P + i], (unsigned long long)c);
     }
 }
 
@@ -530,7 +524,9 @@ int64_t dedup(DevBuf* kb, DevBuf* vb, int cur, int64_t m, hipStream_t s) {
 
 void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     const int64_t n = d.n;
-    int vb = d.value_bytes ? d.value_bytes : 4;
+    // default: 8-byte accumulators, enough for every program (PageRank sums in
+    // FP64; BFS/WCC need only 4)
+    int vb = d.value_bytes ? d.value_bytes : 8;
     if (vb < 1 || vb > 65536) fail(NXG_EINVAL, "value_bytes out of range");
     const int budget = lds_budget_bytes(device);
     int64_t tmax = 1;
@@ -555,19 +551,21 @@ void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     if (T < 0 || (T & (T - 1))) fail(NXG_EINVAL, "tile must be 0 or a power of two");
     if (T == 0) T = tmax;
     if (T * vb > budget) fail(NXG_EINVAL, "tile * value_bytes exceeds the LDS of one workgroup");
-    int64_t Ip2 = int64_t(1) << L.L;
-    if (T > Ip2) T = Ip2;
+    // destination tiles are global ranges [tau*T, (tau+1)*T); a tile may hold
+    // several intervals (T > I) or part of one (T < I)
+    while (T > 1 && (T >> 1) >= n) T >>= 1;
     while (L.L + ceil_log2(T) > 31) T >>= 1;
     if (T < 1) T = 1;
     L.T = (int32_t)T;
     L.t = ceil_log2(T);
-    L.tpi = (int32_t)((I + T - 1) / T);
-    int64_t nt = (int64_t)L.P * L.tpi;
+    int64_t nt = (n + T - 1) / T;
     if (nt > (int64_t)1 << 24) fail(NXG_EINVAL, "too many destination tiles");
     int64_t G = nt * L.P;
-    if (G > (int64_t)1 << 28) fail(NXG_EINVAL, "too many sub-shard groups (P too large)");
+    if (G > (int64_t)1 << 27) fail(NXG_EINVAL, "too many (tile, source interval) groups (P too large)");
     if (ceil_log2(G) + L.t + L.L > 64) fail(NXG_EINVAL, "key does not fit in 64 bits");
     L.n_tiles = (int32_t)nt;
+    if (d.order != NXG_ORDER_DST && d.order != NXG_ORDER_SRC) fail(NXG_EINVAL, "unknown order");
+    L.order = d.order;
     int64_t C = d.chunk;
     if (C == 0) {
         int64_t per_tile = (d.m + nt - 1) / std::max<int64_t>(nt, 1);
@@ -588,7 +586,7 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
     const bool payload = want_perm || want_w;
     const int64_t mt = sym ? 2 * d.m : d.m;
 
-    KeyGeom g{L.n, L.I, L.T, L.tpi, L.P, L.L, L.t};
+    KeyGeom g{L.n, L.I, L.T, L.P, L.L, L.t, L.order};
     const int64_t G = (int64_t)L.n_tiles * L.P;
     const int sh = L.t + L.L;
     const int bits = ceil_log2(std::max<int64_t>(G, 2)) + sh;
@@ -711,23 +709,21 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
 
 void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
                    int32_t* d_perm, hipStream_t s) {
-    KeyGeom g{L.n, L.I, L.T, L.tpi, L.P, L.L, L.t};
+    KeyGeom g{L.n, L.I, L.T, L.P, L.L, L.t, L.order};
     if (d_perm && !L.has_perm) fail(NXG_EINVAL, "export of perm needs NXG_BUILD_KEEP_PERM");
-    if (d_offsets) {
-        const int64_t PP = (int64_t)L.P * L.P;
-        NXG_HIP(hipMemsetAsync(d_offsets, 0, sizeof(int64_t) * (PP + 1), s));
-        hipLaunchKernelGGL(k_logical_counts, dim3(grid_for((int64_t)L.n_tiles * L.P)), dim3(256), 0,
-                           s, L.group_edge.as<int64_t>(), g, d_offsets);
-        NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_i64_inplace_excl, dim3(1), dim3(1024), 0, s, d_offsets, PP);
-        NXG_CHECK_LAUNCH();
-    }
-    if ((d_src || d_dst || d_perm) && L.n_chunks > 0) {
+    const int64_t PP = (int64_t)L.P * L.P;
+    if (d_offsets) NXG_HIP(hipMemsetAsync(d_offsets, 0, sizeof(int64_t) * (PP + 1), s));
+    if ((d_offsets || d_src || d_dst || d_perm) && L.n_chunks > 0) {
         hipLaunchKernelGGL(k_decode, dim3(grid_for(L.n_chunks, 64)), dim3(64), 0, s,
                            L.words.as<uint32_t>(), L.tile_chunk.as<int64_t>(), L.n_tiles,
                            L.chunk_row.as<int32_t>(), L.group_edge.as<int64_t>(),
                            L.group_word.as<int64_t>(), g, L.C, L.n_chunks,
-                           L.has_perm ? L.perm.as<int32_t>() : nullptr, d_src, d_dst, d_perm);
+                           L.has_perm ? L.perm.as<int32_t>() : nullptr, d_src, d_dst, d_perm,
+                           (unsigned long long*)d_offsets);
+        NXG_CHECK_LAUNCH();
+    }
+    if (d_offsets) {
+        hipLaunchKernelGGL(k_scan_i64_inplace_excl, dim3(1), dim3(1024), 0, s, d_offsets, PP);
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipStreamSynchronize(s));

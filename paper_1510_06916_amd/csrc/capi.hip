@@ -100,7 +100,7 @@ nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** o
         nxg_dsss* g = new nxg_dsss();
         try {
             NXG_HIP(hipGetDevice(&g->device));
-            g->value_bytes = d.value_bytes ? d.value_bytes : 4;
+            g->value_bytes = d.value_bytes ? d.value_bytes : 8;
             g->flags = d.flags;
             build_layout(d, false, s, g->fwd);
             if (d.flags & NXG_BUILD_TRANSPOSE) {
@@ -148,6 +148,7 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
         info->has_perm = L.has_perm;
         info->has_weights = L.has_weight;
         info->has_transpose = g->has_rev;
+        info->order = L.order;
         return NXG_OK;
     });
 }

@@ -25,6 +25,9 @@ namespace {
 constexpr uint32_t kMarker = 0x80000000u;
 constexpr int32_t kInf = INT32_MAX;
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 
 struct Geo {
@@ -33,7 +36,8 @@ struct Geo {
     const int32_t* chunk_row_last;
     const Item* items;
     const int32_t* deg;
-    int32_t n, I, P, L, T, t, tpi, n_tiles, C;
+    int32_t n, I, P, L, T, t, n_tiles, C;
+    int32_t sshift, dshift;  // bit offsets of the source and destination fields
     // two-phase partials
     void* partial;
     int32_t* tile_ctr;
@@ -60,9 +64,12 @@ struct Ctl {
 
 // PageRank with W = 1/outdeg. The gathered array holds x_u / outdeg_u (x_u for
 // dangling u, which is never gathered), so no separate x vector is kept.
+// Destination sums accumulate in FP64 in LDS whatever the value type: on gfx950
+// the LDS FP64 atomic add sustains several times the throughput of the FP32
+// one, and the sums of high in-degree vertices keep FP64 accuracy.
 template <typename V>
 struct ProgPR {
-    using acc_t = V;
+    using acc_t = double;
     static constexpr bool kSum = true, kWeights = false, kActivity = false;
     const V* cur;
     V* nxt;
@@ -70,7 +77,7 @@ struct ProgPR {
     V* xout;         // nullable: write x on this iteration
     double d;
     __device__ acc_t identity() const { return (acc_t)0; }
-    __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
+    __device__ acc_t gather(uint32_t src, float) const { return (acc_t)cur[src]; }
     __device__ bool row_active(uint32_t) const { return true; }
     // s0: dangling mass of x^{k+1}; s1: |x^{k+1} - x^k|
     __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
@@ -90,10 +97,11 @@ struct ProgPR {
     }
 };
 
-// PageRank with the stored edge weights: gathers x_u and multiplies by w_e.
+// PageRank with the stored edge weights: gathers x_u and multiplies by w_e
+// (FP64 accumulation as above).
 template <typename V>
 struct ProgPRW {
-    using acc_t = V;
+    using acc_t = double;
     static constexpr bool kSum = true, kWeights = true, kActivity = false;
     const V* cur;
     V* nxt;
@@ -102,7 +110,7 @@ struct ProgPRW {
     const float* w;  // [n_words] weights in stream order
     double d;
     __device__ acc_t identity() const { return (acc_t)0; }
-    __device__ acc_t gather(uint32_t src, float we) const { return (acc_t)we * cur[src]; }
+    __device__ acc_t gather(uint32_t src, float we) const { return (acc_t)we * (acc_t)cur[src]; }
     __device__ bool row_active(uint32_t) const { return true; }
     __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
                           double& s1, int&) const {
@@ -128,7 +136,8 @@ struct ProgBFS {
     const int32_t* cur;
     int32_t* nxt;
     const uint8_t* act;  // [P] source intervals updated in the previous round
-    int32_t P;
+    uint8_t* act_nxt;    // [P] intervals updated in this round
+    int32_t P, I;
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t gather(uint32_t src, float) const {
         int32_t l = cur[src];
@@ -140,7 +149,10 @@ struct ProgBFS {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) flag = 1;
+        if (nv != o) {
+            flag = 1;
+            act_nxt[v / I] = 1;
+        }
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -152,7 +164,8 @@ struct ProgWCC {
     const int32_t* cur;
     int32_t* nxt;
     const uint8_t* act;
-    int32_t P;
+    uint8_t* act_nxt;
+    int32_t P, I;
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
     __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
@@ -161,7 +174,10 @@ struct ProgWCC {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) flag = 1;
+        if (nv != o) {
+            flag = 1;
+            act_nxt[v / I] = 1;
+        }
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -169,6 +185,15 @@ struct ProgWCC {
 __device__ inline void lds_combine(float* p, float v, bool) { atomicAdd(p, v); }
 __device__ inline void lds_combine(double* p, double v, bool) { atomicAdd(p, v); }
 __device__ inline void lds_combine(int32_t* p, int32_t v, bool sum) {
+    if (sum)
+        atomicAdd(p, v);
+    else
+        atomicMin(p, v);
+}
+
+// Device-scope atomics on the hub of a split tile (native FP64 add, int min).
+__device__ inline void global_combine(double* p, double v, bool) { unsafeAtomicAdd(p, v); }
+__device__ inline void global_combine(int32_t* p, int32_t v, bool sum) {
     if (sum)
         atomicAdd(p, v);
     else
@@ -203,10 +228,8 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
 
     const Item it = g.items[blockIdx.x];
     const int tile = it.tile;
-    const int j = tile / g.tpi, q = tile - j * g.tpi;
-    const int64_t base = (int64_t)j * g.I + (int64_t)q * g.T;
-    int64_t len = min((int64_t)g.T, (int64_t)g.I - (int64_t)q * g.T);
-    len = min(len, (int64_t)g.n - base);
+    const int64_t base = (int64_t)tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
     if (len < 0) len = 0;
 
     // Once converged (tolerance met) the remaining iterations only carry the
@@ -238,70 +261,116 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
         c_hi = cnt * (it.piece + 1) / it.npieces;
     }
 
+    // A wave step covers kU sub-blocks of 256 words (64 lanes x 4 consecutive
+    // words, one 16-byte load each): all word loads of the step are issued
+    // first, then all gathers, then the LDS reductions, so each lane keeps up to
+    // 4 * kU independent gathers in flight.
+    constexpr int kU = 4;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
     for (int64_t ci = c_lo + wave; ci < c_hi; ci += WG / 64) {
         const int64_t c = list ? list[ci] : ci;
         uint32_t row = (uint32_t)g.chunk_row[c];
-        const uint4* wp = reinterpret_cast<const uint4*>(g.words + c * (int64_t)g.C);
-        const float4* wwp = nullptr;
-        if constexpr (Prog::kWeights) wwp = reinterpret_cast<const float4*>(prog.w + c * (int64_t)g.C);
-        for (int s = 0; s < steps; ++s) {
-            const uint4 w4 = wp[s * 64 + lane];
-            float wv[4] = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (Prog::kWeights) {
-                const float4 f = wwp[s * 64 + lane];
-                wv[0] = f.x;
-                wv[1] = f.y;
-                wv[2] = f.z;
-                wv[3] = f.w;
-            }
-            const uint32_t wd[4] = {w4.x, w4.y, w4.z, w4.w};
-            // source interval in effect at this lane's first word
-            uint32_t r = row;
-            const uint32_t has = (wd[0] | wd[1] | wd[2] | wd[3]) >> 31;
-            const uint64_t mm = __ballot(has);
-            if (mm) {
-                uint32_t last = 0;
+        const u32x4* wp = reinterpret_cast<const u32x4*>(g.words + c * (int64_t)g.C);
+        const f32x4* wwp = nullptr;
+        if constexpr (Prog::kWeights)
+            wwp = reinterpret_cast<const f32x4*>(prog.w + c * (int64_t)g.C);
+        for (int s = 0; s < steps; s += kU) {
+            uint32_t wd[kU * 4];
+            float wf[kU * 4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (wd[k] & kMarker) last = wd[k] & ~kMarker;
-                const uint64_t prev = mm & lt;
-                const int from = prev ? 63 - __clzll(prev) : lane;
-                const uint32_t got = __shfl(last, from);
-                r = prev ? got : row;
-                row = __shfl(last, 63 - __clzll(mm));
-            }
-            uint32_t rb = r * (uint32_t)g.I;
-            bool on = prog.row_active(r);
-            uint32_t pd = 0xFFFFFFFFu;
-            acc_t pv = prog.identity();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t w = wd[k];
-                if (w & kMarker) {
-                    r = w & ~kMarker;
-                    rb = r * (uint32_t)g.I;
-                    on = prog.row_active(r);
-                    continue;
-                }
-                if (!on) continue;
-                const uint32_t dst = (w >> g.L) & tmask;
-                const acc_t v = prog.gather(rb + (w & lmask), wv[k]);
-                if (dst == pd) {
-                    pv = combine<Prog::kSum>(pv, v);
+            for (int u = 0; u < kU; ++u) {
+                u32x4 w4 = {kNone, kNone, kNone, kNone};  // padding words
+                if (s + u < steps) w4 = __builtin_nontemporal_load(wp + (s + u) * 64 + lane);
+                wd[4 * u + 0] = w4.x;
+                wd[4 * u + 1] = w4.y;
+                wd[4 * u + 2] = w4.z;
+                wd[4 * u + 3] = w4.w;
+                if constexpr (Prog::kWeights) {
+                    f32x4 f4 = {0.f, 0.f, 0.f, 0.f};
+                    if (s + u < steps) f4 = __builtin_nontemporal_load(wwp + (s + u) * 64 + lane);
+                    wf[4 * u + 0] = f4.x;
+                    wf[4 * u + 1] = f4.y;
+                    wf[4 * u + 2] = f4.z;
+                    wf[4 * u + 3] = f4.w;
                 } else {
-                    if (pd != 0xFFFFFFFFu && (Prog::kSum || pv != prog.identity()))
-                        lds_combine(&acc[pd], pv, Prog::kSum);
-                    pd = dst;
-                    pv = v;
+                    wf[4 * u + 0] = wf[4 * u + 1] = wf[4 * u + 2] = wf[4 * u + 3] = 0.f;
                 }
             }
-            if (pd != 0xFFFFFFFFu && (Prog::kSum || pv != prog.identity()))
-                lds_combine(&acc[pd], pv, Prog::kSum);
+            // decode: source index and destination (kNone for markers, padding and
+            // edges out of inactive source intervals)
+            uint32_t sidx[kU * 4], dl[kU * 4];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t* w = wd + 4 * u;
+                const uint64_t mm = __ballot(((w[0] | w[1] | w[2] | w[3]) >> 31) != 0);
+                if (mm == 0) {
+                    // whole sub-block inside one source interval (uniform)
+                    const uint32_t rb = row * (uint32_t)g.I;
+                    const bool on = prog.row_active(row);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
+                        dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
+                    }
+                } else {
+                    uint32_t last = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (w[k] & kMarker) last = w[k] & ~kMarker;
+                    const uint64_t prev = mm & lt;
+                    const int from = prev ? 63 - __clzll(prev) : lane;
+                    const uint32_t got = __shfl(last, from);
+                    uint32_t r = prev ? got : row;
+                    row = __shfl(last, 63 - __clzll(mm));
+                    uint32_t rb = r * (uint32_t)g.I;
+                    bool on = prog.row_active(r);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (w[k] & kMarker) {
+                            r = w[k] & ~kMarker;
+                            rb = r * (uint32_t)g.I;
+                            on = prog.row_active(r);
+                            sidx[4 * u + k] = 0;
+                            dl[4 * u + k] = kNone;
+                        } else {
+                            sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
+                            dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
+                        }
+                    }
+                }
+            }
+            acc_t val[kU * 4];
+#pragma unroll
+            for (int k = 0; k < kU * 4; ++k)
+                val[k] = dl[k] != kNone ? prog.gather(sidx[k], wf[k]) : prog.identity();
+            // reduce: merge runs of equal destination inside the lane's 4 words
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                uint32_t pd = kNone;
+                acc_t pv = prog.identity();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t d = dl[4 * u + k];
+                    if (d == kNone) continue;
+                    if (d == pd) {
+                        pv = combine<Prog::kSum>(pv, val[4 * u + k]);
+                    } else {
+                        if (pd != kNone && (Prog::kSum || pv != prog.identity()))
+                            lds_combine(&acc[pd], pv, Prog::kSum);
+                        pd = d;
+                        pv = val[4 * u + k];
+                    }
+                }
+                if (pd != kNone && (Prog::kSum || pv != prog.identity()))
+                    lds_combine(&acc[pd], pv, Prog::kSum);
+            }
         }
     }
     __syncthreads();
 
-    // ---- two-phase: publish the partial, the last piece combines ---------
+    // ---- two-phase: every piece writes its partial to its slot of the tile's
+    // hub (Alg. 6 ToHub); the last piece to arrive sums the slots in piece order
+    // (FromHub) into LDS and applies the update --------------------------------
     if (it.npieces > 1) {
         acc_t* part = reinterpret_cast<acc_t*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T;
         for (int64_t x = threadIdx.x; x < len; x += WG) part[x] = acc[x];
@@ -315,12 +384,22 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
         __syncthreads();
         if (!slast) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // eight slots per pass so the loads of a thread are independent
         const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
         for (int64_t x = threadIdx.x; x < len; x += WG) {
-            acc_t s = prog.identity();
-            for (int p = 0; p < it.npieces; ++p)
-                s = combine<Prog::kSum>(s, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
-            acc[x] = s;
+            acc_t sum = prog.identity();
+            int p = 0;
+            for (; p + 8 <= it.npieces; p += 8) {
+                acc_t v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    v[q] = __builtin_nontemporal_load(p0 + (int64_t)(p + q) * g.T + x);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sum = combine<Prog::kSum>(sum, v[q]);
+            }
+            for (; p < it.npieces; ++p)
+                sum = combine<Prog::kSum>(sum, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
+            acc[x] = sum;
         }
         if (threadIdx.x == 0) g.tile_ctr[tile] = 0;
         __syncthreads();
@@ -423,39 +502,38 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __r
 }
 
 __global__ void k_init_bfs(int32_t n, int32_t root, int32_t* __restrict__ lev,
-                           int32_t* __restrict__ tile_flag, int n_tiles, int tpi, int I) {
+                           uint8_t* __restrict__ act, int P, int I) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
         lev[v] = v == root ? 0 : kInf;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_tiles;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P;
          x += (int64_t)gridDim.x * blockDim.x)
-        tile_flag[x] = (x / tpi) == (root / I) ? 1 : 0;
+        act[x] = x == root / I ? 1 : 0;
 }
 
-__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, int32_t* __restrict__ tile_flag,
-                           int n_tiles) {
+__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, uint8_t* __restrict__ act, int P) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
         lab[v] = (int32_t)v;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_tiles;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P;
          x += (int64_t)gridDim.x * blockDim.x)
-        tile_flag[x] = 1;
+        act[x] = 1;
 }
 
 // Interval activity (Sec. II-B): interval i is active in this round iff one of
-// its vertices changed in the previous round; apref = prefix count of actives.
-__global__ __launch_bounds__(1024) void k_activity(const int32_t* __restrict__ tile_flag, int P,
-                                                   int tpi, uint8_t* __restrict__ act,
-                                                   int32_t* __restrict__ apref) {
+// its vertices changed in the previous round (flags written by the apply).
+// apref = prefix count of active intervals; the flags the coming round will
+// write are cleared here.
+__global__ __launch_bounds__(1024) void k_activity(const uint8_t* __restrict__ act, int P,
+                                                   int32_t* __restrict__ apref,
+                                                   uint8_t* __restrict__ act_next) {
     __shared__ int32_t part[1024];
     const int per = (P + 1023) / 1024;
     const int a = threadIdx.x * per, b = min(P, a + per);
     int32_t s = 0;
     for (int i = a; i < b; ++i) {
-        int f = 0;
-        for (int q = 0; q < tpi; ++q) f |= tile_flag[(int64_t)i * tpi + q];
-        act[i] = (uint8_t)(f != 0);
-        s += f != 0;
+        s += act[i] != 0;
+        act_next[i] = 0;
     }
     part[threadIdx.x] = s;
     __syncthreads();
@@ -468,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_activity(const int32_t* __restrict__ t
     int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
     for (int i = a; i < b; ++i) {
         apref[i] = run;
-        run += act[i];
+        run += act[i] != 0;
     }
     if (threadIdx.x == 1023) apref[P] = part[1023];
 }
@@ -521,6 +599,13 @@ __global__ __launch_bounds__(256) void k_bfs_final(int32_t n, const int32_t* __r
     }
     atomicMax(maxlev, mx);
     atomicAdd(reached, r);
+}
+
+template <typename V>
+__global__ void k_fill_val(V* __restrict__ p, int64_t n, V v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 template <typename V>
@@ -635,7 +720,8 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
     g.L = L.L;
     g.T = L.T;
     g.t = L.t;
-    g.tpi = L.tpi;
+    g.sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
+    g.dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
     g.n_tiles = L.n_tiles;
     g.C = L.C;
     g.partial = w.partial.p;
@@ -649,8 +735,11 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
 }
 
 void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
-                  hipStream_t s) {
-    w.partial.alloc((size_t)std::max(p.n_slots, 1) * L.T * vb, s);
+                  hipStream_t s, bool min_identity) {
+    // one tile-sized partial per piece of a split tile (written before read)
+    (void)min_identity;
+    const int64_t hub_elems = (int64_t)std::max(p.n_slots, 1) * L.T;
+    w.partial.alloc((size_t)hub_elems * vb, s);
     w.tile_ctr.alloc(sizeof(int32_t) * L.n_tiles, s);
     NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
     w.all_ctr.alloc(sizeof(int32_t), s);
@@ -669,15 +758,17 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
     if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
     const size_t vb = sizeof(V);
-    if ((size_t)L.T * vb > (size_t)lds_budget_bytes(g->device))
-        fail(NXG_EINVAL, "destination tile does not fit in LDS for this dtype; rebuild with value_bytes");
+    const size_t ab = sizeof(double);  // LDS accumulator bytes per destination
+    if ((size_t)L.T * ab > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "destination tile does not fit in LDS (PageRank accumulates 8 bytes per "
+                         "vertex); rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
     Plan* p = get_plan(g, L, piece, false, s);
     Workspace w;
     const int max_iters = d.max_iters;
-    alloc_common(w, L, *p, vb, max_iters, s);
+    alloc_common(w, L, *p, ab, max_iters, s, false);
     w.buf[0].alloc(vb * L.n, s);
     w.buf[1].alloc(vb * L.n, s);
     const int nb = grid_for(L.n, 256, 1024);
@@ -691,7 +782,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
                        w.stats.as<double>());
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w);
-    const size_t lds = (size_t)L.T * vb;
+    const size_t lds = (size_t)L.T * ab;
     const int n_items = (int)p->h_items.size();
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
@@ -790,20 +881,20 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     Plan* p = get_plan(g, L, -piece, true, s);  // whole-tile ranges; pieces split the active list
     Workspace w;
     const int max_iters = d.max_iters;
-    alloc_common(w, L, *p, 4, max_iters, s);
+    alloc_common(w, L, *p, 4, max_iters, s, true);
     w.buf[0].alloc(sizeof(int32_t) * L.n, s);
     w.buf[1].alloc(sizeof(int32_t) * L.n, s);
-    w.act.alloc(L.P, s);
+    w.act.alloc(2 * (size_t)L.P, s);
     w.apref.alloc(sizeof(int32_t) * (L.P + 1), s);
     w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
     w.ccount.alloc(sizeof(int32_t) * L.n_tiles, s);
+    uint8_t* act0 = w.act.as<uint8_t>();
     if (bfs)
-        hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(std::max<int64_t>(L.n, L.n_tiles))), dim3(256), 0,
-                           s, L.n, d.roots[0], w.buf[0].as<int32_t>(), w.tile_flag.as<int32_t>(),
-                           L.n_tiles, L.tpi, L.I);
+        hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
+                           s, L.n, d.roots[0], w.buf[0].as<int32_t>(), act0, L.P, L.I);
     else
-        hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.n_tiles))), dim3(256), 0,
-                           s, L.n, w.buf[0].as<int32_t>(), w.tile_flag.as<int32_t>(), L.n_tiles);
+        hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
+                           s, L.n, w.buf[0].as<int32_t>(), act0, L.P);
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w);
     geo.clist = w.clist.as<int64_t>();
@@ -823,8 +914,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         int kend = std::min(max_iters, k + block);
         int kb = k;
         for (; k < kend; ++k) {
-            hipLaunchKernelGGL(k_activity, dim3(1), dim3(1024), 0, s, w.tile_flag.as<int32_t>(), L.P,
-                               L.tpi, w.act.as<uint8_t>(), w.apref.as<int32_t>());
+            uint8_t* act_cur = act0 + (size_t)(k & 1) * L.P;
+            uint8_t* act_nxt = act0 + (size_t)((k + 1) & 1) * L.P;
+            hipLaunchKernelGGL(k_activity, dim3(1), dim3(1024), 0, s, act_cur, L.P,
+                               w.apref.as<int32_t>(), act_nxt);
             NXG_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_compact, dim3(L.n_tiles), dim3(256), 0, s, L.tile_chunk.as<int64_t>(),
                                L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
@@ -834,10 +927,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             const int32_t* cur = w.buf[k & 1].as<int32_t>();
             int32_t* nxt = w.buf[(k + 1) & 1].as<int32_t>();
             if (bfs) {
-                ProgBFS pr{cur, nxt, w.act.as<uint8_t>(), L.P};
+                ProgBFS pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
                 launch_iter<ProgBFS, 1024>(geo, ctl, pr, n_items, lds, s);
             } else {
-                ProgWCC pr{cur, nxt, w.act.as<uint8_t>(), L.P};
+                ProgWCC pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
                 launch_iter<ProgWCC, 1024>(geo, ctl, pr, n_items, lds, s);
             }
         }

@@ -79,16 +79,19 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // Physical DSSS layout.
 //
-// The destination range of every interval j is cut into tiles of T vertices
-// (T a power of two; tiles never straddle an interval). Tile tau = j*tpi + q
-// owns destinations [j*I + q*T, j*I + min((q+1)*T, I)). The edge stream lists
-// tiles in increasing tau; inside a tile, the edges of source interval i come
-// before those of interval i+1, and inside one (tile, i) group edges are sorted
-// by destination, then source -- the paper's sub-shard order restricted to the
-// tile. With T >= I the stream is exactly the DSSS order.
+// Destinations are cut into tiles of T vertices (T a power of two; tile tau
+// owns [tau*T, (tau+1)*T)), independent of the interval size I: a tile's
+// accumulators must fit in LDS, while I sets the source window each group
+// gathers from. The edge stream lists tiles in increasing tau; inside a tile,
+// the edges of source interval i come before those of interval i+1, and inside
+// one (tile, i) group edges are sorted by destination, then source -- the
+// paper's sub-shard order restricted to the tile. With T == I the stream is
+// exactly the DSSS order. (order == NXG_ORDER_SRC sorts each group by source,
+// then destination instead: the source-sorted ablation.)
 //
-// Each edge is one 32-bit word: bits [0, L) = src - i*I, bits [L, L+t) =
-// dst - tile base, bit 31 clear (needs L + t <= 31). Each non-empty group is
+// Each edge is one 32-bit word, bit 31 clear (needs L + t <= 31): in DSSS
+// order bits [0, L) = src - i*I and bits [L, L+t) = dst - tile base; in the
+// source-major order the two fields swap places. Each non-empty group is
 // preceded by a marker word 0x80000000 | i. A tile's words are padded with
 // 0xFFFFFFFF to a multiple of the chunk size C, so every chunk belongs to one
 // tile; chunk_row[c] is the source interval in effect at the chunk's first
@@ -96,7 +99,7 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 struct Layout {
     int32_t n = 0, I = 0, P = 0, L = 0;
-    int32_t T = 0, t = 0, tpi = 0, n_tiles = 0, C = 0;
+    int32_t T = 0, t = 0, n_tiles = 0, C = 0, order = 0;
     int64_t m = 0, n_chunks = 0, n_words = 0, max_tile_edges = 0;
     DevBuf words;          // uint32 [n_words]
     DevBuf chunk_row;      // int32  [n_chunks]

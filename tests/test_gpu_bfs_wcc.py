@@ -10,7 +10,8 @@ from gpu_util import say, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("scale,interval,tile", [(12, 512, 0), (13, 8192, 1024), (14, 1000, 0)])
+@pytest.mark.parametrize("scale,interval,tile", [(12, 512, 0), (13, 8192, 1024), (14, 1000, 0),
+                                                 (14, 700, 8192)])
 def test_bfs_bit_exact(gpu_device, scale, interval, tile):
     n = 1 << scale
     src, dst = rmatgen.rmat_edges(scale, 8, seed=scale)

@@ -12,13 +12,14 @@ from gpu_util import say, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _stream_order(src, dst, I, T):
-    """(tile, source interval, dst, src) order; equals the DSSS order when T >= I."""
-    j = dst // I
-    q = (dst - j * I) // T
-    tiles_per = -(-I // T)
-    tau = j * tiles_per + q
-    return np.lexsort((np.arange(len(src)), src, dst, src // I, tau))
+def _stream_order(src, dst, I, T, order="dst"):
+    """(tile, source interval, dst, src) order -- (tile, interval, src, dst) for the
+    source-major ablation; with T == I and order "dst" this is the DSSS order."""
+    tau = dst // T
+    idx = np.arange(len(src))
+    if order == "dst":
+        return np.lexsort((idx, src, dst, src // I, tau))
+    return np.lexsort((idx, dst, src, src // I, tau))
 
 
 def test_paper_example(gpu_device):
@@ -28,8 +29,9 @@ def test_paper_example(gpu_device):
     src = np.array([edges[k][0] for k in order], np.int32)
     dst = np.array([edges[k][1] for k in order], np.int32)
     say("paper example: n=8 I=2")
+    # tile == interval makes the stream order exactly the paper's DSSS order
     g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), 8,
-                   interval=meta["interval_size"], keep_perm=True)
+                   interval=meta["interval_size"], tile=meta["interval_size"], keep_perm=True)
     ex = g.export(perm=True)
     off = ex["offsets"].cpu().numpy()
     P = 4
@@ -41,11 +43,13 @@ def test_paper_example(gpu_device):
     assert np.array_equal(ex["perm"].cpu().numpy(), perm_o)
 
 
-@pytest.mark.parametrize("n,interval,tile,chunk", [
-    (1000, 250, 0, 256), (1000, 64, 0, 256), (1000, 1, 0, 256), (1000, 1000, 0, 512),
-    (4096, 1024, 256, 256), (5000, 3000, 1024, 1024), (4096, 4096, 64, 256), (77, 7, 0, 256),
+@pytest.mark.parametrize("n,interval,tile,chunk,order", [
+    (1000, 250, 256, 256, "dst"), (1000, 64, 0, 256, "dst"), (1000, 1, 0, 256, "dst"),
+    (1000, 1000, 1024, 512, "dst"), (4096, 1024, 256, 256, "dst"), (5000, 3000, 1024, 1024, "dst"),
+    (4096, 4096, 64, 256, "dst"), (77, 7, 0, 256, "dst"), (4096, 512, 4096, 256, "dst"),
+    (5000, 700, 2048, 256, "dst"), (4096, 1024, 1024, 256, "src"), (5000, 300, 4096, 512, "src"),
 ])
-def test_structure_matches_oracle(gpu_device, n, interval, tile, chunk):
+def test_structure_matches_oracle(gpu_device, n, interval, tile, chunk, order):
     src, dst = rmatgen.rmat_edges(13, 8, seed=12)
     keep = (src < n) & (dst < n)
     src, dst = src[keep], dst[keep]
@@ -55,20 +59,21 @@ def test_structure_matches_oracle(gpu_device, n, interval, tile, chunk):
     dst = np.concatenate([dst, dst[dup]]).astype(np.int32)
     p = rng.permutation(len(src))
     src, dst = src[p], dst[p]
-    say("build n=%d I=%d tile=%d chunk=%d m=%d" % (n, interval, tile, chunk, len(src)))
+    say("build n=%d I=%d tile=%d chunk=%d order=%s m=%d" % (n, interval, tile, chunk, order,
+                                                            len(src)))
     g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=interval,
-                   tile=tile, chunk=chunk, keep_perm=True)
+                   tile=tile, chunk=chunk, keep_perm=True, order=order)
     inf = g.info()
     assert inf["m"] == len(src) and inf["P"] == -(-n // interval)
     ex = g.export(perm=True)
     perm_o, off_o = oracle.dsss_order(n, src, dst, interval)
     assert np.array_equal(ex["offsets"].cpu().numpy(), off_o)
-    order = _stream_order(src.astype(np.int64), dst.astype(np.int64), interval, inf["tile"])
-    assert np.array_equal(ex["perm"].cpu().numpy(), order)
-    assert np.array_equal(ex["src"].cpu().numpy(), src[order])
-    assert np.array_equal(ex["dst"].cpu().numpy(), dst[order])
-    if inf["tile"] >= interval:
-        assert np.array_equal(order, perm_o)
+    want = _stream_order(src.astype(np.int64), dst.astype(np.int64), interval, inf["tile"], order)
+    assert np.array_equal(ex["perm"].cpu().numpy(), want)
+    assert np.array_equal(ex["src"].cpu().numpy(), src[want])
+    assert np.array_equal(ex["dst"].cpu().numpy(), dst[want])
+    if inf["tile"] == interval and order == "dst":
+        assert np.array_equal(want, perm_o)
 
 
 def test_dedup_and_symmetrize(gpu_device):

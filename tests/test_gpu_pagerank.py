@@ -43,13 +43,16 @@ def test_cfg1_fp32_piece_sizes(gpu_device, cfg1, piece, monkeypatch):
     assert rel_l1(x.cpu().numpy(), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("interval,tile,chunk", [(4096, 0, 256), (1000, 256, 256), (65536, 2048, 1024)])
-def test_layouts_fp64(gpu_device, cfg1, interval, tile, chunk):
+@pytest.mark.parametrize("interval,tile,chunk,order", [
+    (4096, 0, 256, "dst"), (1000, 256, 256, "dst"), (65536, 2048, 1024, "dst"),
+    (2048, 16384, 256, "dst"), (3000, 8192, 1024, "dst"), (4096, 16384, 1024, "src"),
+    (16384, 16384, 2048, "src")])
+def test_layouts_fp64(gpu_device, cfg1, interval, tile, chunk, order):
     src, dst, n = cfg1
     ref, _ = oracle.pagerank(n, src, dst, iters=6)
     g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=interval,
-                   tile=tile, chunk=chunk, value_bytes=8)
-    say("layout I=%d tile=%d chunk=%d" % (interval, tile, chunk))
+                   tile=tile, chunk=chunk, value_bytes=8, order=order)
+    say("layout I=%d tile=%d chunk=%d order=%s" % (interval, tile, chunk, order))
     x, _ = g.pagerank(6, dtype=torch.float64)
     assert rel_l1(x.cpu().numpy(), ref) <= 1e-12
 
