@@ -187,6 +187,40 @@ typedef struct nxg_run_stats {
  * (values are still written). */
 nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
 
+/* ------------------------------------------------------------------------- */
+/* Weighted PageRank: new weights and the adjoint (gradient) pass             */
+/* ------------------------------------------------------------------------- */
+
+/* Replaces the stored edge weights with d_weight [m] (input edge order, FP32)
+ * in the forward and, if present, the reversed graph. Needs a build with
+ * weights and NXG_BUILD_KEEP_PERM. Asynchronous. */
+nxg_status nxg_dsss_set_weights(nxg_dsss* g, const float* d_weight, void* stream);
+
+typedef struct nxg_adjoint_desc {
+    double damping;         /* d of the forward run */
+    double tol;             /* stop when ||lambda^{k+1}-lambda^k||_1 <= tol * ||lambda^{k+1}||_1;
+                               <= 0 runs exactly max_iters */
+    int32_t max_iters;      /* >= 1 */
+    const double* d_xstar;  /* [n] converged forward vector x* (FP64) */
+    const double* d_gx;     /* [n] dL/dx* (FP64) */
+    double* d_lambda;       /* [n] out: adjoint vector, or NULL */
+    float* d_gw;            /* [m] out: dL/dw_e in input edge order, or NULL */
+    double* d_gt;           /* [n] out: dL/dt = (1 - d) lambda, or NULL */
+} nxg_adjoint_desc;
+
+/* Gradient of L(x*) through the weighted-PageRank fixed point
+ * x* = d (W^T x* + delta/n) + (1-d) t, with respect to the stored (given)
+ * weights and the teleport vector, for dL/dx* = gx (the paper has no such
+ * pass; it is the reverse-mode derivative of the forward iteration). The
+ * adjoint lambda = gx + d (W lambda + 1_D sum(lambda)/n) is iterated over the
+ * reversed graph -- each reduction runs by forward source, over out-edges --
+ * then dL/dw_e = d x*[src_e] lambda[dst_e] and dL/dt = (1 - d) lambda. Needs a
+ * build with weights, NXG_BUILD_TRANSPOSE and NXG_BUILD_KEEP_PERM and
+ * value_bytes 8. Synchronises the stream; fills *stats if non-NULL. Returns
+ * NXG_ENOTCONV (outputs still written) when tol was not reached. */
+nxg_status nxg_pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc* desc, void* stream,
+                                nxg_run_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import NxgError  # noqa: F401
 
-__all__ = ["DSSS", "NxgError", "abi_version", "install_torch_allocator"]
+__all__ = ["DSSS", "NxgError", "WeightedPageRank", "abi_version", "install_torch_allocator"]
 
 _alloc_refs = None
 
@@ -69,6 +69,7 @@ class DSSS:
         self._h = handle
         self.device = device
         self._info = None
+        self.weights_version = 0
 
     # ---- construction ---------------------------------------------------
     @classmethod
@@ -196,3 +197,74 @@ class DSSS:
                          max_iters=int(max_rounds if max_rounds is not None else n + 1), tol=0.0,
                          d_teleport=None, roots=None, d_values=lab.data_ptr(), flags=0)
         return lab, self._run(d)
+
+    # ---- weighted PageRank and its adjoint ------------------------------
+    def set_weights(self, w):
+        """Replaces the stored edge weights (input edge order)."""
+        w = w.detach().to(device=self.device, dtype=torch.float32).contiguous()
+        if w.numel() != self.info()["m"]:
+            raise ValueError("one weight per stored edge expected")
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().nxg_dsss_set_weights(self._h, w.data_ptr(), _stream_handle()),
+                       "nxg_dsss_set_weights")
+        self.weights_version += 1
+
+    def pagerank_adjoint(self, xstar, gx, damping=0.85, tol=1e-12, max_iters=100000):
+        """Returns (lambda, dL/dw [m] FP32 input edge order, dL/dt [n] FP64, stats)."""
+        n, m = self.n, self.m
+        xs = xstar.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        g = gx.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        lam = torch.empty(n, dtype=torch.float64, device=self.device)
+        gw = torch.empty(m, dtype=torch.float32, device=self.device)
+        gt = torch.empty(n, dtype=torch.float64, device=self.device)
+        d = _lib.AdjointDesc(damping=float(damping), tol=float(tol), max_iters=int(max_iters),
+                             d_xstar=xs.data_ptr(), d_gx=g.data_ptr(), d_lambda=lam.data_ptr(),
+                             d_gw=gw.data_ptr() if m else None, d_gt=gt.data_ptr())
+        st = _lib.RunStats()
+        with torch.cuda.device(self.device):
+            rc = _lib.check(_lib.lib().nxg_pagerank_adjoint(self._h, ctypes.byref(d),
+                                                            _stream_handle(), ctypes.byref(st)),
+                            "nxg_pagerank_adjoint", allow=(_lib.NXG_ENOTCONV,))
+        out = st.as_dict()
+        out["status"] = rc
+        return lam, gw, gt, out
+
+
+class WeightedPageRank(torch.autograd.Function):
+    """x* = WeightedPageRank.apply(w, t, dsss, damping, tol, max_iters).
+
+    Forward: stores w (input edge order) in the DSSS and iterates weighted
+    PageRank in FP64 to ||x^{k+1} - x^k||_1 <= tol. Only x* is saved. Backward:
+    the hand-written adjoint over the transposed sub-shards returns dL/dw (the
+    given weights, no renormalisation) and dL/dt. The DSSS must be built with
+    weights, transpose=True, keep_perm=True.
+    """
+
+    @staticmethod
+    def forward(ctx, w, t, dsss, damping=0.85, tol=1e-8, max_iters=100000):
+        dsss.set_weights(w)
+        x, st = dsss.pagerank(int(max_iters), damping=damping, dtype=torch.float64, tol=tol,
+                              teleport=t, weighted=True)
+        if st["status"] != _lib.NXG_OK:
+            raise RuntimeError("weighted PageRank did not reach tol=%g in %d iterations"
+                               % (tol, max_iters))
+        ctx.save_for_backward(x)
+        ctx.dsss = dsss
+        ctx.version = dsss.weights_version
+        ctx.damping = damping
+        ctx.adj_tol = min(tol, 1e-10)
+        ctx.max_iters = max_iters
+        ctx.w_dtype = w.dtype
+        ctx.t_dtype = t.dtype if t is not None else None
+        ctx.forward_stats = st
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        if ctx.dsss.weights_version != ctx.version:
+            raise RuntimeError("DSSS weights changed between forward and backward")
+        _, gw, gt, _ = ctx.dsss.pagerank_adjoint(x, gx, damping=ctx.damping, tol=ctx.adj_tol,
+                                                 max_iters=ctx.max_iters)
+        gt_out = gt.to(ctx.t_dtype) if ctx.t_dtype is not None else None
+        return gw.to(ctx.w_dtype), gt_out, None, None, None, None

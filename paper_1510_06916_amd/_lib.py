@@ -56,6 +56,13 @@ class RunStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AdjointDesc(ctypes.Structure):
+    _fields_ = [("damping", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("d_xstar", ctypes.c_void_p),
+                ("d_gx", ctypes.c_void_p), ("d_lambda", ctypes.c_void_p),
+                ("d_gw", ctypes.c_void_p), ("d_gt", ctypes.c_void_p)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                            ctypes.c_void_p)
@@ -74,6 +81,9 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "nxg_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunDesc), ctypes.c_void_p,
                                ctypes.POINTER(RunStats)]),
+    "nxg_dsss_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nxg_pagerank_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AdjointDesc),
+                                            ctypes.c_void_p, ctypes.POINTER(RunStats)]),
 }
 
 _lib = None

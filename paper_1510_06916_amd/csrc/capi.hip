@@ -171,4 +171,20 @@ nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_
     });
 }
 
+nxg_status nxg_dsss_set_weights(nxg_dsss* g, const float* d_weight, void* stream) {
+    return guarded([&]() {
+        if (!g || !d_weight) fail(NXG_EINVAL, "NULL argument");
+        dsss_set_weights(g, d_weight, (hipStream_t)stream);
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc* desc, void* stream,
+                                nxg_run_stats* stats) {
+    return guarded([&]() {
+        if (!g || !desc) fail(NXG_EINVAL, "NULL argument");
+        return pagerank_adjoint(g, *desc, (hipStream_t)stream, stats);
+    });
+}
+
 }  // extern "C"

@@ -42,7 +42,7 @@ struct Geo {
     void* partial;
     int32_t* tile_ctr;
     int32_t* all_ctr;
-    double* tile_s;      // [n_tiles * 2]
+    double* tile_s;      // [n_tiles * 3]
     int32_t* tile_flag;  // [n_tiles]
     // compacted active chunk lists (BFS/WCC), nullable
     const int64_t* clist;
@@ -79,15 +79,17 @@ struct ProgPR {
     __device__ acc_t identity() const { return (acc_t)0; }
     __device__ acc_t gather(uint32_t src, float) const { return (acc_t)cur[src]; }
     __device__ bool row_active(uint32_t) const { return true; }
-    // s0: dangling mass of x^{k+1}; s1: |x^{k+1} - x^k|
-    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
-                          double& s1, int&) const {
+    static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
+    // sv[0]: dangling mass of x^{k+1}; sv[1]: |x^{k+1} - x^k|_1; sv[2]: sum of x^{k+1}
+    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
+                          int&) const {
         double xo = dg ? (double)cur[v] * dg : (double)cur[v];
         double tv = tele ? (double)tele[v] : 1.0 / n;
         double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
         V xr = (V)xn;
-        s1 += fabs((double)xr - xo);
-        if (dg == 0) s0 += (double)xr;
+        sv[1] += fabs((double)xr - xo);
+        sv[2] += (double)xr;
+        if (dg == 0) sv[0] += (double)xr;
         nxt[v] = dg ? (V)((double)xr / dg) : xr;
         if (xout) xout[v] = xr;
     }
@@ -112,14 +114,16 @@ struct ProgPRW {
     __device__ acc_t identity() const { return (acc_t)0; }
     __device__ acc_t gather(uint32_t src, float we) const { return (acc_t)we * (acc_t)cur[src]; }
     __device__ bool row_active(uint32_t) const { return true; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double& s0,
-                          double& s1, int&) const {
+    static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
+                          int&) const {
         double xo = (double)cur[v];
         double tv = tele ? (double)tele[v] : 1.0 / n;
         double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
         V xr = (V)xn;
-        s1 += fabs((double)xr - xo);
-        if (dg == 0) s0 += (double)xr;
+        sv[1] += fabs((double)xr - xo);
+        sv[2] += (double)xr;
+        if (dg == 0) sv[0] += (double)xr;
         nxt[v] = xr;
         if (xout) xout[v] = xr;
     }
@@ -144,7 +148,8 @@ struct ProgBFS {
         return l == kInf ? kInf : l + 1;
     }
     __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double&, double&,
+    static __device__ bool converged(double, double, double) { return false; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
@@ -169,7 +174,8 @@ struct ProgWCC {
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
     __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double&, double&,
+    static __device__ bool converged(double, double, double) { return false; }
+    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
@@ -180,6 +186,43 @@ struct ProgWCC {
         }
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
+// Adjoint of weighted PageRank, iterated on the reversed graph: the gathered
+// array is lambda (indexed by the forward destination), the edge carries the
+// forward weight, and the tile owns forward sources u:
+//   lambda'_u = g_u + d * sum_{e: u->v} w_e lambda_v + d * [outdeg_u = 0] * S / n,
+// S = sum_v lambda_v of the previous iterate. sv[0] = sum of lambda' (next S),
+// sv[1] = |lambda' - lambda|_1, sv[2] = |lambda'|_1 (relative stopping test).
+struct ProgADJ {
+    using acc_t = double;
+    static constexpr bool kSum = true, kWeights = true, kActivity = false;
+    const double* cur;
+    double* nxt;
+    const double* gvec;
+    double* xout;
+    const float* w;
+    double d;
+    __device__ acc_t identity() const { return 0.0; }
+    __device__ acc_t gather(uint32_t src, float we) const { return (double)we * cur[src]; }
+    __device__ bool row_active(uint32_t) const { return true; }
+    static __device__ bool converged(double resid, double norm, double tol) {
+        return resid <= tol * norm;
+    }
+    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
+                          int&) const {
+        double lo = cur[v];
+        double ln = gvec[v] + d * acc + (dg == 0 ? d * scal / n : 0.0);
+        sv[0] += ln;
+        sv[1] += fabs(ln - lo);
+        sv[2] += fabs(ln);
+        nxt[v] = ln;
+        if (xout) xout[v] = ln;
+    }
+    __device__ void pass(int64_t v, int32_t) const {
+        nxt[v] = cur[v];
+        if (xout) xout[v] = cur[v];
+    }
 };
 
 __device__ inline void lds_combine(float* p, float v, bool) { atomicAdd(p, v); }
@@ -222,7 +265,7 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     using acc_t = typename Prog::acc_t;
     extern __shared__ __align__(16) unsigned char smem[];
     acc_t* acc = reinterpret_cast<acc_t*>(smem);
-    __shared__ double red[2][WG / 64];
+    __shared__ double red[3][WG / 64];
     __shared__ int sflag;
     __shared__ int slast;
 
@@ -407,26 +450,24 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
 
     // ---- apply ------------------------------------------------------------
     const double scal = ctl.stats[ctl.k * 4 + 0];
-    double s0 = 0.0, s1 = 0.0;
+    double sv[3] = {0.0, 0.0, 0.0};
     int flag = 0;
     for (int64_t x = threadIdx.x; x < len; x += WG)
-        prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, s0, s1, flag);
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if (lane == 0) {
-        red[0][wave] = s0;
-        red[1][wave] = s1;
+        prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, flag);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sv[q] = wave_sum(sv[q]);
+        if (lane == 0) red[q][wave] = sv[q];
     }
     if (flag) sflag = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int w = 0; w < WG / 64; ++w) {
-            a += red[0][w];
-            b += red[1][w];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double a = 0.0;
+            for (int w = 0; w < WG / 64; ++w) a += red[q][w];
+            g.tile_s[3 * tile + q] = a;
         }
-        g.tile_s[2 * tile + 0] = a;
-        g.tile_s[2 * tile + 1] = b;
         g.tile_flag[tile] = sflag;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         int old = __hip_atomic_fetch_add(g.all_ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -436,37 +477,35 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     if (!slast) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // ---- last tile: per-iteration scalars in tile order ---------------------
-    double a = 0.0, b = 0.0;
+    double tv[3] = {0.0, 0.0, 0.0};
     int f = 0;
     for (int x = threadIdx.x; x < g.n_tiles; x += WG) {
-        a += __builtin_nontemporal_load(&g.tile_s[2 * x + 0]);
-        b += __builtin_nontemporal_load(&g.tile_s[2 * x + 1]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) tv[q] += __builtin_nontemporal_load(&g.tile_s[3 * x + q]);
         f |= __builtin_nontemporal_load(&g.tile_flag[x]);
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-        red[0][wave] = a;
-        red[1][wave] = b;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        tv[q] = wave_sum(tv[q]);
+        if (lane == 0) red[q][wave] = tv[q];
     }
     if (f) sflag = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double ta = 0.0, tb = 0.0;
-        for (int w = 0; w < WG / 64; ++w) {
-            ta += red[0][w];
-            tb += red[1][w];
+        double t3[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            t3[q] = 0.0;
+            for (int w = 0; w < WG / 64; ++w) t3[q] += red[q][w];
         }
-        ctl.stats[(ctl.k + 1) * 4 + 0] = ta;
-        ctl.stats[ctl.k * 4 + 1] = tb;
+        ctl.stats[(ctl.k + 1) * 4 + 0] = t3[0];
+        ctl.stats[ctl.k * 4 + 1] = t3[1];
+        ctl.stats[ctl.k * 4 + 2] = t3[2];
         ctl.stats[ctl.k * 4 + 3] = sflag ? 1.0 : 0.0;
-        if (Prog::kSum) {
-            if (ctl.tol > 0.0 && tb <= ctl.tol) *ctl.done = 1;
-        }
+        if (ctl.tol > 0.0 && Prog::converged(t3[1], t3[2], ctl.tol)) *ctl.done = 1;
         *g.all_ctr = 0;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // Initialisation, activity and end-of-run kernels
@@ -599,6 +638,92 @@ __global__ __launch_bounds__(256) void k_bfs_final(int32_t n, const int32_t* __r
     }
     atomicMax(maxlev, mx);
     atomicAdd(reached, r);
+}
+
+// lambda^0 = g, and per-block partial sums of g (S^0).
+__global__ __launch_bounds__(256) void k_init_adj(int32_t n, const double* __restrict__ gx,
+                                                  double* __restrict__ cur,
+                                                  double* __restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        cur[v] = gx[v];
+        s += gx[v];
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// dL/dw_e = d * x*[src_e] * lambda[dst_e], written at the input position of
+// edge e (through the kept permutation). One wavefront per chunk; the source
+// interval of every word is recovered from the markers as in k_iterate.
+__global__ __launch_bounds__(256) void k_edge_grad(
+    const uint32_t* __restrict__ words, const int32_t* __restrict__ crow,
+    const int64_t* __restrict__ tchunk, int n_tiles, int64_t n_chunks, int C, int I, int L, int t,
+    int sshift, int dshift, const int32_t* __restrict__ perm, const double* __restrict__ xs,
+    const double* __restrict__ lam, double d, float* __restrict__ gw) {
+    const int lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t lmask = (1u << L) - 1u, tmask = (1u << t) - 1u;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += nw) {
+        int lo = 0, hi = n_tiles;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tchunk[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t tbase = (int64_t)lo << t;
+        uint32_t row = (uint32_t)crow[c];
+        const u32x4* wp = reinterpret_cast<const u32x4*>(words + c * (int64_t)C);
+        for (int s = 0; s < (C >> 8); ++s) {
+            const u32x4 w4 = wp[s * 64 + lane];
+            const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+            const uint64_t mm = __ballot(((w[0] | w[1] | w[2] | w[3]) >> 31) != 0);
+            uint32_t r = row;
+            if (mm) {
+                uint32_t last = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (w[k] & kMarker) last = w[k] & ~kMarker;
+                const uint64_t prev = mm & lt;
+                const uint32_t got = __shfl(last, prev ? 63 - __clzll(prev) : lane);
+                r = prev ? got : row;
+                row = __shfl(last, 63 - __clzll(mm));
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (w[k] & kMarker) {
+                    r = w[k] & ~kMarker;
+                    continue;
+                }
+                const int64_t pos = c * (int64_t)C + (int64_t)s * 256 + lane * 4 + k;
+                const int64_t src = (int64_t)r * I + ((w[k] >> sshift) & lmask);
+                const int64_t dst = tbase + ((w[k] >> dshift) & tmask);
+                gw[perm[pos]] = (float)(d * xs[src] * lam[dst]);
+            }
+        }
+    }
+}
+
+__global__ void k_scale_copy(const double* __restrict__ a, double f, double* __restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = f * a[i];
+}
+
+// Weights in stream order from weights in input order (words that hold an edge).
+__global__ void k_set_weights(const int32_t* __restrict__ perm, int64_t n_words,
+                              const float* __restrict__ win, float* __restrict__ wout) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e = perm[i];
+        wout[i] = e >= 0 ? win[e] : 0.0f;
+    }
 }
 
 template <typename V>
@@ -744,7 +869,7 @@ void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int m
     NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
     w.all_ctr.alloc(sizeof(int32_t), s);
     NXG_HIP(hipMemsetAsync(w.all_ctr.p, 0, sizeof(int32_t), s));
-    w.tile_s.alloc(sizeof(double) * 2 * L.n_tiles, s);
+    w.tile_s.alloc(sizeof(double) * 3 * L.n_tiles, s);
     w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
     w.stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
     NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * 4 * (size_t)(max_iters + 2), s));
@@ -979,7 +1104,118 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     return fixed ? NXG_OK : NXG_ENOTCONV;
 }
 
+nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st) {
+    if (!g->has_rev || !g->fwd.has_weight || !g->fwd.has_perm || !g->rev.has_weight)
+        fail(NXG_EINVAL, "the adjoint needs a build with weights, NXG_BUILD_TRANSPOSE and "
+                         "NXG_BUILD_KEEP_PERM");
+    if (!d.d_xstar || !d.d_gx) fail(NXG_EINVAL, "d_xstar / d_gx is NULL");
+    if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+    if (d.max_iters < 1) fail(NXG_EINVAL, "max_iters must be >= 1");
+    const Layout& R = g->rev;
+    const Layout& F = g->fwd;
+    if ((size_t)R.T * 8 > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "destination tile does not fit in LDS; rebuild with value_bytes = 8");
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = (int)std::max<int64_t>(16, R.n_chunks / std::max(1, 4 * cus));
+    Plan* p = get_plan(g, R, piece, false, s);
+    Workspace w;
+    const int max_iters = d.max_iters;
+    alloc_common(w, R, *p, 8, max_iters, s, false);
+    w.buf[0].alloc(sizeof(double) * R.n, s);
+    w.buf[1].alloc(sizeof(double) * R.n, s);
+    const int nb = grid_for(R.n, 256, 1024);
+    w.part.alloc(sizeof(double) * nb, s);
+    hipLaunchKernelGGL(k_init_adj, dim3(nb), dim3(256), 0, s, R.n, d.d_gx, w.buf[0].as<double>(),
+                       w.part.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
+                       w.stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(R, *p, w);
+    geo.deg = F.outdeg.as<int32_t>();  // dangling set of the forward graph
+    const size_t lds = (size_t)R.T * 8;
+    const int n_items = (int)p->h_items.size();
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    const double tol = d.tol > 0 ? d.tol : 0.0;
+    const int block = tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
+    int k = 0, done_h = 0;
+    while (k < max_iters) {
+        const int kend = std::min(max_iters, k + block);
+        for (; k < kend; ++k) {
+            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, tol};
+            ProgADJ pr{w.buf[k & 1].as<double>(), w.buf[(k + 1) & 1].as<double>(), d.d_gx, nullptr,
+                       R.weight.as<float>(), d.damping};
+            launch_iter<ProgADJ, 1024>(geo, ctl, pr, n_items, lds, s);
+        }
+        if (tol > 0 && k < max_iters) {
+            NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (done_h) break;
+        }
+    }
+    const double* lam = w.buf[k & 1].as<double>();
+    if (d.d_lambda)
+        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0, d.d_lambda,
+                           (int64_t)R.n);
+    if (d.d_gt)
+        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0 - d.damping,
+                           d.d_gt, (int64_t)R.n);
+    NXG_CHECK_LAUNCH();
+    if (d.d_gw && F.n_chunks > 0) {
+        hipLaunchKernelGGL(k_edge_grad, dim3(grid_for(F.n_chunks * 64, 256, 16384)), dim3(256), 0, s,
+                           F.words.as<uint32_t>(), F.chunk_row.as<int32_t>(),
+                           F.tile_chunk.as<int64_t>(), F.n_tiles, F.n_chunks, F.C, F.I, F.L, F.t,
+                           F.order == NXG_ORDER_SRC ? F.t : 0, F.order == NXG_ORDER_SRC ? 0 : F.L,
+                           F.perm.as<int32_t>(), d.d_xstar, lam, d.damping, d.d_gw);
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipEventRecord(e1, s));
+    std::vector<double> hs(4 * (size_t)(max_iters + 2));
+    NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    int iters = k, conv_at = -1;
+    for (int i = 0; i < k; ++i)
+        if (tol > 0 && hs[4 * i + 1] <= tol * hs[4 * i + 2]) {
+            conv_at = i;
+            break;
+        }
+    if (conv_at >= 0) iters = conv_at + 1;
+    float ms = 0.f;
+    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = iters;
+        st->converged = conv_at >= 0;
+        st->residual = iters > 0 ? hs[4 * (iters - 1) + 1] / std::max(hs[4 * (iters - 1) + 2], 1e-300) : 0.0;
+        st->device_ms = ms;
+    }
+    return (tol > 0 && conv_at < 0) ? NXG_ENOTCONV : NXG_OK;
+}
+
+void set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) {
+    for (Layout* L : {&g->fwd, &g->rev}) {
+        if (L == &g->rev && !g->has_rev) continue;
+        if (!L->has_weight || !L->has_perm)
+            fail(NXG_EINVAL, "setting weights needs a build with weights and NXG_BUILD_KEEP_PERM");
+        hipLaunchKernelGGL(k_set_weights, dim3(grid_for(L->n_words)), dim3(256), 0, s,
+                           L->perm.as<int32_t>(), L->n_words, d_w, L->weight.as<float>());
+        NXG_CHECK_LAUNCH();
+    }
+}
+
 }  // namespace
+
+nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st) {
+    return run_adjoint(g, d, s, st);
+}
+
+void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) { set_weights(g, d_w, s); }
 
 int lds_budget_bytes(int device) {
     int v = 0;

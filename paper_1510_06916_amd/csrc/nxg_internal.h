@@ -155,5 +155,7 @@ void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t*
                    int32_t* d_perm, hipStream_t s);
 // runtime entry (iterate.hip)
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
+nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
+void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s);
 int lds_budget_bytes(int device);
 }  // namespace nxg
