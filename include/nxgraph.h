@@ -159,7 +159,9 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
 typedef struct nxg_run_desc {
     nxg_program program;
     nxg_dtype dtype;        /* F32 or F64 for PageRank, I32 for BFS/WCC */
-    int32_t batch;          /* B >= 1 value columns (PageRank only; B > 1 = batched PPR) */
+    int32_t batch;          /* B in [1, 64] value columns. B > 1 (or d_seeds set) runs batched
+                               PageRank, FP32, values [n, B] row-major; the build needs
+                               value_bytes >= 8 * B (FP64 sums per column in LDS) */
     double damping;         /* d in [0, 1) */
     int32_t max_iters;      /* upper bound on iterations (>= 0) */
     double tol;             /* PageRank: stop when ||x^{k+1}-x^k||_1 <= tol (per column);
@@ -169,6 +171,8 @@ typedef struct nxg_run_desc {
     const int32_t* roots;   /* BFS: host [B] root ids */
     void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC label) */
     uint32_t flags;         /* NXG_RUN_* */
+    const int32_t* d_seeds; /* batched personalised PageRank: device [B] seed vertices;
+                               column b teleports to seeds[b] (one-hot t). NULL = uniform */
 } nxg_run_desc;
 
 typedef struct nxg_run_stats {

@@ -180,6 +180,21 @@ class DSSS:
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 
+    def ppr(self, seeds, iters, damping=0.85, tol=0.0, out=None):
+        """Batched personalised PageRank: column b teleports to seeds[b]; returns
+        x [n, B] FP32 (B = len(seeds) <= 64). The graph must be built with
+        value_bytes >= 8 * B."""
+        seeds = torch.as_tensor(seeds, dtype=torch.int32).to(self.device).contiguous()
+        B = seeds.numel()
+        x = out if out is not None else torch.empty((self.n, B), dtype=torch.float32,
+                                                    device=self.device)
+        d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=B,
+                         damping=float(damping), max_iters=int(iters), tol=float(tol),
+                         d_teleport=None, roots=None, d_values=x.data_ptr(), flags=0,
+                         d_seeds=seeds.data_ptr())
+        st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
+        return x, st
+
     def bfs(self, root, max_rounds=None):
         n = self.n
         lev = torch.empty(n, dtype=torch.int32, device=self.device)

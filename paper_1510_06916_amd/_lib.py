@@ -43,7 +43,7 @@ class RunDesc(ctypes.Structure):
                 ("damping", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("d_teleport", ctypes.c_void_p),
                 ("roots", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("d_seeds", ctypes.c_void_p)]
 
 
 class RunStats(ctypes.Structure):

@@ -716,6 +716,229 @@ __global__ void k_scale_copy(const double* __restrict__ a, double f, double* __r
         b[i] = f * a[i];
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched personalised PageRank: B value columns per vertex, stored [n, B]
+// row-major. A wavefront processes one edge per step with lane b handling
+// column b, so the source row is one coalesced load; sums along a run of equal
+// destination stay in registers and reach the LDS accumulators [T, B] (FP64)
+// once per run. Column b teleports to seeds[b] (one-hot), or uniformly when no
+// seeds are given; the dangling mass and the residual are kept per column.
+// ---------------------------------------------------------------------------
+struct BCtl {
+    double* stats;   // [(max_iters + 2) * 3 * B]: per iteration, per column: delta, resid, sum
+    int32_t* done;
+    int32_t k;
+    double tol;
+};
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const float* __restrict__ cur,
+                                                        float* __restrict__ nxt, float* __restrict__ xout,
+                                                        const int32_t* __restrict__ seeds, int B,
+                                                        double d, double* __restrict__ tile_sb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* acc = reinterpret_cast<double*>(smem);  // [T][B]
+    __shared__ int slast;
+    const Item it = g.items[blockIdx.x];
+    const int tile = it.tile;
+    const int64_t base = (int64_t)tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const bool col = lane < B;
+    if (*ctl.done) {  // converged earlier: carry the vectors over
+        if (it.piece == 0)
+            for (int64_t v = wave; v < len; v += WG / 64)
+                if (col) {
+                    const int64_t o = (base + v) * B + lane;
+                    nxt[o] = cur[o];
+                    if (xout) {
+                        const int32_t dg = g.deg[base + v];
+                        xout[o] = dg ? (float)((double)cur[o] * dg) : cur[o];
+                    }
+                }
+        return;
+    }
+    for (int64_t x = threadIdx.x; x < len * B; x += WG) acc[x] = 0.0;
+    __syncthreads();
+    const uint32_t lmask = (1u << g.L) - 1u, tmask = (1u << g.t) - 1u;
+    constexpr int kG = 16;  // row gathers in flight per lane
+    for (int64_t c = it.c0 + wave; c < it.c1; c += WG / 64) {
+        uint32_t row = (uint32_t)g.chunk_row[c];
+        const uint32_t* wp = g.words + c * (int64_t)g.C;
+        for (int s0 = 0; s0 < g.C; s0 += 64) {
+            const uint32_t wl = wp[s0 + lane];  // 64 words, one per lane
+            // source interval in effect at each lane's word
+            const uint64_t mm = __ballot((wl >> 31) != 0);
+            uint32_t r = row;
+            if (mm) {
+                const uint64_t upto = mm & (lt | (1ull << lane));
+                const uint32_t got = __shfl(wl & ~kMarker, upto ? 63 - __clzll(upto) : lane);
+                r = upto ? got : row;
+                row = __shfl(wl & ~kMarker, 63 - __clzll(mm));
+            }
+            const bool edge = (wl >> 31) == 0;
+            const uint32_t src_l = r * (uint32_t)g.I + ((wl >> g.sshift) & lmask);
+            const uint32_t dst_l = edge ? ((wl >> g.dshift) & tmask) : 0xFFFFFFFFu;
+            uint32_t pd = 0xFFFFFFFFu;
+            double pv = 0.0;
+            for (int j0 = 0; j0 < 64; j0 += kG) {
+                float v[kG];
+                uint32_t dj[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    dj[q] = __shfl(dst_l, j0 + q);
+                    const uint32_t sj = __shfl(src_l, j0 + q);
+                    v[q] = (dj[q] != 0xFFFFFFFFu && col) ? cur[(int64_t)sj * B + lane] : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    if (dj[q] == 0xFFFFFFFFu) continue;
+                    if (dj[q] != pd) {
+                        if (pd != 0xFFFFFFFFu && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
+                        pd = dj[q];
+                        pv = 0.0;
+                    }
+                    pv += (double)v[q];
+                }
+            }
+            if (pd != 0xFFFFFFFFu && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
+        }
+    }
+    __syncthreads();
+    if (it.npieces > 1) {
+        double* part = reinterpret_cast<double*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T * B;
+        for (int64_t x = threadIdx.x; x < len * B; x += WG) part[x] = acc[x];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int old = __hip_atomic_fetch_add(&g.tile_ctr[tile], 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            slast = (old == it.npieces - 1);
+        }
+        __syncthreads();
+        if (!slast) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const double* p0 = reinterpret_cast<const double*>(g.partial) + (int64_t)it.slot * g.T * B;
+        for (int64_t x = threadIdx.x; x < len * B; x += WG) {
+            double sum = 0.0;
+            for (int p = 0; p < it.npieces; ++p)
+                sum += __builtin_nontemporal_load(p0 + (int64_t)p * g.T * B + x);
+            acc[x] = sum;
+        }
+        if (threadIdx.x == 0) g.tile_ctr[tile] = 0;
+        __syncthreads();
+    }
+    // apply, lane = column; per-column partial sums reduced across waves in LDS
+    const double* sc = ctl.stats + (int64_t)ctl.k * 3 * B;
+    const double delta = col ? sc[lane] : 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int32_t seed = (col && seeds) ? seeds[lane] : -1;
+    for (int64_t v = wave; v < len; v += WG / 64) {
+        if (!col) continue;
+        const int64_t gv = base + v;
+        const int64_t o = gv * B + lane;
+        const int32_t dg = g.deg[gv];
+        const double xo = dg ? (double)cur[o] * dg : (double)cur[o];
+        const double tv = seeds ? (gv == seed ? 1.0 : 0.0) : 1.0 / g.n;
+        const double xn = d * (acc[v * B + lane] + delta / g.n) + (1.0 - d) * tv;
+        const float xr = (float)xn;
+        s1 += fabs((double)xr - xo);
+        s2 += (double)xr;
+        if (dg == 0) s0 += (double)xr;
+        nxt[o] = dg ? (float)((double)xr / dg) : xr;
+        if (xout) xout[o] = xr;
+    }
+    __syncthreads();  // acc is reused as the reduction buffer
+    double* red = acc;
+    red[(0 * (WG / 64) + wave) * 64 + lane] = s0;
+    red[(1 * (WG / 64) + wave) * 64 + lane] = s1;
+    red[(2 * (WG / 64) + wave) * 64 + lane] = s2;
+    __syncthreads();
+    if (threadIdx.x < 3 * 64) {
+        const int q = threadIdx.x >> 6, b = threadIdx.x & 63;
+        double a = 0.0;
+        for (int w = 0; w < WG / 64; ++w) a += red[(q * (WG / 64) + w) * 64 + b];
+        if (b < B) tile_sb[((int64_t)tile * 3 + q) * B + b] = a;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int old = __hip_atomic_fetch_add(g.all_ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        slast = (old == g.n_tiles - 1);
+    }
+    __syncthreads();
+    if (!slast) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // last tile: per-column scalars; wave w sums tiles w, w+16, ... (lane = column,
+    // coalesced), then the 16 wave partials are summed in wave order
+    {
+        double t3[3] = {0.0, 0.0, 0.0};
+        if (col)
+            for (int64_t x = wave; x < g.n_tiles; x += WG / 64) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    t3[q] += __builtin_nontemporal_load(&tile_sb[((int64_t)x * 3 + q) * B + lane]);
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) red[(q * (WG / 64) + wave) * 64 + lane] = t3[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 * 64) {
+        const int q = threadIdx.x >> 6, b = threadIdx.x & 63;
+        if (b < B) {
+            double a = 0.0;
+            for (int w = 0; w < WG / 64; ++w) a += red[(q * (WG / 64) + w) * 64 + b];
+            double* so = ctl.stats + (int64_t)(q == 0 ? ctl.k + 1 : ctl.k) * 3 * B;
+            so[q * B + b] = a;  // q=0: delta entering k+1 at [k+1][0][b]; q=1,2: [k][q][b]
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ctl.tol > 0.0) {
+            double mx = 0.0;
+            for (int b = 0; b < B; ++b) mx = fmax(mx, ctl.stats[(int64_t)ctl.k * 3 * B + B + b]);
+            if (mx <= ctl.tol) *ctl.done = 1;
+        }
+        *g.all_ctr = 0;
+    }
+}
+
+// x^0 = t per column (one-hot at seeds[b], or uniform); per-block per-column
+// dangling partial sums.
+__global__ __launch_bounds__(256) void k_init_batched(int32_t n, int B, const int32_t* __restrict__ deg,
+                                                      const int32_t* __restrict__ seeds,
+                                                      float* __restrict__ cur,
+                                                      double* __restrict__ part) {
+    // cur[v*B + b]
+    const int64_t total = (int64_t)n * B;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t v = i / B;
+        const int b = (int)(i - v * B);
+        const double x = seeds ? (v == seeds[b] ? 1.0 : 0.0) : 1.0 / n;
+        const int32_t dg = deg[v];
+        cur[i] = dg ? (float)(x / dg) : (float)x;
+    }
+    (void)part;
+}
+
+// delta^0[b] = sum over dangling v of x^0[v][b]: one thread per column.
+__global__ void k_init_batched_delta(int32_t n, int B, const int32_t* __restrict__ deg,
+                                     const int32_t* __restrict__ seeds, double* __restrict__ stats) {
+    const int b = threadIdx.x;
+    if (b >= B) return;
+    if (seeds) {
+        stats[b] = deg[seeds[b]] == 0 ? 1.0 : 0.0;
+    } else {
+        // uniform: (number of dangling vertices) / n, counted by this thread
+        int64_t cnt = 0;
+        for (int64_t v = 0; v < n; ++v) cnt += deg[v] == 0;
+        stats[b] = (double)cnt / n;
+    }
+}
+
 // Weights in stream order from weights in input order (words that hold an edge).
 __global__ void k_set_weights(const int32_t* __restrict__ perm, int64_t n_words,
                               const float* __restrict__ win, float* __restrict__ wout) {
@@ -1104,6 +1327,117 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     return fixed ? NXG_OK : NXG_ENOTCONV;
 }
 
+
+nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const Layout& L = g->fwd;
+    const int B = d.batch;
+    if (B < 1 || B > 64) fail(NXG_EINVAL, "batch must be in [1, 64]");
+    if (d.program != NXG_PAGERANK || d.dtype != NXG_F32)
+        fail(NXG_EUNSUPPORTED, "batched runs support plain PageRank in FP32");
+    if (d.d_teleport) fail(NXG_EUNSUPPORTED, "batched runs take seed vertices (d_seeds), not a dense teleport");
+    if (d.flags & NXG_RUN_WARM_START) fail(NXG_EUNSUPPORTED, "batched runs start from the teleport vector");
+    const size_t lds = (size_t)L.T * B * 8;
+    if (lds > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "tile * batch * 8 bytes exceeds LDS; build with value_bytes = 8 * batch");
+    if ((size_t)(3 * 16) * 64 * 8 > lds) fail(NXG_EINVAL, "tile too small for the batched reduction");
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    Plan* p = get_plan(g, L, piece, false, s);
+    Workspace w;
+    const int max_iters = d.max_iters;
+    // partial slots hold T*B doubles each
+    const int64_t hub = (int64_t)std::max(p->n_slots, 1) * L.T * B;
+    w.partial.alloc(sizeof(double) * hub, s);
+    w.tile_ctr.alloc(sizeof(int32_t) * L.n_tiles, s);
+    NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
+    w.all_ctr.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(w.all_ctr.p, 0, sizeof(int32_t), s));
+    w.tile_s.alloc(sizeof(double) * 3 * B * (size_t)L.n_tiles, s);
+    w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+    const size_t nstat = (size_t)(max_iters + 2) * 3 * B;
+    w.stats.alloc(sizeof(double) * nstat, s);
+    NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * nstat, s));
+    w.done.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
+    w.buf[0].alloc(sizeof(float) * (size_t)L.n * B, s);
+    w.buf[1].alloc(sizeof(float) * (size_t)L.n * B, s);
+    const int32_t* seeds = d.d_seeds;
+    hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, s,
+                       L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, s, L.n, B, L.outdeg.as<int32_t>(),
+                       seeds, w.stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(L, *p, w);
+    const int n_items = (int)p->h_items.size();
+    static size_t attr = 0;
+    if (lds > attr) {
+        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate_batched<1024>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = lds;
+    }
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    const int block = d.tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
+    int k = 0, done_h = 0;
+    while (k < max_iters) {
+        const int kend = std::min(max_iters, k + block);
+        for (; k < kend; ++k) {
+            BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
+            float* xout = (k == max_iters - 1) ? (float*)d.d_values : nullptr;
+            hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl,
+                               w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout, seeds,
+                               B, d.damping, w.tile_s.as<double>());
+            NXG_CHECK_LAUNCH();
+        }
+        if (d.tol > 0 && k < max_iters) {
+            NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (done_h) break;
+        }
+    }
+    if (k < max_iters || max_iters == 0) {
+        // emit x from the newest vector through the carry-over path
+        NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
+        BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
+        hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl,
+                           w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(),
+                           (float*)d.d_values, seeds, B, d.damping, w.tile_s.as<double>());
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipEventRecord(e1, s));
+    std::vector<double> hs(nstat);
+    NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    int iters = k, conv_at = -1;
+    double resid = 0.0;
+    for (int i = 0; i < k; ++i) {
+        double mx = 0.0;
+        for (int b = 0; b < B; ++b) mx = std::max(mx, hs[(size_t)i * 3 * B + B + b]);
+        resid = mx;
+        if (d.tol > 0 && mx <= d.tol) {
+            conv_at = i;
+            break;
+        }
+    }
+    if (conv_at >= 0) iters = conv_at + 1;
+    float ms = 0.f;
+    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = iters;
+        st->converged = conv_at >= 0;
+        st->residual = resid;
+        st->device_ms = ms;
+    }
+    return (d.tol > 0 && conv_at < 0) ? NXG_ENOTCONV : NXG_OK;
+}
+
 nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (!g->has_rev || !g->fwd.has_weight || !g->fwd.has_perm || !g->rev.has_weight)
         fail(NXG_EINVAL, "the adjoint needs a build with weights, NXG_BUILD_TRANSPOSE and "
@@ -1228,8 +1562,12 @@ int lds_budget_bytes(int device) {
 
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
-    if (d.batch != 1 && d.batch != 0) fail(NXG_EUNSUPPORTED, "batch > 1 is not supported by nxg_run yet");
     if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    if (d.batch > 1 || d.d_seeds) {
+        if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+        return run_batched(g, d, s, st);
+    }
+    if (d.batch != 1 && d.batch != 0) fail(NXG_EINVAL, "batch must be >= 1");
     switch (d.program) {
         case NXG_PAGERANK:
         case NXG_PAGERANK_WEIGHTED:
