@@ -155,6 +155,7 @@ typedef enum nxg_program {
 typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
 
 #define NXG_RUN_WARM_START 0x1u /* d_values holds x^0 on entry (PageRank) */
+#define NXG_RUN_PERSISTENT 0x2u /* nxg_multi_run: single persistent launch (switched off) */
 
 typedef struct nxg_run_desc {
     nxg_program program;
@@ -190,6 +191,30 @@ typedef struct nxg_run_stats {
  * stream and fills *stats. Returns NXG_ENOTCONV when tol > 0 was not reached
  * (values are still written). */
 nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
+
+/* ------------------------------------------------------------------------- */
+/* Many graphs, one persistent launch                                         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct nxg_multi nxg_multi; /* opaque set of independent graphs */
+
+/* Builds count independent graphs (descs[i] as for nxg_dsss_build). On failure
+ * nothing is kept and *out is NULL. Synchronises the stream. */
+nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* stream,
+                           nxg_multi** out);
+
+/* Runs desc->max_iters synchronous PageRank iterations (FP32 values, uniform
+ * teleport, x^0 = 1/n, no tolerance stop) on every graph together: each
+ * iteration is ONE launch whose workgroups are the tile pieces of all graphs,
+ * so small graphs fill the GPU together instead of one after another. d_values
+ * is a host array of count device pointers, graph i's result [n_i] FP32.
+ * NXG_RUN_PERSISTENT (one launch for all iterations, workgroups waiting on
+ * per-graph iteration counters) returns NXG_EUNSUPPORTED: that variant did not
+ * complete on MI355X and is switched off. Synchronises the stream. */
+nxg_status nxg_multi_run(nxg_multi* mg, const nxg_run_desc* desc, void* const* d_values,
+                         void* stream, nxg_run_stats* stats);
+
+nxg_status nxg_multi_destroy(nxg_multi* mg); /* NULL accepted */
 
 /* ------------------------------------------------------------------------- */
 /* Weighted PageRank: new weights and the adjoint (gradient) pass             */

@@ -15,7 +15,8 @@ import torch
 from . import _lib
 from ._lib import NxgError  # noqa: F401
 
-__all__ = ["DSSS", "NxgError", "WeightedPageRank", "abi_version", "install_torch_allocator"]
+__all__ = ["DSSS", "MultiDSSS", "NxgError", "WeightedPageRank", "abi_version",
+           "install_torch_allocator"]
 
 _alloc_refs = None
 
@@ -283,3 +284,58 @@ class WeightedPageRank(torch.autograd.Function):
                                                  max_iters=ctx.max_iters)
         gt_out = gt.to(ctx.t_dtype) if ctx.t_dtype is not None else None
         return gw.to(ctx.w_dtype), gt_out, None, None, None, None
+
+
+class MultiDSSS:
+    """Many independent graphs iterated together in one persistent launch."""
+
+    def __init__(self, handle, device, sizes):
+        self._h = handle
+        self.device = device
+        self.sizes = sizes  # vertex counts
+
+    @classmethod
+    def build(cls, graphs, interval=0, tile=0, chunk=0, stream=None):
+        """graphs: list of (src, dst, n) with int32 device tensors."""
+        install_torch_allocator()
+        keep = []
+        descs = (_lib.BuildDesc * len(graphs))()
+        for i, (src, dst, n) in enumerate(graphs):
+            src = _dev_i32(src, "src")
+            dst = _dev_i32(dst, "dst")
+            keep += [src, dst]
+            descs[i] = _lib.BuildDesc(n=int(n), m=src.numel(),
+                                      d_src=src.data_ptr() if src.numel() else None,
+                                      d_dst=dst.data_ptr() if dst.numel() else None,
+                                      d_weight=None, interval=int(interval), tile=int(tile),
+                                      chunk=int(chunk), value_bytes=0, flags=0, order=0)
+        h = ctypes.c_void_p()
+        dev = graphs[0][0].device
+        with torch.cuda.device(dev):
+            _lib.check(_lib.lib().nxg_multi_build(len(graphs), descs, _stream_handle(stream),
+                                                  ctypes.byref(h)), "nxg_multi_build")
+        return cls(h, dev, [int(g[2]) for g in graphs])
+
+    def close(self):
+        if self._h:
+            _lib.lib().nxg_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pagerank(self, iters, damping=0.85, persistent=False):
+        outs = [torch.empty(n, dtype=torch.float32, device=self.device) for n in self.sizes]
+        ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=1,
+                         damping=float(damping), max_iters=int(iters), tol=0.0, d_teleport=None,
+                         roots=None, d_values=None,
+                         flags=_lib.NXG_RUN_PERSISTENT if persistent else 0, d_seeds=None)
+        st = _lib.RunStats()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().nxg_multi_run(self._h, ctypes.byref(d), ptrs, _stream_handle(),
+                                                ctypes.byref(st)), "nxg_multi_run")
+        return outs, st.as_dict()

@@ -17,6 +17,7 @@ NXG_BUILD_DEDUP = 0x8
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
 NXG_RUN_WARM_START = 0x1
+NXG_RUN_PERSISTENT = 0x2
 NXG_ORDER_DST, NXG_ORDER_SRC = 0, 1
 
 
@@ -82,6 +83,12 @@ SIGNATURES = {
     "nxg_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunDesc), ctypes.c_void_p,
                                ctypes.POINTER(RunStats)]),
     "nxg_dsss_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nxg_multi_build": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(BuildDesc), ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "nxg_multi_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunDesc),
+                                     ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                     ctypes.POINTER(RunStats)]),
+    "nxg_multi_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "nxg_pagerank_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AdjointDesc),
                                             ctypes.c_void_p, ctypes.POINTER(RunStats)]),
 }

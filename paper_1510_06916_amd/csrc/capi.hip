@@ -78,10 +78,51 @@ const char* nxg_last_error(void) { return g_last_error.c_str(); }
 
 int nxg_abi_version(void) { return NXG_ABI_VERSION; }
 
+static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream);
+
 nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** out) {
     return guarded([&]() {
         if (!out) fail(NXG_EINVAL, "out is NULL");
         *out = nullptr;
+        *out = build_one(desc, stream);
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* stream, nxg_multi** out) {
+    return guarded([&]() {
+        if (!out) fail(NXG_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (count < 1 || !descs) fail(NXG_EINVAL, "count must be >= 1 and descs non-NULL");
+        nxg_multi* mg = new nxg_multi();
+        try {
+            for (int32_t i = 0; i < count; ++i) mg->graphs.push_back(build_one(&descs[i], stream));
+        } catch (...) {
+            delete mg;
+            throw;
+        }
+        *out = mg;
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_multi_run(nxg_multi* mg, const nxg_run_desc* desc, void* const* d_values,
+                         void* stream, nxg_run_stats* stats) {
+    return guarded([&]() {
+        if (!mg || !desc) fail(NXG_EINVAL, "NULL argument");
+        return multi_run(mg, *desc, d_values, (hipStream_t)stream, stats);
+    });
+}
+
+nxg_status nxg_multi_destroy(nxg_multi* mg) {
+    return guarded([&]() {
+        delete mg;
+        return NXG_OK;
+    });
+}
+
+static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
+    {
         if (!desc) fail(NXG_EINVAL, "desc is NULL");
         const nxg_build_desc& d = *desc;
         if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
@@ -111,9 +152,8 @@ nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** o
             delete g;
             throw;
         }
-        *out = g;
-        return NXG_OK;
-    });
+        return g;
+    }
 }
 
 nxg_status nxg_dsss_destroy(nxg_dsss* g) {

@@ -260,16 +260,20 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // The edge kernel
 // ---------------------------------------------------------------------------
+// Processes one work item (a piece of a destination tile) of one iteration.
+// Returns 1 in the workgroup that applied the last tile of the iteration (it
+// has then reduced the per-iteration scalars), 0 otherwise. Every thread of
+// the workgroup returns the same value.
 template <class Prog, int WG>
-__global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
+__device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, const Item& it,
+                            unsigned char* smem) {
     using acc_t = typename Prog::acc_t;
-    extern __shared__ __align__(16) unsigned char smem[];
     acc_t* acc = reinterpret_cast<acc_t*>(smem);
     __shared__ double red[3][WG / 64];
     __shared__ int sflag;
     __shared__ int slast;
+    __syncthreads();  // shared state of a previous item in this workgroup is dead
 
-    const Item it = g.items[blockIdx.x];
     const int tile = it.tile;
     const int64_t base = (int64_t)tile << g.t;
     int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     if (*ctl.done) {
         if (it.piece == 0)
             for (int64_t x = threadIdx.x; x < len; x += WG) prog.pass(base + x, g.deg[base + x]);
-        return;
+        return 0;
     }
 
     for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     int64_t c_lo = it.c0, c_hi = it.c1;
     const int64_t* list = nullptr;
     if (g.clist) {
-        const int64_t lbeg = g.items[blockIdx.x].c0;  // tile's first chunk = list origin
+        const int64_t lbeg = it.c0;  // tile's first chunk = list origin
         const int64_t cnt = g.ccount[tile];
         list = g.clist + lbeg;
         c_lo = cnt * it.piece / it.npieces;
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
             slast = (old == it.npieces - 1);
         }
         __syncthreads();
-        if (!slast) return;
+        if (!slast) return 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         // eight slots per pass so the loads of a thread are independent
         const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
@@ -474,7 +478,7 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
         slast = (old == g.n_tiles - 1);
     }
     __syncthreads();
-    if (!slast) return;
+    if (!slast) return 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // ---- last tile: per-iteration scalars in tile order ---------------------
     double tv[3] = {0.0, 0.0, 0.0};
@@ -505,6 +509,54 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
         if (ctl.tol > 0.0 && Prog::converged(t3[1], t3[2], ctl.tol)) *ctl.done = 1;
         *g.all_ctr = 0;
     }
+    return 1;
+}
+
+template <class Prog, int WG>
+__global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    iterate_item<Prog, WG>(g, ctl, prog, g.items[blockIdx.x], smem);
+}
+
+// ---------------------------------------------------------------------------
+// Many graphs per launch: one launch per iteration covers the work items (tile
+// pieces) of every graph; workgroup w finds its graph by a search over the
+// per-graph item prefix. Iterations are ordered by the stream, so no
+// workgroup ever waits for another; each graph's last tile reduces that
+// graph's scalars exactly as in a single-graph launch.
+// ---------------------------------------------------------------------------
+struct MultiGraph {
+    Geo geo;
+    double* stats;     // [4 * (iters + 2)]
+    float* buf0;
+    float* buf1;
+    float* xout;       // [n] result
+    int32_t* done0;    // a zero word (no tolerance stop in this mode)
+    int32_t item_base; // first item of this graph in the global item array
+    int32_t n_items;
+};
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict__ graphs, int G,
+                                                   const int32_t* __restrict__ item_prefix,
+                                                   const Item* __restrict__ items, int k, int iters,
+                                                   double damping) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int r = blockIdx.x;
+    int lo = 0, hi = G;  // graph: last index with item_prefix[gi] <= r
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (item_prefix[mid] <= r)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const MultiGraph& mg = graphs[lo];
+    Ctl ctl{mg.stats, mg.done0, k, 0.0};
+    ProgPR<float> prog{(k & 1) ? mg.buf1 : mg.buf0, (k & 1) ? mg.buf0 : mg.buf1, nullptr,
+                       k == iters - 1 ? mg.xout : nullptr, damping};
+    iterate_item<ProgPR<float>, WG>(mg.geo, ctl, prog, items[mg.item_base + (r - item_prefix[lo])],
+                                    smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1438,6 +1490,117 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     return (d.tol > 0 && conv_at < 0) ? NXG_ENOTCONV : NXG_OK;
 }
 
+
+nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values, hipStream_t s,
+                     nxg_run_stats* st) {
+    if (d.program != NXG_PAGERANK || d.dtype != NXG_F32 || (d.batch != 1 && d.batch != 0))
+        fail(NXG_EUNSUPPORTED, "the multi-graph launch runs plain FP32 PageRank");
+    if (d.tol > 0) fail(NXG_EUNSUPPORTED, "the multi-graph launch runs a fixed number of iterations");
+    if (d.flags & NXG_RUN_PERSISTENT)
+        fail(NXG_EUNSUPPORTED, "the single persistent launch over all iterations is disabled: its "
+                               "test did not finish on MI355X and the cause is not known");
+    if (d.d_teleport || d.d_seeds || (d.flags & NXG_RUN_WARM_START))
+        fail(NXG_EUNSUPPORTED, "the multi-graph launch uses the uniform teleport from x^0 = 1/n");
+    if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+    if (!d_values) fail(NXG_EINVAL, "d_values is NULL");
+    const int G = (int)mg->graphs.size();
+    const int iters = d.max_iters;
+    if (iters < 1) fail(NXG_EINVAL, "max_iters must be >= 1");
+    for (int i = 0; i < G; ++i)
+        if (!d_values[i]) fail(NXG_EINVAL, "d_values[" + std::to_string(i) + "] is NULL");
+    const int device = mg->graphs[0]->device;
+    const int cus = num_cus(device);
+    int64_t chunks = 0;
+    int maxT = 1;
+    for (nxg_dsss* g : mg->graphs) {
+        chunks += g->fwd.n_chunks;
+        maxT = std::max(maxT, g->fwd.T);
+    }
+    const size_t lds = (size_t)maxT * 8;
+    if (lds > (size_t)lds_budget_bytes(device)) fail(NXG_EINVAL, "a tile does not fit in LDS");
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = (int)std::max<int64_t>(16, chunks / std::max(1, 4 * cus));
+    // per-graph plans, workspaces and descriptors
+    std::vector<Item> all_items;
+    std::vector<int32_t> prefix(1, 0);
+    std::vector<MultiGraph> hdesc(G);
+    std::vector<Workspace> ws(G);
+    const int nbp = 64;
+    DevBuf parts;
+    parts.alloc(sizeof(double) * nbp * G, s);
+    for (int i = 0; i < G; ++i) {
+        nxg_dsss* g = mg->graphs[i];
+        const Layout& L = g->fwd;
+        Plan* p = get_plan(g, L, piece, false, s);
+        Workspace& w = ws[i];
+        alloc_common(w, L, *p, 8, iters, s, false);
+        w.buf[0].alloc(sizeof(float) * L.n, s);
+        w.buf[1].alloc(sizeof(float) * L.n, s);
+        hipLaunchKernelGGL(k_init_pr<float>, dim3(nbp), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
+                           (const float*)nullptr, (const float*)nullptr, 1, w.buf[0].as<float>(),
+                           parts.as<double>() + (size_t)nbp * i);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, parts.as<double>() + (size_t)nbp * i,
+                           nbp, w.stats.as<double>());
+        NXG_CHECK_LAUNCH();
+        MultiGraph& m = hdesc[i];
+        m.geo = make_geo(L, *p, w);
+        m.stats = w.stats.as<double>();
+        m.buf0 = w.buf[0].as<float>();
+        m.buf1 = w.buf[1].as<float>();
+        m.xout = (float*)d_values[i];
+        m.done0 = w.done.as<int32_t>();
+        m.item_base = (int32_t)all_items.size();
+        m.n_items = (int32_t)p->h_items.size();
+        all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
+        prefix.push_back((int32_t)all_items.size());
+    }
+    DevBuf ditems, dprefix, ddesc;
+    ditems.alloc(sizeof(Item) * all_items.size(), s);
+    dprefix.alloc(sizeof(int32_t) * prefix.size(), s);
+    ddesc.alloc(sizeof(MultiGraph) * G, s);
+    NXG_HIP(hipMemcpyAsync(ditems.p, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice, s));
+    NXG_HIP(hipMemcpyAsync(dprefix.p, prefix.data(), sizeof(int32_t) * prefix.size(), hipMemcpyHostToDevice, s));
+    NXG_HIP(hipMemcpyAsync(ddesc.p, hdesc.data(), sizeof(MultiGraph) * G, hipMemcpyHostToDevice, s));
+    static size_t attr = 0;
+    if (lds > attr) {
+        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = lds;
+    }
+    const int per_iter = prefix.back();
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < iters; ++k) {
+        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(per_iter), dim3(1024), lds, s,
+                           ddesc.as<MultiGraph>(), G, dprefix.as<int32_t>(), ditems.as<Item>(), k,
+                           iters, d.damping);
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipEventRecord(e1, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    if (st) {
+        double worst = 0.0;
+        std::vector<double> hs(4);
+        for (int i = 0; i < G; ++i) {
+            NXG_HIP(hipMemcpy(hs.data(), ws[i].stats.as<double>() + 4 * (iters - 1), sizeof(double) * 4,
+                              hipMemcpyDeviceToHost));
+            worst = std::max(worst, hs[1]);
+        }
+        memset(st, 0, sizeof(*st));
+        st->iterations = iters;
+        st->residual = worst;
+        st->device_ms = ms;
+    }
+    return NXG_OK;
+}
+
 nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (!g->has_rev || !g->fwd.has_weight || !g->fwd.has_perm || !g->rev.has_weight)
         fail(NXG_EINVAL, "the adjoint needs a build with weights, NXG_BUILD_TRANSPOSE and "
@@ -1547,6 +1710,11 @@ void set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) {
 
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st) {
     return run_adjoint(g, d, s, st);
+}
+
+nxg_status multi_run(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values, hipStream_t s,
+                     nxg_run_stats* st) {
+    return run_multi(mg, d, d_values, s, st);
 }
 
 void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) { set_weights(g, d_w, s); }

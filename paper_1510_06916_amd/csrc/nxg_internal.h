@@ -148,6 +148,13 @@ struct nxg_dsss {
     ~nxg_dsss();
 };
 
+struct nxg_multi {
+    std::vector<nxg_dsss*> graphs;
+    ~nxg_multi() {
+        for (nxg_dsss* g : graphs) delete g;
+    }
+};
+
 namespace nxg {
 // builder entry (builder.hip)
 void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& out);
@@ -157,5 +164,7 @@ void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t*
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
 void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s);
+nxg_status multi_run(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values, hipStream_t s,
+                     nxg_run_stats* st);
 int lds_budget_bytes(int device);
 }  // namespace nxg
