@@ -156,6 +156,10 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
 
 #define NXG_RUN_WARM_START 0x1u /* d_values holds x^0 on entry (PageRank) */
 #define NXG_RUN_PERSISTENT 0x2u /* nxg_multi_run: single persistent launch (switched off) */
+#define NXG_RUN_CAPTURE 0x4u    /* PageRank, tol <= 0: record the launches of the run into a
+                                   hipGraph kept by the handle (with its workspace) and replay
+                                   it when a later run has the same program, dtype, iteration
+                                   count, damping, flags, buffers and piece size */
 
 typedef struct nxg_run_desc {
     nxg_program program;
@@ -174,6 +178,8 @@ typedef struct nxg_run_desc {
     uint32_t flags;         /* NXG_RUN_* */
     const int32_t* d_seeds; /* batched personalised PageRank: device [B] seed vertices;
                                column b teleports to seeds[b] (one-hot t). NULL = uniform */
+    int32_t piece_chunks;   /* chunks per workgroup piece of a destination tile (0 = planner);
+                               larger tiles are split and combined in two phases */
 } nxg_run_desc;
 
 typedef struct nxg_run_stats {
@@ -193,7 +199,32 @@ typedef struct nxg_run_stats {
 nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
 
 /* ------------------------------------------------------------------------- */
-/* Many graphs, one persistent launch                                         */
+/* Autotuning                                                                 */
+/* ------------------------------------------------------------------------- */
+
+typedef struct nxg_tune_result {
+    int32_t interval;      /* best interval size I */
+    int32_t tile;          /* best destination tile T */
+    int32_t chunk;         /* best chunk size */
+    int32_t order;         /* NXG_ORDER_* of the best layout */
+    int32_t piece_chunks;  /* best nxg_run_desc.piece_chunks (0 = planner) */
+    double ms_per_iter;    /* measured milliseconds per iteration */
+    int32_t candidates;    /* candidates timed (0 when served from the cache) */
+} nxg_tune_result;
+
+/* Times PageRank iterations of the graph in desc under candidate layouts
+ * (source interval x destination tile, then chunk and piece size) and returns
+ * the fastest. The paper picks the interval count from experience (Sec.
+ * IV-B2); here it is measured. Results are cached per process and, when the
+ * environment variable NXG_TUNE_CACHE names a file, appended to it and read
+ * back, keyed by device, n, m, program, dtype, batch, value_bytes and flags.
+ * Builds and runs on `stream` and synchronises it; never use under capture.
+ * PageRank (plain or weighted), F32 or F64, batch 1. */
+nxg_status nxg_tune(const nxg_build_desc* desc, nxg_program program, nxg_dtype dtype,
+                    int32_t batch, void* stream, nxg_tune_result* result);
+
+/* ------------------------------------------------------------------------- */
+/* Many graphs per launch                                                     */
 /* ------------------------------------------------------------------------- */
 
 typedef struct nxg_multi nxg_multi; /* opaque set of independent graphs */

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import NxgError  # noqa: F401
 
 __all__ = ["DSSS", "MultiDSSS", "NxgError", "WeightedPageRank", "abi_version",
-           "install_torch_allocator"]
+           "install_torch_allocator", "tune"]
 
 _alloc_refs = None
 
@@ -61,6 +61,25 @@ def _dev_i32(t, name):
 
 
 _DT = {torch.float32: _lib.NXG_F32, torch.float64: _lib.NXG_F64}
+
+
+def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
+    """Times candidate layouts for PageRank on this graph; returns a dict with
+    interval, tile, chunk, order, piece_chunks, ms_per_iter, candidates."""
+    install_torch_allocator()
+    src = _dev_i32(src, "src")
+    dst = _dev_i32(dst, "dst")
+    w = None if weights is None else weights.to(device=src.device, dtype=torch.float32).contiguous()
+    d = _lib.BuildDesc(n=int(n), m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
+                       d_dst=dst.data_ptr() if dst.numel() else None,
+                       d_weight=w.data_ptr() if w is not None else None, interval=0, tile=0,
+                       chunk=0, value_bytes=8, flags=0, order=0)
+    r = _lib.TuneResult()
+    prog = _lib.NXG_PAGERANK_WEIGHTED if w is not None else _lib.NXG_PAGERANK
+    with torch.cuda.device(src.device):
+        _lib.check(_lib.lib().nxg_tune(ctypes.byref(d), prog, _DT[dtype], 1, _stream_handle(stream),
+                                       ctypes.byref(r)), "nxg_tune")
+    return {k: getattr(r, k) for k, _ in r._fields_}
 
 
 class DSSS:
@@ -161,7 +180,7 @@ class DSSS:
         return out
 
     def pagerank(self, iters, damping=0.85, dtype=torch.float32, tol=0.0, teleport=None,
-                 x0=None, weighted=False, out=None):
+                 x0=None, weighted=False, out=None, capture=False, piece_chunks=0):
         n = self.n
         if dtype not in _DT:
             raise ValueError("dtype must be float32 or float64")
@@ -173,11 +192,15 @@ class DSSS:
         tp = None
         if teleport is not None:
             tp = teleport.to(device=self.device, dtype=dtype).contiguous()
+        if capture:
+            flags |= _lib.NXG_RUN_CAPTURE
+            self._keep = getattr(self, "_keep", [])
+            self._keep += [x, tp]  # captured graphs hold these pointers
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK_WEIGHTED if weighted else _lib.NXG_PAGERANK,
                          dtype=_DT[dtype], batch=1, damping=float(damping),
                          max_iters=int(iters), tol=float(tol),
                          d_teleport=tp.data_ptr() if tp is not None else None, roots=None,
-                         d_values=x.data_ptr(), flags=flags)
+                         d_values=x.data_ptr(), flags=flags, piece_chunks=int(piece_chunks))
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 

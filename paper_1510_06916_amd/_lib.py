@@ -18,6 +18,7 @@ NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
 NXG_RUN_WARM_START = 0x1
 NXG_RUN_PERSISTENT = 0x2
+NXG_RUN_CAPTURE = 0x4
 NXG_ORDER_DST, NXG_ORDER_SRC = 0, 1
 
 
@@ -44,7 +45,8 @@ class RunDesc(ctypes.Structure):
                 ("damping", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("d_teleport", ctypes.c_void_p),
                 ("roots", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32), ("d_seeds", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("d_seeds", ctypes.c_void_p),
+                ("piece_chunks", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -62,6 +64,12 @@ class AdjointDesc(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("d_xstar", ctypes.c_void_p),
                 ("d_gx", ctypes.c_void_p), ("d_lambda", ctypes.c_void_p),
                 ("d_gw", ctypes.c_void_p), ("d_gt", ctypes.c_void_p)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("interval", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("piece_chunks", ctypes.c_int32),
+                ("ms_per_iter", ctypes.c_double), ("candidates", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -89,6 +97,8 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                      ctypes.POINTER(RunStats)]),
     "nxg_multi_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nxg_tune": (ctypes.c_int, [ctypes.POINTER(BuildDesc), ctypes.c_int, ctypes.c_int, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.POINTER(TuneResult)]),
     "nxg_pagerank_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AdjointDesc),
                                             ctypes.c_void_p, ctypes.POINTER(RunStats)]),
 }

@@ -56,7 +56,9 @@ nxg_status guarded(F&& f) {
 }  // namespace nxg
 
 nxg_dsss::~nxg_dsss() {
+    for (nxg::Cached* c : cached) delete c;
     for (nxg::Plan* p : plans) delete p;
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 using namespace nxg;
@@ -208,6 +210,16 @@ nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_
     return guarded([&]() {
         if (!g || !desc) fail(NXG_EINVAL, "NULL argument");
         return run_program(g, *desc, (hipStream_t)stream, stats);
+    });
+}
+
+nxg_status nxg_tune(const nxg_build_desc* desc, nxg_program program, nxg_dtype dtype,
+                    int32_t batch, void* stream, nxg_tune_result* result) {
+    return guarded([&]() {
+        if (!desc || !result) fail(NXG_EINVAL, "NULL argument");
+        if (desc->n < 1 || desc->m < 0 || (desc->m > 0 && (!desc->d_src || !desc->d_dst)))
+            fail(NXG_EINVAL, "invalid graph");
+        return tune(*desc, program, dtype, batch, (hipStream_t)stream, result);
     });
 }
 

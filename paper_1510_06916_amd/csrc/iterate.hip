@@ -14,6 +14,7 @@
 // The last tile to finish reduces the per-iteration scalars (dangling mass,
 // residual, activity) in tile order, so they are independent of scheduling.
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstring>
 
@@ -1152,6 +1153,148 @@ void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int m
     NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
 }
 
+// A PageRank run recorded into a hipGraph (NXG_RUN_CAPTURE) with the
+// workspace it uses; replayed when a later run asks for the same thing.
+struct CapturedPR : Cached {
+    int program = 0, dtype = 0, iters = 0, piece = 0;
+    uint32_t flags = 0;
+    double damping = 0.0;
+    const void* values = nullptr;
+    const void* tele = nullptr;
+    Workspace w;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~CapturedPR() override {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+template <class Prog, int WG>
+void prepare_iter(size_t lds) {
+    static size_t attr_lds = 0;
+    if (lds > attr_lds) {
+        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_lds = lds;
+    }
+}
+
+// Enqueues x^0 and max_iters iterations of (weighted) PageRank; no syncs.
+template <typename V>
+void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_run_desc& d,
+                      bool weighted, hipStream_t s) {
+    const int nb = grid_for(L.n, 256, 1024);
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? (const V*)d.d_values : nullptr;
+    hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
+                       (const V*)d.d_teleport, x0, weighted ? 0 : 1, w.buf[0].as<V>(),
+                       w.part.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
+                       w.stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(L, p, w);
+    const size_t lds = (size_t)L.T * sizeof(double);
+    const int n_items = (int)p.h_items.size();
+    for (int k = 0; k < d.max_iters; ++k) {
+        Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
+        const V* cur = w.buf[k & 1].as<V>();
+        V* nxt = w.buf[(k + 1) & 1].as<V>();
+        V* xout = (k == d.max_iters - 1) ? (V*)d.d_values : nullptr;
+        if (weighted) {
+            ProgPRW<V> pr{cur, nxt, (const V*)d.d_teleport, xout, L.weight.as<float>(), d.damping};
+            hipLaunchKernelGGL((k_iterate<ProgPRW<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
+                               ctl, pr);
+        } else {
+            ProgPR<V> pr{cur, nxt, (const V*)d.d_teleport, xout, d.damping};
+            hipLaunchKernelGGL((k_iterate<ProgPR<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
+                               ctl, pr);
+        }
+        NXG_CHECK_LAUNCH();
+    }
+}
+
+template <typename V>
+nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s,
+                                 nxg_run_stats* st, int piece) {
+    const Layout& L = g->fwd;
+    const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
+    if (d.tol > 0) fail(NXG_EINVAL, "NXG_RUN_CAPTURE needs a fixed iteration count (tol <= 0)");
+    if (d.max_iters < 1) fail(NXG_EINVAL, "NXG_RUN_CAPTURE needs max_iters >= 1");
+    CapturedPR* e = nullptr;
+    for (Cached* c : g->cached) {
+        CapturedPR* r = dynamic_cast<CapturedPR*>(c);
+        if (r && r->program == d.program && r->dtype == d.dtype && r->iters == d.max_iters &&
+            r->piece == piece && r->flags == d.flags && r->damping == d.damping &&
+            r->values == d.d_values && r->tele == d.d_teleport) {
+            e = r;
+            break;
+        }
+    }
+    if (!e) {
+        Plan* p = get_plan(g, L, piece, false, s);
+        std::unique_ptr<CapturedPR> n(new CapturedPR());
+        n->program = d.program;
+        n->dtype = d.dtype;
+        n->iters = d.max_iters;
+        n->piece = piece;
+        n->flags = d.flags;
+        n->damping = d.damping;
+        n->values = d.d_values;
+        n->tele = d.d_teleport;
+        Workspace& w = n->w;
+        alloc_common(w, L, *p, sizeof(double), d.max_iters, s, false);
+        w.buf[0].alloc(sizeof(V) * L.n, s);
+        w.buf[1].alloc(sizeof(V) * L.n, s);
+        w.part.alloc(sizeof(double) * grid_for(L.n, 256, 1024), s);
+        const size_t lds = (size_t)L.T * sizeof(double);
+        if (weighted)
+            prepare_iter<ProgPRW<V>, 1024>(lds);
+        else
+            prepare_iter<ProgPR<V>, 1024>(lds);
+        NXG_HIP(hipStreamSynchronize(s));
+        if (!g->capture_stream)
+            NXG_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = g->capture_stream;
+        NXG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_pagerank<V>(L, *p, w, d, weighted, cs);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cs, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            throw;
+        }
+        NXG_HIP(hipStreamEndCapture(cs, &n->graph));
+        NXG_HIP(hipGraphInstantiate(&n->exec, n->graph, nullptr, nullptr, 0));
+        e = n.release();
+        g->cached.push_back(e);
+    }
+    hipEvent_t e0, e1;
+    if (st) {
+        NXG_HIP(hipEventCreate(&e0));
+        NXG_HIP(hipEventCreate(&e1));
+        NXG_HIP(hipEventRecord(e0, s));
+    }
+    NXG_HIP(hipGraphLaunch(e->exec, s));
+    if (st) {
+        NXG_HIP(hipEventRecord(e1, s));
+        std::vector<double> hs(4 * (size_t)(d.max_iters + 2));
+        NXG_HIP(hipMemcpyAsync(hs.data(), e->w.stats.p, sizeof(double) * hs.size(),
+                               hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        NXG_HIP(hipEventDestroy(e0));
+        NXG_HIP(hipEventDestroy(e1));
+        memset(st, 0, sizeof(*st));
+        st->iterations = d.max_iters;
+        st->residual = hs[4 * (d.max_iters - 1) + 1];
+        st->device_ms = ms;
+    }
+    return NXG_OK;
+}
+
 template <typename V>
 nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     const Layout& L = g->fwd;
@@ -1163,8 +1306,9 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         fail(NXG_EINVAL, "destination tile does not fit in LDS (PageRank accumulates 8 bytes per "
                          "vertex); rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
-    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    int piece = d.piece_chunks > 0 ? d.piece_chunks : env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    if (d.flags & NXG_RUN_CAPTURE) return run_pagerank_captured<V>(g, d, s, st, piece);
     Plan* p = get_plan(g, L, piece, false, s);
     Workspace w;
     const int max_iters = d.max_iters;

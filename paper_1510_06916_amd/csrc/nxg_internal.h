@@ -124,6 +124,11 @@ struct Item {
     int64_t c0, c1; // chunk range [c0, c1)
 };
 
+// Something a handle keeps between runs (captured hipGraphs with their workspace).
+struct Cached {
+    virtual ~Cached() {}
+};
+
 struct Layout;
 struct Plan {
     const Layout* layout = nullptr;
@@ -145,6 +150,10 @@ struct nxg_dsss {
     bool has_rev = false;
     // cached iteration plans, keyed by piece size
     std::vector<nxg::Plan*> plans;
+    // captured runs (hipGraph + workspace), see NXG_RUN_CAPTURE, recorded on a
+    // private stream (the legacy default stream cannot be captured)
+    std::vector<nxg::Cached*> cached;
+    hipStream_t capture_stream = nullptr;
     ~nxg_dsss();
 };
 
@@ -164,6 +173,8 @@ void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t*
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
 void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s);
+nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, hipStream_t s,
+                nxg_tune_result* out);
 nxg_status multi_run(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values, hipStream_t s,
                      nxg_run_stats* st);
 int lds_budget_bytes(int device);

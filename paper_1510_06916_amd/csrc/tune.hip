@@ -1,0 +1,182 @@
+// Autotuner: times candidate DSSS layouts (interval, tile, chunk) and work
+// splits (piece size) for one graph and program, and keeps the fastest. The
+// paper reports intervals between 12 and 48 as good choices on its CPU
+// (Sec. IV-B2); on the GPU the useful range is set by the LDS size and the
+// cache hierarchy, so it is measured instead of assumed.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "nxg_internal.h"
+
+namespace nxg {
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, nxg_tune_result> g_tune_cache;
+
+std::string tune_key(const nxg_build_desc& d, int program, int dtype, int batch, int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s n=%d m=%lld prog=%d dtype=%d batch=%d vb=%d flags=%u", arch.c_str(),
+             d.n, (long long)d.m, program, dtype, batch, d.value_bytes, d.flags);
+    return buf;
+}
+
+bool load_cached(const std::string& key, nxg_tune_result* out) {
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        *out = it->second;
+        out->candidates = 0;  // served from the cache
+        return true;
+    }
+    const char* path = getenv("NXG_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (key != line) continue;
+        nxg_tune_result r;
+        memset(&r, 0, sizeof r);
+        if (sscanf(bar + 1, "%d %d %d %d %d %lf", &r.interval, &r.tile, &r.chunk, &r.order,
+                   &r.piece_chunks, &r.ms_per_iter) == 6) {
+            *out = r;
+            found = true;
+        }
+    }
+    fclose(f);
+    if (found) {
+        out->candidates = 0;
+        g_tune_cache[key] = *out;
+    }
+    return found;
+}
+
+void store_cached(const std::string& key, const nxg_tune_result& r) {
+    g_tune_cache[key] = r;
+    const char* path = getenv("NXG_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s|%d %d %d %d %d %.6f\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
+            r.piece_chunks, r.ms_per_iter);
+    fclose(f);
+}
+
+// Mean milliseconds per iteration of `iters` PageRank iterations (after one
+// warm-up run) on a built handle.
+double time_run(nxg_dsss* g, const nxg_run_desc& base, void* values, int piece, hipStream_t s) {
+    nxg_run_desc d = base;
+    d.d_values = values;
+    d.piece_chunks = piece;
+    d.tol = 0.0;
+    nxg_run_stats st;
+    d.max_iters = 2;
+    run_program(g, d, s, &st);
+    d.max_iters = 6;
+    run_program(g, d, s, &st);
+    return st.device_ms / d.max_iters;
+}
+
+}  // namespace
+
+nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, hipStream_t s,
+                nxg_tune_result* out) {
+    if (program != NXG_PAGERANK && program != NXG_PAGERANK_WEIGHTED)
+        fail(NXG_EUNSUPPORTED, "the autotuner times PageRank runs");
+    if (dtype != NXG_F32 && dtype != NXG_F64) fail(NXG_EINVAL, "PageRank dtype must be F32 or F64");
+    if (batch != 1) fail(NXG_EUNSUPPORTED, "the autotuner times single-column runs");
+    int device = 0;
+    NXG_HIP(hipGetDevice(&device));
+    const std::string key = tune_key(desc, program, dtype, batch, device);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (load_cached(key, out)) return NXG_OK;
+    const size_t vsize = dtype == NXG_F64 ? 8 : 4;
+    DevBuf values;
+    values.alloc(vsize * (size_t)desc.n, s);
+    nxg_run_desc base;
+    memset(&base, 0, sizeof base);
+    base.program = (nxg_program)program;
+    base.dtype = (nxg_dtype)dtype;
+    base.batch = 1;
+    base.damping = 0.85;
+    const int budget = lds_budget_bytes(device);
+    int tmax = 1;
+    while ((int64_t)tmax * 2 * 8 <= budget) tmax *= 2;
+    nxg_tune_result best;
+    memset(&best, 0, sizeof best);
+    best.ms_per_iter = 1e300;
+    int timed = 0;
+    auto try_layout = [&](int interval, int tile, int chunk, int order, const int* pieces, int np) {
+        nxg_build_desc d = desc;
+        d.interval = interval;
+        d.tile = tile;
+        d.chunk = chunk;
+        d.order = order;
+        d.value_bytes = 8;
+        nxg_dsss* g = new nxg_dsss();
+        try {
+            g->device = device;
+            g->value_bytes = 8;
+            g->flags = d.flags;
+            build_layout(d, false, s, g->fwd);
+            for (int k = 0; k < np; ++k) {
+                const double ms = time_run(g, base, values.p, pieces[k], s);
+                ++timed;
+                if (ms < best.ms_per_iter) {
+                    best.ms_per_iter = ms;
+                    best.interval = g->fwd.I;
+                    best.tile = g->fwd.T;
+                    best.chunk = g->fwd.C;
+                    best.order = order;
+                    best.piece_chunks = pieces[k];
+                }
+            }
+        } catch (const Error& e) {
+            // candidates that do not fit this graph are skipped
+            if (e.status != NXG_EINVAL) {
+                delete g;
+                throw;
+            }
+        }
+        delete g;
+    };
+    const int no_piece[1] = {0};
+    // stage 1: source interval x destination tile, default chunk and pieces
+    const int intervals[] = {2048, 4096, 8192, 16384, 32768};
+    for (int I : intervals) {
+        if (I > desc.n) continue;
+        for (int T : {tmax, tmax / 2}) try_layout(I, T, 1024, NXG_ORDER_DST, no_piece, 1);
+    }
+    if (best.ms_per_iter == 1e300) try_layout(0, 0, 0, NXG_ORDER_DST, no_piece, 1);
+    // stage 2: chunk size and piece size for the best layout
+    const int cus = [&] {
+        int c = 0;
+        return hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && c > 0
+                   ? c
+                   : 256;
+    }();
+    const nxg_tune_result stage1 = best;
+    for (int C : {1024, 2048}) {
+        const int64_t words = desc.m + (int64_t)desc.n;  // rough stream size for the piece grid
+        const int autop = (int)std::max<int64_t>(16, words / C / (4 * cus));
+        const int pieces[4] = {autop / 2, autop, 2 * autop, 4 * autop};
+        try_layout(stage1.interval, stage1.tile, C, NXG_ORDER_DST, pieces, 4);
+    }
+    best.candidates = timed;
+    store_cached(key, best);
+    *out = best;
+    return NXG_OK;
+}
+
+}  // namespace nxg

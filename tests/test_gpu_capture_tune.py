@@ -1,0 +1,69 @@
+"""hipGraph capture of PageRank runs (replays checked against eager runs) and the
+autotuner (valid layouts, cache file)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rmatgen
+from paper_1510_06916_amd import DSSS, tune
+from gpu_util import rel_l1, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_capture_replays_match_eager(gpu_device):
+    n = 1 << 13
+    src, dst = rmatgen.rmat_edges(13, 8, seed=90)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=1024, tile=2048)
+    ref, _ = oracle.pagerank(n, src, dst, iters=12)
+    eager, _ = g.pagerank(12, dtype=torch.float64)
+    out = torch.empty(n, dtype=torch.float64, device=gpu_device)
+    for rep in range(4):
+        out.fill_(-1.0)
+        x, st = g.pagerank(12, dtype=torch.float64, capture=True, out=out)
+        assert x.data_ptr() == out.data_ptr() and st["iterations"] == 12
+        say("replay %d: rel-L1 vs eager %.2e" % (rep, rel_l1(x.cpu().numpy(), eager.cpu().numpy())))
+        assert rel_l1(x.cpu().numpy(), eager.cpu().numpy()) <= 1e-13
+        assert rel_l1(x.cpu().numpy(), ref) <= 1e-12
+        # eager work and a sync between replays
+        g.pagerank(3, dtype=torch.float32)
+        torch.cuda.synchronize()
+
+
+def test_capture_weighted_fp32(gpu_device):
+    n = 1 << 12
+    src, dst = rmatgen.rmat_edges(12, 8, seed=91)
+    w = rmatgen.row_normalized_weights(src, n, seed=191)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=512,
+                   weights=torch.from_numpy(w))
+    ref, _ = oracle.pagerank(n, src, dst, iters=9, w=w.astype(np.float64))
+    out = torch.empty(n, dtype=torch.float32, device=gpu_device)
+    for _ in range(3):
+        x, _ = g.pagerank(9, dtype=torch.float32, weighted=True, capture=True, out=out)
+        assert rel_l1(x.cpu().numpy(), ref) <= 1e-5
+
+
+def test_capture_rejects_tolerance(gpu_device):
+    src, dst = rmatgen.rmat_edges(8, 4, seed=1)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), 256)
+    with pytest.raises(Exception, match="EINVAL"):
+        g.pagerank(5, tol=1e-6, capture=True)
+
+
+def test_tune_picks_a_valid_layout_and_caches(gpu_device, tmp_path, monkeypatch):
+    monkeypatch.setenv("NXG_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    n = 1 << 14
+    src, dst = rmatgen.rmat_edges(14, 8, seed=92)
+    s, d = to_dev(src, gpu_device), to_dev(dst, gpu_device)
+    r = tune(s, d, n)
+    say("tune: %s" % r)
+    assert r["candidates"] > 4 and r["ms_per_iter"] > 0
+    assert r["interval"] >= 1 and r["tile"] >= 1 and r["chunk"] in (1024, 2048)
+    r2 = tune(s, d, n)
+    assert r2["candidates"] == 0 and r2["interval"] == r["interval"]
+    assert (tmp_path / "tune.txt").read_text().count("|") == 1
+    g = DSSS.build(s, d, n, interval=r["interval"], tile=r["tile"], chunk=r["chunk"])
+    x, _ = g.pagerank(10, dtype=torch.float32, piece_chunks=r["piece_chunks"])
+    ref, _ = oracle.pagerank(n, src, dst, iters=10)
+    assert rel_l1(x.cpu().numpy(), ref) <= 1e-5
