@@ -1,13 +1,20 @@
-"""PageRank iteration throughput on an R-MAT scale-25, edge-factor-48 graph.
+"""Benchmarks of the DSSS iteration on one MI355X.
 
-One step = one synchronous PageRank iteration (FP32 values and accumulation)
-over the whole graph stored as destination-sorted sub-shards: every edge word
-is streamed once, its source value gathered, reduced by destination in LDS and
-the vertex update applied. Prints one JSON line (rank 0).
+Default (the headline): PageRank on an R-MAT graph of scale 25, edge factor 48
+(a/b/c/d = 0.57/0.19/0.19/0.05, seeded, self-loops kept, duplicates removed),
+FP32 values. One step = one synchronous PageRank iteration over the whole graph:
+every edge word is streamed once, its source value gathered, reduced by
+destination in LDS and the vertex update applied. The layout is autotuned, the
+K timed iterations are one replay of a captured hipGraph. Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--scale 25] [--ef 48]
+Other workloads (--mode): bfs, wcc (scale 22, ef 16, 32 intervals), ppr (64
+seeds, scale 22), multi (256 graphs, scales 10..18), adjoint (scale 20, fwd to
+1e-8 residual + backward); --mode all runs every one (one JSON line each).
+
+  python bench.py [--steps K] [--warmup W] [--mode pagerank|bfs|wcc|ppr|multi|adjoint|all]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -17,27 +24,274 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pagerank_rmat_s25_ef48.traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1510_06916_amd", "csrc", "iterate.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(src_d, dst_d, n, sample_stride, iters=1):
+def kernel_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per iteration from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("bytes_per_iter")
+
+
+def cpu_baseline_pagerank(src_d, dst_d, n, stride):
     """Times the CPU oracle (single thread, FP64) for one PageRank iteration over
-    every sample_stride-th edge of the same graph (n unchanged)."""
-    import numpy as np
+    every stride-th edge of the same graph (n unchanged)."""
     import oracle
-    src = src_d[::sample_stride].cpu().numpy()
-    dst = dst_d[::sample_stride].cpu().numpy()
-    oracle.outdeg(n, src[:1])  # load the library outside the timed region
+    src = src_d[::stride].cpu().numpy()
+    dst = dst_d[::stride].cpu().numpy()
+    oracle.outdeg(1, src[:1] * 0)  # load the library outside the timed region
     t0 = time.perf_counter()
-    oracle.pagerank(n, src, dst, iters=iters)
+    oracle.pagerank(n, src, dst, iters=1)
     dt = time.perf_counter() - t0
     m = len(src)
-    return {"value": m * iters / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": "1 FP64 PageRank iteration of the single-threaded C oracle over every "
-                      "%d-th edge (%d edges, n=%d), %.1f s" % (sample_stride, m, n, dt)}
+    return {"value": m / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 PageRank iteration of the single-threaded C oracle over %s "
+                      "(%d edges, n=%d): %.1f s" % ("every edge" if stride == 1 else
+                                                    "every %d-th edge" % stride, m, n, dt)}
+
+
+def rmat(scale, ef, seed, dev):
+    import rmatgen
+    t0 = time.perf_counter()
+    src, dst = rmatgen.rmat_edges_gpu(scale, ef, seed, device=dev)
+    log("R-MAT scale %d ef %d seed %d: m=%d (%.1fs)" % (scale, ef, seed, src.numel(),
+                                                       time.perf_counter() - t0))
+    return src, dst
+
+
+# ---------------------------------------------------------------------------
+def bench_pagerank(args, dev):
+    import torch
+    from paper_1510_06916_amd import DSSS, copy_probe, tune
+    n = 1 << args.scale
+    src, dst = rmat(args.scale, args.ef, args.seed, dev)
+    if args.interval or args.tile or args.chunk:
+        best = {"interval": args.interval, "tile": args.tile, "chunk": args.chunk,
+                "piece_chunks": 0, "order": 0, "candidates": 0}
+    else:
+        t0 = time.perf_counter()
+        os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "tune_cache.txt"))
+        os.makedirs(os.path.dirname(os.environ["NXG_TUNE_CACHE"]), exist_ok=True)
+        best = tune(src, dst, n)
+        log("tuned in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
+    t0 = time.perf_counter()
+    g = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"],
+                   chunk=best["chunk"], order=args.order)
+    torch.cuda.synchronize()
+    inf = g.info()
+    log("built DSSS in %.2fs: %s" % (time.perf_counter() - t0, json.dumps(inf)))
+    m = inf["m"]
+    piece = best["piece_chunks"]
+    x, st = g.pagerank(max(args.warmup, 1), dtype=torch.float32, piece_chunks=piece)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    g.pagerank(args.steps, dtype=torch.float32, capture=True, out=out, piece_chunks=piece)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    x, st = g.pagerank(args.steps, dtype=torch.float32, capture=True, out=out, piece_chunks=piece)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    log("timed %d steps (one graph replay): wall %.3f ms/step, events %.3f ms/step" %
+        (args.steps, ms_step, kern_ms))
+    b_iter = 4.0 * m + 12.0 * n
+    achieved = b_iter / (kern_ms * 1e-3) / 1e9
+    log("sum(x) = %.9f" % float(x.double().sum()))
+    copy_gbs = copy_probe(1 << 30, 10)
+    log("copy probe: %.0f GB/s" % copy_gbs)
+    traffic = measured_traffic()
+    res = {
+        "metric": "PageRank GTEPS per iteration (R-MAT scale %d, ef %d)" % (args.scale, args.ef),
+        "value": m / (ms_step * 1e-3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic R-MAT (a/b/c/d=0.57/0.19/0.19/0.05, Philox seed %d, dedup)" % args.seed,
+        "config": {"workload": "pagerank-iteration rmat-s%d-ef%d" % (args.scale, args.ef),
+                   "n": n, "m": m, "interval": inf["interval"], "P": inf["P"],
+                   "tile": inf["tile"], "chunk": inf["chunk"], "piece_chunks": piece,
+                   "order": args.order, "damping": 0.85, "tuned_candidates": best["candidates"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_iter": b_iter, "kernel_ms": kern_ms,
+                     "copy_probe_gbs": copy_gbs},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_pagerank(src, dst, n, args.cpu_stride)
+    print(json.dumps(res), flush=True)
+
+
+# ---------------------------------------------------------------------------
+def bench_bfs_wcc(args, dev, which):
+    import numpy as np
+    import torch
+    import rmatgen
+    from paper_1510_06916_amd import DSSS
+    scale, ef, seed, P = 22, 16, 2, 32
+    n = 1 << scale
+    src, dst = rmat(scale, ef, seed, dev)
+    interval = n // P
+    if which == "bfs":
+        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4)
+        deg = torch.bincount(src.long(), minlength=n).cpu().numpy()
+        roots = rmatgen.distinct_vertices(seed + 100, 16, n, eligible=deg > 0)
+        g.bfs(int(roots[0]))  # warm-up
+        rates, times = [], []
+        for r in roots.tolist():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lev, st = g.bfs(r)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            times.append(dt)
+            rates.append(st["reached_edges"] / dt)
+        hm = len(rates) / sum(1.0 / r for r in rates)
+        res = {"metric": "BFS TEPS (harmonic mean over 16 roots)", "value": hm / 1e9,
+               "unit": "GTEPS", "n_gpus": 1, "dtype": "i32", "higher_is_better": True,
+               "config": {"workload": "bfs rmat-s22-ef16 P=32", "n": n, "m": g.m,
+                          "mean_ms": 1e3 * float(np.mean(times)), "roots": len(roots)}}
+    else:
+        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, symmetrize=True)
+        g.wcc()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab, st = g.wcc()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"metric": "WCC label propagation (edges x rounds per second)",
+               "value": g.m * st["changed_rounds"] / dt / 1e9, "unit": "GTEPS", "n_gpus": 1,
+               "dtype": "i32", "higher_is_better": True,
+               "config": {"workload": "wcc rmat-s22-ef16 symmetrised P=32", "n": n,
+                          "m_sym": g.m, "rounds": st["changed_rounds"], "ms": dt * 1e3}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_ppr(args, dev):
+    import torch
+    import rmatgen
+    from paper_1510_06916_amd import DSSS
+    scale, ef, seed, B, iters = 22, 16, 4, 64, 30
+    n = 1 << scale
+    src, dst = rmat(scale, ef, seed, dev)
+    seeds = torch.from_numpy(rmatgen.distinct_vertices(seed + 100, B, n))
+    gb = DSSS.build(src, dst, n, tile=256, interval=16384, value_bytes=8 * B)
+    gb.ppr(seeds, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xb, st = gb.ppr(seeds, iters)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    gp = DSSS.build(src, dst, n)
+    tele = torch.zeros(n, dtype=torch.float32, device=dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    tele[int(seeds[0])] = 1.0
+    gp.pagerank(iters, teleport=tele, out=out, capture=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(B):
+        tele.zero_()
+        tele[int(seeds[b])] = 1.0
+        gp.pagerank(iters, teleport=tele, out=out, capture=True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    res = {"metric": "batched PPR edge-vector updates per second", "value": B * gb.m * iters / tb / 1e9,
+           "unit": "G updates/s", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
+           "config": {"workload": "ppr rmat-s22-ef16 B=64 30 iterations", "n": n, "m": gb.m,
+                      "batched_ms": tb * 1e3, "plain_64_runs_ms": tp * 1e3,
+                      "speedup_vs_plain": tp / tb}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_multi(args, dev):
+    import numpy as np
+    import torch
+    import rmatgen
+    from paper_1510_06916_amd import DSSS, MultiDSSS
+    rng = np.random.default_rng(4000)
+    graphs = []
+    for g in range(256):
+        scale = int(rng.integers(10, 19))
+        ef = int(rng.integers(8, 33))
+        s, d = rmatgen.rmat_edges_gpu(scale, ef, 4000 + g, device=dev)
+        graphs.append((s, d, 1 << scale))
+    m_total = sum(int(s.numel()) for s, _, _ in graphs)
+    mg = MultiDSSS.build(graphs)
+    mg.pagerank(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, st = mg.pagerank(30)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    plain = [DSSS.build(s, d, n) for s, d, n in graphs]
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for _, _, n in graphs]
+    for g, o in zip(plain, outs):
+        g.pagerank(30, out=o, capture=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, o in zip(plain, outs):
+        g.pagerank(30, out=o, capture=True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    res = {"metric": "256-graph PageRank (30 iterations) edges per second", "value": m_total * 30 / tm / 1e9,
+           "unit": "GTEPS", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
+           "config": {"workload": "multi 256 rmat graphs s10..18 ef8..32", "m_total": m_total,
+                      "one_launch_per_iteration_ms": tm * 1e3, "plain_captured_runs_ms": tp * 1e3,
+                      "speedup_vs_plain": tp / tm}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_adjoint(args, dev):
+    import numpy as np
+    import torch
+    import rmatgen
+    from paper_1510_06916_amd import DSSS, WeightedPageRank
+    scale, ef, seed = 20, 16, 5
+    n = 1 << scale
+    src, dst = rmat(scale, ef, seed, dev)
+    w = rmatgen.row_normalized_weights(src.cpu().numpy(), n, seed=seed + 100)
+    gvec = torch.from_numpy(rmatgen.normal_f32(seed + 200, n).astype(np.float64)).to(dev)
+    g = DSSS.build(src, dst, n, weights=torch.from_numpy(w), transpose=True, keep_perm=True)
+    wt = torch.from_numpy(w).to(dev)
+    x, st = g.pagerank(100000, dtype=torch.float64, tol=1e-8, weighted=True)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = g.pagerank(100000, dtype=torch.float64, tol=1e-8, weighted=True)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    wt.requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs = WeightedPageRank.apply(wt, None, g, 0.85, 1e-8)
+    (xs * gvec).sum().backward()
+    torch.cuda.synchronize()
+    tfb = time.perf_counter() - t0
+    res = {"metric": "weighted PageRank forward (1e-8) + adjoint backward time",
+           "value": tfb * 1e3, "unit": "ms", "n_gpus": 1, "dtype": "f64", "higher_is_better": False,
+           "config": {"workload": "adjoint rmat-s20-ef16 weighted", "n": n, "m": g.m,
+                      "forward_iterations": st["iterations"], "forward_alone_ms": tf * 1e3,
+                      "fwd_bwd_over_fwd": tfb / tf}}
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -45,6 +299,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="pagerank",
+                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "all"])
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--ef", type=int, default=48)
     ap.add_argument("--seed", type=int, default=3)
@@ -54,70 +310,28 @@ def main():
     ap.add_argument("--order", default="dst", choices=["dst", "src"])
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="also check sampled vertices vs FP64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the DSSS iteration runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(DESIGN.md describes how it would shard; nothing multi-GPU is built)",
+              file=sys.stderr)
         sys.exit(2)
-
     import torch
-    import rmatgen
-    from paper_1510_06916_amd import DSSS
-
     dev = torch.device("cuda:0")
-    n = 1 << args.scale
-    t0 = time.perf_counter()
-    src, dst = rmatgen.rmat_edges_gpu(args.scale, args.ef, args.seed, device=dev)
-    torch.cuda.synchronize()
-    log("generated R-MAT scale %d ef %d: m=%d in %.1fs" % (args.scale, args.ef, src.numel(),
-                                                           time.perf_counter() - t0))
-    t0 = time.perf_counter()
-    g = DSSS.build(src, dst, n, interval=args.interval, tile=args.tile, chunk=args.chunk,
-                   order=args.order)
-    torch.cuda.synchronize()
-    inf = g.info()
-    log("built DSSS in %.2fs: %s" % (time.perf_counter() - t0, json.dumps(inf)))
-    m = inf["m"]
-
-    x, st = g.pagerank(args.warmup, dtype=torch.float32)
-    torch.cuda.synchronize()
-    log("warmup done: %s" % json.dumps(st))
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    x, st = g.pagerank(args.steps, dtype=torch.float32)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    kern_ms = ev0.elapsed_time(ev1) / args.steps
-    log("timed %d steps: wall %.3f ms/step, events %.3f ms/step, lib %.3f ms total" %
-        (args.steps, ms_step, kern_ms, st["device_ms"]))
-    b_iter = 4.0 * m + 12.0 * n
-    achieved = b_iter / (kern_ms * 1e-3) / 1e9
-    mass = float(x.double().sum())
-    log("sum(x) = %.9f" % mass)
-    out = {
-        "metric": "PageRank GTEPS per iteration (R-MAT scale %d, ef %d)" % (args.scale, args.ef),
-        "value": m / (ms_step * 1e-3) / 1e9,
-        "unit": "GTEPS",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic R-MAT (a/b/c/d=0.57/0.19/0.19/0.05, Philox seed %d, dedup)" % args.seed,
-        "config": {"workload": "pagerank-iteration rmat-s%d-ef%d" % (args.scale, args.ef),
-                   "n": n, "m": m, "interval": inf["interval"], "P": inf["P"],
-                   "tile": inf["tile"], "chunk": inf["chunk"], "damping": 0.85,
-                   "order": args.order},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_iter": b_iter, "kernel_ms": kern_ms},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(src, dst, n, args.cpu_stride)
-    print(json.dumps(out), flush=True)
+    modes = ["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint"] if args.mode == "all" else [args.mode]
+    for mode in modes:
+        log("== mode %s" % mode)
+        if mode == "pagerank":
+            bench_pagerank(args, dev)
+        elif mode in ("bfs", "wcc"):
+            bench_bfs_wcc(args, dev, mode)
+        elif mode == "ppr":
+            bench_ppr(args, dev)
+        elif mode == "multi":
+            bench_multi(args, dev)
+        else:
+            bench_adjoint(args, dev)
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -64,6 +64,12 @@ const char* nxg_last_error(void);
 /* NXG_ABI_VERSION of the loaded library. */
 int nxg_abi_version(void);
 
+/* Attainable HBM bandwidth: times reps copies of a `bytes`-byte buffer (16-byte
+ * non-temporal loads, plain stores) and returns read+written GB/s. The same
+ * kernel, run under the FETCH_SIZE / WRITE_SIZE counters, calibrates them.
+ * Synchronises the stream. */
+nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbps);
+
 /* ------------------------------------------------------------------------- */
 /* DSSS construction (Sec. III-A: intervals and sub-shards from an edge list)  */
 /* ------------------------------------------------------------------------- */

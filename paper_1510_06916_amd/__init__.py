@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import NxgError  # noqa: F401
 
 __all__ = ["DSSS", "MultiDSSS", "NxgError", "WeightedPageRank", "abi_version",
-           "install_torch_allocator", "tune"]
+           "install_torch_allocator", "tune", "copy_probe"]
 
 _alloc_refs = None
 
@@ -61,6 +61,15 @@ def _dev_i32(t, name):
 
 
 _DT = {torch.float32: _lib.NXG_F32, torch.float64: _lib.NXG_F64}
+
+
+def copy_probe(nbytes=1 << 30, reps=10):
+    """Attainable HBM bandwidth (read + write GB/s) of a plain streaming copy."""
+    install_torch_allocator()
+    g = ctypes.c_double(0.0)
+    _lib.check(_lib.lib().nxg_copy_probe(int(nbytes), int(reps), _stream_handle(), ctypes.byref(g)),
+               "nxg_copy_probe")
+    return g.value
 
 
 def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
