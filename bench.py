@@ -37,15 +37,18 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per iteration from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
+def measured_traffic(cfg):
+    """HBM bytes per iteration (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe's
+    reading) from committed rocprofv3 counter runs, if they were taken on the
+    current kernel source with the same layout (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != kernel_sha():
+        return None
+    if any(t["config"].get(k) != cfg.get(k) for k in ("interval", "tile", "chunk", "piece_chunks", "order")):
         return None
     return t.get("bytes_per_iter")
 
@@ -84,7 +87,7 @@ def bench_pagerank(args, dev):
     src, dst = rmat(args.scale, args.ef, args.seed, dev)
     if args.interval or args.tile or args.chunk:
         best = {"interval": args.interval, "tile": args.tile, "chunk": args.chunk,
-                "piece_chunks": 0, "order": 0, "candidates": 0}
+                "piece_chunks": args.piece, "order": 0, "candidates": 0}
     else:
         t0 = time.perf_counter()
         os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "tune_cache.txt"))
@@ -120,7 +123,8 @@ def bench_pagerank(args, dev):
     log("sum(x) = %.9f" % float(x.double().sum()))
     copy_gbs = copy_probe(1 << 30, 10)
     log("copy probe: %.0f GB/s" % copy_gbs)
-    traffic = measured_traffic()
+    traffic = measured_traffic({"interval": inf["interval"], "tile": inf["tile"], "chunk": inf["chunk"],
+                                "piece_chunks": piece, "order": args.order})
     res = {
         "metric": "PageRank GTEPS per iteration (R-MAT scale %d, ef %d)" % (args.scale, args.ef),
         "value": m / (ms_step * 1e-3) / 1e9,
@@ -307,6 +311,7 @@ def main():
     ap.add_argument("--interval", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--piece", type=int, default=0, help="chunks per work item (0: automatic)")
     ap.add_argument("--order", default="dst", choices=["dst", "src"])
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
