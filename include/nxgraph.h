@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 1
+#define NXG_ABI_VERSION 2
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -78,11 +78,18 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
 #define NXG_BUILD_TRANSPOSE 0x2u  /* also store the reversed graph (source-sorted view) */
 #define NXG_BUILD_SYMMETRIZE 0x4u /* store E and reverse(E); implies NXG_BUILD_DEDUP */
 #define NXG_BUILD_DEDUP 0x8u      /* store each distinct (src, dst) pair once */
+#define NXG_BUILD_RELABEL 0x10u   /* number the vertices internally by decreasing
+                                     out-degree (ties by id), so the most gathered
+                                     source values are adjacent in memory; every
+                                     run still takes and returns vertex data in
+                                     the caller's ids (WCC labels stay the minimum
+                                     caller id of the component) */
 
 /* Order of the edges inside one sub-shard. */
 #define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */
-#define NXG_ORDER_SRC 1 /* source, then destination: the source-sorted layout the
-                           paper compares against (Sec. IV-B1), kept for ablation */
+#define NXG_ORDER_SRC 1 /* source, then destination: the source-sorted sub-shard
+                           the paper compares against (Sec. IV-B1); on this GPU it
+                           lets the lanes of one gather read adjacent sources */
 
 typedef struct nxg_build_desc {
     int32_t n;              /* vertices, >= 1 */
@@ -127,6 +134,7 @@ typedef struct nxg_dsss_info {
     int64_t max_tile_edges; /* edges of the heaviest destination tile */
     int32_t has_perm, has_weights, has_transpose;
     int32_t order;       /* NXG_ORDER_* */
+    int32_t relabeled;   /* built with NXG_BUILD_RELABEL */
 } nxg_dsss_info;
 
 nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
@@ -146,6 +154,12 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
  * Synchronises the stream. */
 nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets,
                            int32_t* d_src, int32_t* d_dst, int32_t* d_perm, void* stream);
+
+/* Internal vertex numbering of a NXG_BUILD_RELABEL build: d_new2old[k] (device,
+ * [n], caller-owned) receives the caller id of internal vertex k. The ids that
+ * nxg_dsss_export returns are internal ids. NXG_EINVAL if the handle was not
+ * relabeled. Synchronises the stream. */
+nxg_status nxg_dsss_vertex_map(const nxg_dsss* g, int32_t* d_new2old, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Iterations (Alg. 1 update model, synchronous per Sec. II-B)                */

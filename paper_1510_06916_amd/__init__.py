@@ -104,7 +104,7 @@ class DSSS:
     @classmethod
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
               value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
-              order="dst", stream=None):
+              order="dst", relabel=False, stream=None):
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -121,7 +121,8 @@ class DSSS:
         flags = ((_lib.NXG_BUILD_KEEP_PERM if keep_perm else 0) |
                  (_lib.NXG_BUILD_TRANSPOSE if transpose else 0) |
                  (_lib.NXG_BUILD_SYMMETRIZE if symmetrize else 0) |
-                 (_lib.NXG_BUILD_DEDUP if dedup else 0))
+                 (_lib.NXG_BUILD_DEDUP if dedup else 0) |
+                 (_lib.NXG_BUILD_RELABEL if relabel else 0))
         d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,
@@ -159,6 +160,13 @@ class DSSS:
     @property
     def m(self):
         return self.info()["m"]
+
+    def vertex_map(self):
+        """Caller id of every internal vertex (relabeled builds): int32 [n]."""
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _lib.check(_lib.lib().nxg_dsss_vertex_map(self._h, out.data_ptr(), _stream_handle()),
+                   "nxg_dsss_vertex_map")
+        return out
 
     def export(self, transposed=False, perm=False):
         """Offsets [P*P+1] (paper order j*P+i) and the stored edges in stream order."""
@@ -327,7 +335,7 @@ class MultiDSSS:
         self.sizes = sizes  # vertex counts
 
     @classmethod
-    def build(cls, graphs, interval=0, tile=0, chunk=0, stream=None):
+    def build(cls, graphs, interval=0, tile=0, chunk=0, order="dst", relabel=False, stream=None):
         """graphs: list of (src, dst, n) with int32 device tensors."""
         install_torch_allocator()
         keep = []
@@ -340,7 +348,9 @@ class MultiDSSS:
                                       d_src=src.data_ptr() if src.numel() else None,
                                       d_dst=dst.data_ptr() if dst.numel() else None,
                                       d_weight=None, interval=int(interval), tile=int(tile),
-                                      chunk=int(chunk), value_bytes=0, flags=0, order=0)
+                                      chunk=int(chunk), value_bytes=0,
+                                      flags=_lib.NXG_BUILD_RELABEL if relabel else 0,
+                                      order={"dst": _lib.NXG_ORDER_DST, "src": _lib.NXG_ORDER_SRC}[order])
         h = ctypes.c_void_p()
         dev = graphs[0][0].device
         with torch.cuda.device(dev):

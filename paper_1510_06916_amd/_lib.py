@@ -13,6 +13,7 @@ NXG_BUILD_KEEP_PERM = 0x1
 NXG_BUILD_TRANSPOSE = 0x2
 NXG_BUILD_SYMMETRIZE = 0x4
 NXG_BUILD_DEDUP = 0x8
+NXG_BUILD_RELABEL = 0x10
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
@@ -37,7 +38,7 @@ class DsssInfo(ctypes.Structure):
                 ("n_words", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("max_tile_edges", ctypes.c_int64), ("has_perm", ctypes.c_int32),
                 ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("relabeled", ctypes.c_int32)]
 
 
 class RunDesc(ctypes.Structure):
@@ -85,6 +86,7 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "nxg_dsss_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "nxg_dsss_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DsssInfo)]),
+    "nxg_dsss_vertex_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "nxg_dsss_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),

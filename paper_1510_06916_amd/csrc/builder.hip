@@ -520,6 +520,53 @@ int64_t dedup(DevBuf* kb, DevBuf* vb, int cur, int64_t m, hipStream_t s) {
     return mu;
 }
 
+// ---- vertex renumbering (NXG_BUILD_RELABEL) --------------------------------
+
+// Degree of every input id (out-degree; plus in-degree when both != 0). The
+// ids index the array, so they are validated here.
+__global__ void k_input_degree(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                               int64_t m, int32_t n, int both, uint32_t* __restrict__ deg,
+                               int32_t* __restrict__ err) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = src[e], d = dst[e];
+        if (s < 0 || s >= n || d < 0 || d >= n) {
+            atomicOr(err, 1);
+            continue;
+        }
+        atomicAdd(&deg[s], 1u);
+        if (both) atomicAdd(&deg[d], 1u);
+    }
+}
+
+// Sort keys of the new order: degree descending, then id ascending.
+__global__ void k_vertex_keys(const uint32_t* __restrict__ deg, int32_t n,
+                              uint64_t* __restrict__ keys) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        keys[v] = ((uint64_t)(0xFFFFFFFFu - deg[v]) << 32) | (uint64_t)v;
+}
+
+__global__ void k_vertex_maps(const uint64_t* __restrict__ sorted, int32_t n,
+                              int32_t* __restrict__ new2old, int32_t* __restrict__ old2new) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)(sorted[k] & 0xFFFFFFFFu);
+        new2old[k] = v;
+        old2new[v] = (int32_t)k;
+    }
+}
+
+__global__ void k_relabel_edges(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                int64_t m, const int32_t* __restrict__ old2new,
+                                int32_t* __restrict__ src2, int32_t* __restrict__ dst2) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        src2[e] = old2new[src[e]];
+        dst2[e] = old2new[dst[e]];
+    }
+}
+
 }  // namespace
 
 void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
@@ -702,6 +749,46 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
                            L.group_word.as<int64_t>(), L.P,
                            L.C, L.n_chunks, L.chunk_row.as<int32_t>(),
                            L.chunk_row_last.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipStreamSynchronize(s));
+}
+
+void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevBuf& old2new,
+                   DevBuf& src2, DevBuf& dst2) {
+    const int32_t n = d.n;
+    const int64_t m = d.m;
+    DevBuf deg, err, kb[2], vb[2];
+    deg.alloc(sizeof(uint32_t) * n, s);
+    err.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(deg.p, 0, sizeof(uint32_t) * n, s));
+    NXG_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_input_degree, dim3(grid_for(m)), dim3(256), 0, s, d.d_src, d.d_dst, m,
+                           n, (d.flags & NXG_BUILD_SYMMETRIZE) ? 1 : 0, deg.as<uint32_t>(),
+                           err.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+    }
+    int32_t herr = 0;
+    NXG_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    if (herr) fail(NXG_EINVAL, "edge id outside [0, n)");
+    kb[0].alloc(sizeof(uint64_t) * n, s);
+    kb[1].alloc(sizeof(uint64_t) * n, s);
+    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for(n)), dim3(256), 0, s, deg.as<uint32_t>(), n,
+                       kb[0].as<uint64_t>());
+    NXG_CHECK_LAUNCH();
+    const int cur = radix_sort(kb, vb, n, 64, s);
+    new2old.alloc(sizeof(int32_t) * n, s);
+    old2new.alloc(sizeof(int32_t) * n, s);
+    hipLaunchKernelGGL(k_vertex_maps, dim3(grid_for(n)), dim3(256), 0, s, kb[cur].as<uint64_t>(), n,
+                       new2old.as<int32_t>(), old2new.as<int32_t>());
+    NXG_CHECK_LAUNCH();
+    src2.alloc(sizeof(int32_t) * std::max<int64_t>(m, 1), s);
+    dst2.alloc(sizeof(int32_t) * std::max<int64_t>(m, 1), s);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_relabel_edges, dim3(grid_for(m)), dim3(256), 0, s, d.d_src, d.d_dst, m,
+                           old2new.as<int32_t>(), src2.as<int32_t>(), dst2.as<int32_t>());
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipStreamSynchronize(s));

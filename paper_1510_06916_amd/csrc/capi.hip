@@ -134,7 +134,7 @@ static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
             fail(NXG_EINVAL, "too many edges");
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
-                                  NXG_BUILD_DEDUP))
+                                  NXG_BUILD_DEDUP | NXG_BUILD_RELABEL))
             fail(NXG_EINVAL, "unknown build flag");
         if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
             fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
@@ -145,9 +145,17 @@ static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
             NXG_HIP(hipGetDevice(&g->device));
             g->value_bytes = d.value_bytes ? d.value_bytes : 8;
             g->flags = d.flags;
-            build_layout(d, false, s, g->fwd);
+            nxg_build_desc dd = d;
+            DevBuf src2, dst2;
+            if (d.flags & NXG_BUILD_RELABEL) {
+                relabel_input(d, s, g->new2old, g->old2new, src2, dst2);
+                g->relabeled = true;
+                dd.d_src = src2.as<int32_t>();
+                dd.d_dst = dst2.as<int32_t>();
+            }
+            build_layout(dd, false, s, g->fwd);
             if (d.flags & NXG_BUILD_TRANSPOSE) {
-                build_layout(d, true, s, g->rev);
+                build_layout(dd, true, s, g->rev);
                 g->has_rev = true;
             }
         } catch (...) {
@@ -186,11 +194,25 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
                                     &x->group_edge, &x->group_word, &x->perm, &x->weight, &x->outdeg})
                 bytes += (int64_t)b->bytes;
         }
+        bytes += (int64_t)(g->new2old.bytes + g->old2new.bytes);
         info->device_bytes = bytes;
+        info->relabeled = g->relabeled ? 1 : 0;
         info->has_perm = L.has_perm;
         info->has_weights = L.has_weight;
         info->has_transpose = g->has_rev;
         info->order = L.order;
+        return NXG_OK;
+    });
+}
+
+nxg_status nxg_dsss_vertex_map(const nxg_dsss* g, int32_t* d_new2old, void* stream) {
+    return guarded([&]() {
+        if (!g || !d_new2old) fail(NXG_EINVAL, "NULL argument");
+        if (!g->relabeled) fail(NXG_EINVAL, "the handle was built without NXG_BUILD_RELABEL");
+        hipStream_t s = (hipStream_t)stream;
+        NXG_HIP(hipMemcpyAsync(d_new2old, g->new2old.p, sizeof(int32_t) * g->fwd.n,
+                               hipMemcpyDeviceToDevice, s));
+        NXG_HIP(hipStreamSynchronize(s));
         return NXG_OK;
     });
 }

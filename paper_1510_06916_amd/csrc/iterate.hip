@@ -603,10 +603,13 @@ __global__ void k_init_bfs(int32_t n, int32_t root, int32_t* __restrict__ lev,
         act[x] = x == root / I ? 1 : 0;
 }
 
-__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, uint8_t* __restrict__ act, int P) {
+// Labels start as the vertex's caller id (its own id, or new2old[v] in a
+// relabeled build), so the fixed point is the minimum caller id of the component.
+__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, uint8_t* __restrict__ act, int P,
+                           const int32_t* __restrict__ ids) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
-        lab[v] = (int32_t)v;
+        lab[v] = ids ? ids[v] : (int32_t)v;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P;
          x += (int64_t)gridDim.x * blockDim.x)
         act[x] = 1;
@@ -760,6 +763,21 @@ __global__ __launch_bounds__(256) void k_edge_grad(
                 gw[perm[pos]] = (float)(d * xs[src] * lam[dst]);
             }
         }
+    }
+}
+
+// Vertex data between caller ids and the internal ids of a relabeled build:
+// out[k*w + c] = f * in[idx[k]*w + c]. idx = new2old brings caller data in,
+// idx = old2new hands results back.
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute_rows(const T* __restrict__ in,
+                                                      const int32_t* __restrict__ idx, int64_t n,
+                                                      int w, T f, T* __restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n * w;
+         x += (int64_t)gridDim.x * 256) {
+        const int64_t k = x / w;
+        const int64_t c = x - k * w;
+        out[x] = f * in[(int64_t)idx[k] * w + c];
     }
 }
 
@@ -1093,7 +1111,33 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
 struct Workspace {
     DevBuf buf[2], partial, tile_ctr, all_ctr, tile_s, tile_flag, stats, done, act, apref, clist,
         ccount, part, bfsout;
+    DevBuf mtele, mvals, mseeds, mgx, mxs;  // caller data in internal ids (relabeled builds)
 };
+
+// Index arrays of a relabeled build (both NULL otherwise).
+struct VMap {
+    const int32_t* n2o = nullptr;
+    const int32_t* o2n = nullptr;
+    explicit operator bool() const { return n2o != nullptr; }
+};
+
+VMap vmap_of(const nxg_dsss* g) {
+    VMap m;
+    if (g->relabeled) {
+        m.n2o = g->new2old.as<int32_t>();
+        m.o2n = g->old2new.as<int32_t>();
+    }
+    return m;
+}
+
+template <typename T>
+void permute_rows(const T* in, const int32_t* idx, int64_t n, int w, T* out, hipStream_t s,
+                  T f = (T)1) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_permute_rows<T>, dim3(grid_for(n * w, 256, 8192)), dim3(256), 0, s, in, idx,
+                       n, w, f, out);
+    NXG_CHECK_LAUNCH();
+}
 
 template <class Prog, int WG>
 void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, int n_items, size_t lds,
@@ -1183,12 +1227,21 @@ void prepare_iter(size_t lds) {
 // Enqueues x^0 and max_iters iterations of (weighted) PageRank; no syncs.
 template <typename V>
 void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_run_desc& d,
-                      bool weighted, hipStream_t s) {
+                      bool weighted, const VMap& vm, hipStream_t s) {
     const int nb = grid_for(L.n, 256, 1024);
-    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? (const V*)d.d_values : nullptr;
+    const V* tele = (const V*)d.d_teleport;
+    V* vals = (V*)d.d_values;
+    if (vm) {
+        if (tele) {
+            permute_rows<V>(tele, vm.n2o, L.n, 1, w.mtele.as<V>(), s);
+            tele = w.mtele.as<V>();
+        }
+        if (d.flags & NXG_RUN_WARM_START) permute_rows<V>(vals, vm.n2o, L.n, 1, w.mvals.as<V>(), s);
+        vals = w.mvals.as<V>();
+    }
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? vals : nullptr;
     hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
-                       (const V*)d.d_teleport, x0, weighted ? 0 : 1, w.buf[0].as<V>(),
-                       w.part.as<double>());
+                       tele, x0, weighted ? 0 : 1, w.buf[0].as<V>(), w.part.as<double>());
     NXG_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
                        w.stats.as<double>());
@@ -1200,18 +1253,19 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
         Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
         const V* cur = w.buf[k & 1].as<V>();
         V* nxt = w.buf[(k + 1) & 1].as<V>();
-        V* xout = (k == d.max_iters - 1) ? (V*)d.d_values : nullptr;
+        V* xout = (k == d.max_iters - 1) ? vals : nullptr;
         if (weighted) {
-            ProgPRW<V> pr{cur, nxt, (const V*)d.d_teleport, xout, L.weight.as<float>(), d.damping};
+            ProgPRW<V> pr{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
             hipLaunchKernelGGL((k_iterate<ProgPRW<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
                                ctl, pr);
         } else {
-            ProgPR<V> pr{cur, nxt, (const V*)d.d_teleport, xout, d.damping};
+            ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
             hipLaunchKernelGGL((k_iterate<ProgPR<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
                                ctl, pr);
         }
         NXG_CHECK_LAUNCH();
     }
+    if (vm) permute_rows<V>(vals, vm.o2n, L.n, 1, (V*)d.d_values, s);
 }
 
 template <typename V>
@@ -1247,6 +1301,11 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         w.buf[0].alloc(sizeof(V) * L.n, s);
         w.buf[1].alloc(sizeof(V) * L.n, s);
         w.part.alloc(sizeof(double) * grid_for(L.n, 256, 1024), s);
+        const VMap vm = vmap_of(g);
+        if (vm) {
+            w.mvals.alloc(sizeof(V) * L.n, s);
+            if (d.d_teleport) w.mtele.alloc(sizeof(V) * L.n, s);
+        }
         const size_t lds = (size_t)L.T * sizeof(double);
         if (weighted)
             prepare_iter<ProgPRW<V>, 1024>(lds);
@@ -1258,7 +1317,7 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         hipStream_t cs = g->capture_stream;
         NXG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_pagerank<V>(L, *p, w, d, weighted, cs);
+            enqueue_pagerank<V>(L, *p, w, d, weighted, vm, cs);
         } catch (...) {
             hipGraph_t dead = nullptr;
             (void)hipStreamEndCapture(cs, &dead);
@@ -1317,10 +1376,23 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     w.buf[1].alloc(vb * L.n, s);
     const int nb = grid_for(L.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
-    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? (const V*)d.d_values : nullptr;
-    hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
-                       (const V*)d.d_teleport, x0, weighted ? 0 : 1, w.buf[0].as<V>(),
-                       w.part.as<double>());
+    // a relabeled build works on copies in internal ids
+    const VMap vm = vmap_of(g);
+    const V* tele = (const V*)d.d_teleport;
+    V* vals = (V*)d.d_values;
+    if (vm) {
+        w.mvals.alloc(vb * L.n, s);
+        if (tele) {
+            w.mtele.alloc(vb * L.n, s);
+            permute_rows<V>(tele, vm.n2o, L.n, 1, w.mtele.as<V>(), s);
+            tele = w.mtele.as<V>();
+        }
+        if (d.flags & NXG_RUN_WARM_START) permute_rows<V>(vals, vm.n2o, L.n, 1, w.mvals.as<V>(), s);
+        vals = w.mvals.as<V>();
+    }
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? vals : nullptr;
+    hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(), tele,
+                       x0, weighted ? 0 : 1, w.buf[0].as<V>(), w.part.as<double>());
     NXG_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
                        w.stats.as<double>());
@@ -1341,12 +1413,12 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             const V* cur = w.buf[k & 1].as<V>();
             V* nxt = w.buf[(k + 1) & 1].as<V>();
-            V* xout = (k == max_iters - 1) ? (V*)d.d_values : nullptr;
+            V* xout = (k == max_iters - 1) ? vals : nullptr;
             if (weighted) {
-                ProgPRW<V> pr{cur, nxt, (const V*)d.d_teleport, xout, L.weight.as<float>(), d.damping};
+                ProgPRW<V> pr{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
                 launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, n_items, lds, s);
             } else {
-                ProgPR<V> pr{cur, nxt, (const V*)d.d_teleport, xout, d.damping};
+                ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
                 launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
             }
         }
@@ -1360,17 +1432,18 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         // converged early (or no iteration asked): the newest vector is buf[k & 1]
         const V* cur = w.buf[k & 1].as<V>();
         if (weighted) {
-            hipLaunchKernelGGL(k_copy<V>, dim3(grid_for(L.n)), dim3(256), 0, s, cur, (V*)d.d_values,
+            hipLaunchKernelGGL(k_copy<V>, dim3(grid_for(L.n)), dim3(256), 0, s, cur, vals,
                                (int64_t)L.n);
         } else {
             // x = gathered value * outdeg; reuse the carry-over path of the kernel
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
-            ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, (V*)d.d_values, d.damping};
+            ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, vals, d.damping};
             NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
             launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
         }
         NXG_CHECK_LAUNCH();
     }
+    if (vm) permute_rows<V>(vals, vm.o2n, L.n, 1, (V*)d.d_values, s);
     NXG_HIP(hipEventRecord(e1, s));
     nxg_status rc = NXG_OK;
     if (st || d.tol > 0) {
@@ -1418,6 +1491,12 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         if (d.batch != 1) fail(NXG_EUNSUPPORTED, "BFS runs one root per call");
         if (d.roots[0] < 0 || d.roots[0] >= L.n) fail(NXG_EINVAL, "BFS root outside [0, n)");
     }
+    const VMap vm = vmap_of(g);
+    int32_t root = bfs ? d.roots[0] : 0;
+    if (bfs && vm) {
+        NXG_HIP(hipMemcpyAsync(&root, vm.o2n + root, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+    }
     if ((size_t)L.T * 4 > (size_t)lds_budget_bytes(g->device)) fail(NXG_EINVAL, "tile does not fit in LDS");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
@@ -1435,10 +1514,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     uint8_t* act0 = w.act.as<uint8_t>();
     if (bfs)
         hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
-                           s, L.n, d.roots[0], w.buf[0].as<int32_t>(), act0, L.P, L.I);
+                           s, L.n, root, w.buf[0].as<int32_t>(), act0, L.P, L.I);
     else
         hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
-                           s, L.n, w.buf[0].as<int32_t>(), act0, L.P);
+                           s, L.n, w.buf[0].as<int32_t>(), act0, L.P, vm.n2o);
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w);
     geo.clist = w.clist.as<int64_t>();
@@ -1491,8 +1570,11 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     }
     // the values after round k live in buf[k & 1]; rounds past the fixed point copy
     NXG_HIP(hipEventRecord(e1, s));
-    hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s,
-                       w.buf[k & 1].as<int32_t>(), (int32_t*)d.d_values, (int64_t)L.n);
+    if (vm)
+        permute_rows<int32_t>(w.buf[k & 1].as<int32_t>(), vm.o2n, L.n, 1, (int32_t*)d.d_values, s);
+    else
+        hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s,
+                           w.buf[k & 1].as<int32_t>(), (int32_t*)d.d_values, (int64_t)L.n);
     NXG_CHECK_LAUNCH();
     int32_t mx = 0;
     unsigned long long reached = 0;
@@ -1559,6 +1641,26 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     w.buf[0].alloc(sizeof(float) * (size_t)L.n * B, s);
     w.buf[1].alloc(sizeof(float) * (size_t)L.n * B, s);
     const int32_t* seeds = d.d_seeds;
+    if (seeds) {
+        // seeds index the vertex arrays (and the id map of a relabeled build)
+        int32_t hseed[64];
+        NXG_HIP(hipMemcpyAsync(hseed, seeds, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < B; ++b)
+            if (hseed[b] < 0 || hseed[b] >= L.n) fail(NXG_EINVAL, "seed vertex outside [0, n)");
+    }
+    const VMap vm = vmap_of(g);
+    float* vals = (float*)d.d_values;
+    if (vm) {
+        // seeds to internal ids; the result rows come back through old2new
+        if (seeds) {
+            w.mseeds.alloc(sizeof(int32_t) * B, s);
+            permute_rows<int32_t>(vm.o2n, seeds, B, 1, w.mseeds.as<int32_t>(), s);
+            seeds = w.mseeds.as<int32_t>();
+        }
+        w.mvals.alloc(sizeof(float) * (size_t)L.n * B, s);
+        vals = w.mvals.as<float>();
+    }
     hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, s,
                        L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
     NXG_CHECK_LAUNCH();
@@ -1583,7 +1685,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         const int kend = std::min(max_iters, k + block);
         for (; k < kend; ++k) {
             BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
-            float* xout = (k == max_iters - 1) ? (float*)d.d_values : nullptr;
+            float* xout = (k == max_iters - 1) ? vals : nullptr;
             hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl,
                                w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout, seeds,
                                B, d.damping, w.tile_s.as<double>());
@@ -1600,10 +1702,11 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
         BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
         hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl,
-                           w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(),
-                           (float*)d.d_values, seeds, B, d.damping, w.tile_s.as<double>());
+                           w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), vals, seeds, B,
+                           d.damping, w.tile_s.as<double>());
         NXG_CHECK_LAUNCH();
     }
+    if (vm) permute_rows<float>(vals, vm.o2n, L.n, B, (float*)d.d_values, s);
     NXG_HIP(hipEventRecord(e1, s));
     std::vector<double> hs(nstat);
     NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
@@ -1693,6 +1796,10 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         m.buf0 = w.buf[0].as<float>();
         m.buf1 = w.buf[1].as<float>();
         m.xout = (float*)d_values[i];
+        if (g->relabeled) {
+            w.mvals.alloc(sizeof(float) * L.n, s);
+            m.xout = w.mvals.as<float>();
+        }
         m.done0 = w.done.as<int32_t>();
         m.item_base = (int32_t)all_items.size();
         m.n_items = (int32_t)p->h_items.size();
@@ -1722,6 +1829,12 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
                            ddesc.as<MultiGraph>(), G, dprefix.as<int32_t>(), ditems.as<Item>(), k,
                            iters, d.damping);
         NXG_CHECK_LAUNCH();
+    }
+    for (int i = 0; i < G; ++i) {
+        const VMap vm = vmap_of(mg->graphs[i]);
+        if (vm)
+            permute_rows<float>(ws[i].mvals.as<float>(), vm.o2n, mg->graphs[i]->fwd.n, 1,
+                                (float*)d_values[i], s);
     }
     NXG_HIP(hipEventRecord(e1, s));
     NXG_HIP(hipStreamSynchronize(s));
@@ -1767,7 +1880,19 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     w.buf[1].alloc(sizeof(double) * R.n, s);
     const int nb = grid_for(R.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
-    hipLaunchKernelGGL(k_init_adj, dim3(nb), dim3(256), 0, s, R.n, d.d_gx, w.buf[0].as<double>(),
+    // a relabeled build works on x* and g in internal ids
+    const VMap vm = vmap_of(g);
+    const double* gx = d.d_gx;
+    const double* xs = d.d_xstar;
+    if (vm) {
+        w.mgx.alloc(sizeof(double) * R.n, s);
+        w.mxs.alloc(sizeof(double) * R.n, s);
+        permute_rows<double>(gx, vm.n2o, R.n, 1, w.mgx.as<double>(), s);
+        permute_rows<double>(xs, vm.n2o, R.n, 1, w.mxs.as<double>(), s);
+        gx = w.mgx.as<double>();
+        xs = w.mxs.as<double>();
+    }
+    hipLaunchKernelGGL(k_init_adj, dim3(nb), dim3(256), 0, s, R.n, gx, w.buf[0].as<double>(),
                        w.part.as<double>());
     NXG_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
@@ -1788,7 +1913,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
         const int kend = std::min(max_iters, k + block);
         for (; k < kend; ++k) {
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, tol};
-            ProgADJ pr{w.buf[k & 1].as<double>(), w.buf[(k + 1) & 1].as<double>(), d.d_gx, nullptr,
+            ProgADJ pr{w.buf[k & 1].as<double>(), w.buf[(k + 1) & 1].as<double>(), gx, nullptr,
                        R.weight.as<float>(), d.damping};
             launch_iter<ProgADJ, 1024>(geo, ctl, pr, n_items, lds, s);
         }
@@ -1799,19 +1924,24 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
         }
     }
     const double* lam = w.buf[k & 1].as<double>();
-    if (d.d_lambda)
-        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0, d.d_lambda,
-                           (int64_t)R.n);
-    if (d.d_gt)
-        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0 - d.damping,
-                           d.d_gt, (int64_t)R.n);
+    if (vm) {
+        if (d.d_lambda) permute_rows<double>(lam, vm.o2n, R.n, 1, d.d_lambda, s);
+        if (d.d_gt) permute_rows<double>(lam, vm.o2n, R.n, 1, d.d_gt, s, 1.0 - d.damping);
+    } else {
+        if (d.d_lambda)
+            hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0,
+                               d.d_lambda, (int64_t)R.n);
+        if (d.d_gt)
+            hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam,
+                               1.0 - d.damping, d.d_gt, (int64_t)R.n);
+    }
     NXG_CHECK_LAUNCH();
     if (d.d_gw && F.n_chunks > 0) {
         hipLaunchKernelGGL(k_edge_grad, dim3(grid_for(F.n_chunks * 64, 256, 16384)), dim3(256), 0, s,
                            F.words.as<uint32_t>(), F.chunk_row.as<int32_t>(),
                            F.tile_chunk.as<int64_t>(), F.n_tiles, F.n_chunks, F.C, F.I, F.L, F.t,
                            F.order == NXG_ORDER_SRC ? F.t : 0, F.order == NXG_ORDER_SRC ? 0 : F.L,
-                           F.perm.as<int32_t>(), d.d_xstar, lam, d.damping, d.d_gw);
+                           F.perm.as<int32_t>(), xs, lam, d.damping, d.d_gw);
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipEventRecord(e1, s));

@@ -148,6 +148,10 @@ struct nxg_dsss {
     nxg::Layout fwd;
     nxg::Layout rev;  // reversed graph (NXG_BUILD_TRANSPOSE)
     bool has_rev = false;
+    // NXG_BUILD_RELABEL: both layouts use internal ids; new2old[k] is the caller
+    // id of internal vertex k, old2new the inverse
+    bool relabeled = false;
+    nxg::DevBuf new2old, old2new;
     // cached iteration plans, keyed by piece size
     std::vector<nxg::Plan*> plans;
     // captured runs (hipGraph + workspace), see NXG_RUN_CAPTURE, recorded on a
@@ -169,6 +173,9 @@ namespace nxg {
 void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& out);
 void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
                    int32_t* d_perm, hipStream_t s);
+// validates the ids, orders the vertices by decreasing degree and renames the edges
+void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevBuf& old2new,
+                   DevBuf& src2, DevBuf& dst2);
 // runtime entry (iterate.hip)
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
