@@ -25,6 +25,9 @@ namespace {
 
 constexpr uint32_t kMarker = 0x80000000u;
 constexpr int32_t kInf = INT32_MAX;
+constexpr int kWinBytes = 1024;  // LDS window slot of one wavefront (source-major streams)
+constexpr int kValPad = 256;     // vertex-value buffers hold n + kValPad elements so a
+                                 // window that starts near n stays inside them
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -39,6 +42,12 @@ struct Geo {
     const int32_t* deg;
     int32_t n, I, P, L, T, t, n_tiles, C;
     int32_t sshift, dshift;  // bit offsets of the source and destination fields
+    int32_t order;           // NXG_ORDER_* of the stream
+    // source windows of a source-major stream: chunk_sbase[c] >= 0 names the
+    // first source of chunk c's window; win_on enables the window path and
+    // win_off is the byte offset of the per-wave window slots in LDS
+    const int32_t* chunk_sbase;
+    int32_t win_on, win_off;
     // two-phase partials
     void* partial;
     int32_t* tile_ctr;
@@ -71,6 +80,7 @@ struct Ctl {
 template <typename V>
 struct ProgPR {
     using acc_t = double;
+    using val_t = V;
     static constexpr bool kSum = true, kWeights = false, kActivity = false;
     const V* cur;
     V* nxt;
@@ -78,7 +88,8 @@ struct ProgPR {
     V* xout;         // nullable: write x on this iteration
     double d;
     __device__ acc_t identity() const { return (acc_t)0; }
-    __device__ acc_t gather(uint32_t src, float) const { return (acc_t)cur[src]; }
+    __device__ acc_t from_val(V v, float) const { return (acc_t)v; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
     // sv[0]: dangling mass of x^{k+1}; sv[1]: |x^{k+1} - x^k|_1; sv[2]: sum of x^{k+1}
@@ -105,6 +116,7 @@ struct ProgPR {
 template <typename V>
 struct ProgPRW {
     using acc_t = double;
+    using val_t = V;
     static constexpr bool kSum = true, kWeights = true, kActivity = false;
     const V* cur;
     V* nxt;
@@ -113,7 +125,8 @@ struct ProgPRW {
     const float* w;  // [n_words] weights in stream order
     double d;
     __device__ acc_t identity() const { return (acc_t)0; }
-    __device__ acc_t gather(uint32_t src, float we) const { return (acc_t)we * (acc_t)cur[src]; }
+    __device__ acc_t from_val(V v, float we) const { return (acc_t)we * (acc_t)v; }
+    __device__ acc_t gather(uint32_t src, float we) const { return from_val(cur[src], we); }
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
     __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
@@ -137,6 +150,7 @@ struct ProgPRW {
 // BFS (Alg. 3): a reached source offers level + 1; min-reduce.
 struct ProgBFS {
     using acc_t = int32_t;
+    using val_t = int32_t;
     static constexpr bool kSum = false, kWeights = false, kActivity = true;
     const int32_t* cur;
     int32_t* nxt;
@@ -144,10 +158,8 @@ struct ProgBFS {
     uint8_t* act_nxt;    // [P] intervals updated in this round
     int32_t P, I;
     __device__ acc_t identity() const { return kInf; }
-    __device__ acc_t gather(uint32_t src, float) const {
-        int32_t l = cur[src];
-        return l == kInf ? kInf : l + 1;
-    }
+    __device__ acc_t from_val(int32_t l, float) const { return l == kInf ? kInf : l + 1; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
     __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
     static __device__ bool converged(double, double, double) { return false; }
     __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
@@ -166,6 +178,7 @@ struct ProgBFS {
 // WCC by min-label propagation on the symmetrised graph.
 struct ProgWCC {
     using acc_t = int32_t;
+    using val_t = int32_t;
     static constexpr bool kSum = false, kWeights = false, kActivity = true;
     const int32_t* cur;
     int32_t* nxt;
@@ -173,7 +186,8 @@ struct ProgWCC {
     uint8_t* act_nxt;
     int32_t P, I;
     __device__ acc_t identity() const { return kInf; }
-    __device__ acc_t gather(uint32_t src, float) const { return cur[src]; }
+    __device__ acc_t from_val(int32_t l, float) const { return l; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
     __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
     static __device__ bool converged(double, double, double) { return false; }
     __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
@@ -197,6 +211,7 @@ struct ProgWCC {
 // sv[1] = |lambda' - lambda|_1, sv[2] = |lambda'|_1 (relative stopping test).
 struct ProgADJ {
     using acc_t = double;
+    using val_t = double;
     static constexpr bool kSum = true, kWeights = true, kActivity = false;
     const double* cur;
     double* nxt;
@@ -205,7 +220,8 @@ struct ProgADJ {
     const float* w;
     double d;
     __device__ acc_t identity() const { return 0.0; }
-    __device__ acc_t gather(uint32_t src, float we) const { return (double)we * cur[src]; }
+    __device__ acc_t from_val(double v, float we) const { return (double)we * v; }
+    __device__ acc_t gather(uint32_t src, float we) const { return from_val(cur[src], we); }
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double resid, double norm, double tol) {
         return resid <= tol * norm;
@@ -309,109 +325,239 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
         c_hi = cnt * (it.piece + 1) / it.npieces;
     }
 
-    // A wave step covers kU sub-blocks of 256 words (64 lanes x 4 consecutive
-    // words, one 16-byte load each): all word loads of the step are issued
-    // first, then all gathers, then the LDS reductions, so each lane keeps up to
-    // 4 * kU independent gathers in flight.
-    constexpr int kU = 4;
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    for (int64_t ci = c_lo + wave; ci < c_hi; ci += WG / 64) {
-        const int64_t c = list ? list[ci] : ci;
-        uint32_t row = (uint32_t)g.chunk_row[c];
-        const u32x4* wp = reinterpret_cast<const u32x4*>(g.words + c * (int64_t)g.C);
-        const f32x4* wwp = nullptr;
-        if constexpr (Prog::kWeights)
-            wwp = reinterpret_cast<const f32x4*>(prog.w + c * (int64_t)g.C);
-        for (int s = 0; s < steps; s += kU) {
-            uint32_t wd[kU * 4];
-            float wf[kU * 4];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                u32x4 w4 = {kNone, kNone, kNone, kNone};  // padding words
-                if (s + u < steps) w4 = __builtin_nontemporal_load(wp + (s + u) * 64 + lane);
-                wd[4 * u + 0] = w4.x;
-                wd[4 * u + 1] = w4.y;
-                wd[4 * u + 2] = w4.z;
-                wd[4 * u + 3] = w4.w;
-                if constexpr (Prog::kWeights) {
-                    f32x4 f4 = {0.f, 0.f, 0.f, 0.f};
-                    if (s + u < steps) f4 = __builtin_nontemporal_load(wwp + (s + u) * 64 + lane);
-                    wf[4 * u + 0] = f4.x;
-                    wf[4 * u + 1] = f4.y;
-                    wf[4 * u + 2] = f4.z;
-                    wf[4 * u + 3] = f4.w;
-                } else {
-                    wf[4 * u + 0] = wf[4 * u + 1] = wf[4 * u + 2] = wf[4 * u + 3] = 0.f;
-                }
-            }
-            // decode: source index and destination (kNone for markers, padding and
-            // edges out of inactive source intervals)
-            uint32_t sidx[kU * 4], dl[kU * 4];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const uint32_t* w = wd + 4 * u;
-                const uint64_t mm = __ballot(((w[0] | w[1] | w[2] | w[3]) >> 31) != 0);
-                if (mm == 0) {
-                    // whole sub-block inside one source interval (uniform)
-                    const uint32_t rb = row * (uint32_t)g.I;
-                    const bool on = prog.row_active(row);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
-                        dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
+    if (g.order != NXG_ORDER_SRC) {
+        // A wave step covers kU sub-blocks of 256 words (64 lanes x 4 consecutive
+        // words, one 16-byte load each): all word loads of the step are issued
+        // first, then all gathers, then the LDS reductions, so each lane keeps up to
+        // 4 * kU independent gathers in flight.
+        constexpr int kU = 4;
+        for (int64_t ci = c_lo + wave; ci < c_hi; ci += WG / 64) {
+            const int64_t c = list ? list[ci] : ci;
+            uint32_t row = (uint32_t)g.chunk_row[c];
+            const u32x4* wp = reinterpret_cast<const u32x4*>(g.words + c * (int64_t)g.C);
+            const f32x4* wwp = nullptr;
+            if constexpr (Prog::kWeights)
+                wwp = reinterpret_cast<const f32x4*>(prog.w + c * (int64_t)g.C);
+            for (int s = 0; s < steps; s += kU) {
+                uint32_t wd[kU * 4];
+                float wf[kU * 4];
+    #pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    u32x4 w4 = {kNone, kNone, kNone, kNone};  // padding words
+                    if (s + u < steps) w4 = __builtin_nontemporal_load(wp + (s + u) * 64 + lane);
+                    wd[4 * u + 0] = w4.x;
+                    wd[4 * u + 1] = w4.y;
+                    wd[4 * u + 2] = w4.z;
+                    wd[4 * u + 3] = w4.w;
+                    if constexpr (Prog::kWeights) {
+                        f32x4 f4 = {0.f, 0.f, 0.f, 0.f};
+                        if (s + u < steps) f4 = __builtin_nontemporal_load(wwp + (s + u) * 64 + lane);
+                        wf[4 * u + 0] = f4.x;
+                        wf[4 * u + 1] = f4.y;
+                        wf[4 * u + 2] = f4.z;
+                        wf[4 * u + 3] = f4.w;
+                    } else {
+                        wf[4 * u + 0] = wf[4 * u + 1] = wf[4 * u + 2] = wf[4 * u + 3] = 0.f;
                     }
-                } else {
-                    uint32_t last = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (w[k] & kMarker) last = w[k] & ~kMarker;
-                    const uint64_t prev = mm & lt;
-                    const int from = prev ? 63 - __clzll(prev) : lane;
-                    const uint32_t got = __shfl(last, from);
-                    uint32_t r = prev ? got : row;
-                    row = __shfl(last, 63 - __clzll(mm));
-                    uint32_t rb = r * (uint32_t)g.I;
-                    bool on = prog.row_active(r);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        if (w[k] & kMarker) {
-                            r = w[k] & ~kMarker;
-                            rb = r * (uint32_t)g.I;
-                            on = prog.row_active(r);
-                            sidx[4 * u + k] = 0;
-                            dl[4 * u + k] = kNone;
-                        } else {
+                }
+                // decode: source index and destination (kNone for markers, padding and
+                // edges out of inactive source intervals)
+                uint32_t sidx[kU * 4], dl[kU * 4];
+    #pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const uint32_t* w = wd + 4 * u;
+                    const uint64_t mm = __ballot(((w[0] | w[1] | w[2] | w[3]) >> 31) != 0);
+                    if (mm == 0) {
+                        // whole sub-block inside one source interval (uniform)
+                        const uint32_t rb = row * (uint32_t)g.I;
+                        const bool on = prog.row_active(row);
+    #pragma unroll
+                        for (int k = 0; k < 4; ++k) {
                             sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
                             dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
                         }
+                    } else {
+                        uint32_t last = 0;
+    #pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (w[k] & kMarker) last = w[k] & ~kMarker;
+                        const uint64_t prev = mm & lt;
+                        const int from = prev ? 63 - __clzll(prev) : lane;
+                        const uint32_t got = __shfl(last, from);
+                        uint32_t r = prev ? got : row;
+                        row = __shfl(last, 63 - __clzll(mm));
+                        uint32_t rb = r * (uint32_t)g.I;
+                        bool on = prog.row_active(r);
+    #pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (w[k] & kMarker) {
+                                r = w[k] & ~kMarker;
+                                rb = r * (uint32_t)g.I;
+                                on = prog.row_active(r);
+                                sidx[4 * u + k] = 0;
+                                dl[4 * u + k] = kNone;
+                            } else {
+                                sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
+                                dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
+                            }
+                        }
                     }
                 }
+                acc_t val[kU * 4];
+    #pragma unroll
+                for (int k = 0; k < kU * 4; ++k)
+                    val[k] = dl[k] != kNone ? prog.gather(sidx[k], wf[k]) : prog.identity();
+                // reduce: merge runs of equal destination inside the lane's 4 words
+    #pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    uint32_t pd = kNone;
+                    acc_t pv = prog.identity();
+    #pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t d = dl[4 * u + k];
+                        if (d == kNone) continue;
+                        if (d == pd) {
+                            pv = combine<Prog::kSum>(pv, val[4 * u + k]);
+                        } else {
+                            if (pd != kNone && (Prog::kSum || pv != prog.identity()))
+                                lds_combine(&acc[pd], pv, Prog::kSum);
+                            pd = d;
+                            pv = val[4 * u + k];
+                        }
+                    }
+                    if (pd != kNone && (Prog::kSum || pv != prog.identity()))
+                        lds_combine(&acc[pd], pv, Prog::kSum);
+                }
             }
-            acc_t val[kU * 4];
+        }
+    } else {
+        // Source-major groups. Load k of a lane reads word 64k + lane of a 256-word
+        // sub-block, so each gather serves 64 consecutive edges, whose sources
+        // are adjacent. A chunk whose edges mostly come from the window of
+        // kWinBytes of values starting at chunk_sbase[c] first copies that window
+        // into this wave's LDS slot (one 16-byte load per lane) and gathers from
+        // there. The next step's words (and window) are loaded before this
+        // step's LDS reductions, so their latency overlaps the gathers'.
+        using val_t = typename Prog::val_t;
+        // 16 edges per lane and step; 8 when weights or 8-byte values need the registers
+        constexpr int kU = (Prog::kWeights || sizeof(val_t) > 4) ? 2 : 4, kQ = 4 * kU;
+        constexpr uint32_t W = kWinBytes / sizeof(val_t);
+        val_t* win = reinterpret_cast<val_t*>(smem + g.win_off + wave * kWinBytes);
+        int64_t ci = c_lo + wave;
+        int s = 0;
+        uint32_t wd[kQ];
+        float wf[kQ];
+        u32x4 wv = {0u, 0u, 0u, 0u};
+        int32_t wb = -1;
+        auto fetch = [&](int64_t ci_, int s_, uint32_t* wo, float* fo) {
+            const int64_t c_ = list ? list[ci_] : ci_;
+            const int64_t base = c_ * (int64_t)g.C + (int64_t)s_ * 256 + lane;
 #pragma unroll
-            for (int k = 0; k < kU * 4; ++k)
-                val[k] = dl[k] != kNone ? prog.gather(sidx[k], wf[k]) : prog.identity();
-            // reduce: merge runs of equal destination inside the lane's 4 words
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                uint32_t pd = kNone;
-                acc_t pv = prog.identity();
+            for (int u = 0; u < kU; ++u)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const uint32_t d = dl[4 * u + k];
-                    if (d == kNone) continue;
-                    if (d == pd) {
-                        pv = combine<Prog::kSum>(pv, val[4 * u + k]);
-                    } else {
-                        if (pd != kNone && (Prog::kSum || pv != prog.identity()))
-                            lds_combine(&acc[pd], pv, Prog::kSum);
-                        pd = d;
-                        pv = val[4 * u + k];
+                    const bool in = s_ + u < steps;
+                    wo[4 * u + k] =
+                        in ? __builtin_nontemporal_load(g.words + base + u * 256 + k * 64) : kNone;
+                    if constexpr (Prog::kWeights)
+                        fo[4 * u + k] =
+                            in ? __builtin_nontemporal_load(prog.w + base + u * 256 + k * 64) : 0.f;
+                    else
+                        fo[4 * u + k] = 0.f;
+                }
+        };
+        auto fetch_win = [&](int64_t ci_, u32x4& v, int32_t& b) {
+            b = -1;
+            if (g.win_on) {
+                const int64_t c_ = list ? list[ci_] : ci_;
+                b = g.chunk_sbase[c_];
+                if (b >= 0) v = reinterpret_cast<const u32x4*>(prog.cur + b)[lane];
+            }
+        };
+        uint32_t row = 0;
+        if (ci < c_hi) {
+            fetch(ci, 0, wd, wf);
+            fetch_win(ci, wv, wb);
+            row = (uint32_t)g.chunk_row[list ? list[ci] : ci];
+        }
+        while (ci < c_hi) {
+            int64_t nci = ci;
+            int ns = s + kU;
+            if (ns >= steps) {
+                nci = ci + WG / 64;
+                ns = 0;
+            }
+            if (s == 0 && wb >= 0) reinterpret_cast<u32x4*>(win)[lane] = wv;
+            // decode in edge order: source index, destination (kNone for markers,
+            // padding and edges out of inactive source intervals)
+            uint32_t sidx[kQ], dl[kQ];
+            bool far = false;
+            const uint32_t wbase = (uint32_t)wb;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const uint32_t w = wd[q];
+                const uint64_t mm = __ballot((w >> 31) != 0);
+                uint32_t r = row;
+                if (mm) {
+                    const uint64_t upto = mm & (lt | (1ull << lane));
+                    const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
+                    r = upto ? got : row;
+                    row = __shfl(w & ~kMarker, 63 - __clzll(mm));
+                }
+                const bool edge = (w >> 31) == 0 && prog.row_active(r);
+                sidx[q] = edge ? r * (uint32_t)g.I + ((w >> g.sshift) & lmask) : 0u;
+                dl[q] = edge ? ((w >> g.dshift) & tmask) : kNone;
+                far |= edge && !(wb >= 0 && sidx[q] - wbase < W);
+            }
+            val_t raw[kQ];
+            if (__ballot(far) == 0) {
+                // every edge of the step reads the LDS window
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    if (dl[q] != kNone) raw[q] = win[sidx[q] - wbase];
+            } else {
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    if (dl[q] != kNone) {
+                        const uint32_t off = sidx[q] - wbase;
+                        if (wb >= 0 && off < W)
+                            raw[q] = win[off];
+                        else
+                            raw[q] = prog.cur[sidx[q]];
                     }
                 }
-                if (pd != kNone && (Prog::kSum || pv != prog.identity()))
-                    lds_combine(&acc[pd], pv, Prog::kSum);
             }
+            uint32_t wn[kQ];
+            float fn[kQ];
+            u32x4 wvn = wv;
+            int32_t wbn = wb;
+            const bool more = nci < c_hi;
+            if (more) {
+                fetch(nci, ns, wn, fn);
+                if (ns == 0) fetch_win(nci, wvn, wbn);
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                if (dl[q] != kNone) {
+                    const acc_t v = prog.from_val(raw[q], wf[q]);
+                    if (Prog::kSum || v != prog.identity()) lds_combine(&acc[dl[q]], v, Prog::kSum);
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    wd[q] = wn[q];
+                    wf[q] = fn[q];
+                }
+                if (ns == 0) {
+                    row = (uint32_t)g.chunk_row[list ? list[nci] : nci];
+                    wv = wvn;
+                    wb = wbn;
+                }
+            }
+            ci = nci;
+            s = ns;
         }
     }
     __syncthreads();
@@ -1152,7 +1298,8 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, int n_items, 
     NXG_CHECK_LAUNCH();
 }
 
-Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
+// ab = bytes of one LDS accumulator of the program.
+Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     Geo g;
     g.words = L.words.as<uint32_t>();
     g.chunk_row = L.chunk_row.as<int32_t>();
@@ -1167,6 +1314,14 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
     g.t = L.t;
     g.sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
     g.dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
+    g.order = L.order;
+    g.chunk_sbase = L.chunk_sbase.as<int32_t>();
+    g.win_off = (int32_t)(((size_t)L.T * ab + 15) & ~(size_t)15);
+    int dev = 0;
+    NXG_HIP(hipGetDevice(&dev));
+    g.win_on = (L.order == NXG_ORDER_SRC && L.chunk_sbase.p &&
+                (size_t)g.win_off + (size_t)(1024 / 64) * kWinBytes <= (size_t)lds_budget_bytes(dev))
+                   ? 1 : 0;
     g.n_tiles = L.n_tiles;
     g.C = L.C;
     g.partial = w.partial.p;
@@ -1177,6 +1332,12 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w) {
     g.clist = nullptr;
     g.ccount = nullptr;
     return g;
+}
+
+// Dynamic LDS of one iteration launch: the tile's accumulators, plus the
+// per-wave window slots when the window path is on.
+size_t iter_lds(const Geo& g, const Layout& L, size_t ab) {
+    return g.win_on ? (size_t)g.win_off + (size_t)(1024 / 64) * kWinBytes : (size_t)L.T * ab;
 }
 
 void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
@@ -1246,8 +1407,8 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
                        w.stats.as<double>());
     NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(L, p, w);
-    const size_t lds = (size_t)L.T * sizeof(double);
+    Geo geo = make_geo(L, p, w, sizeof(double));
+    const size_t lds = iter_lds(geo, L, sizeof(double));
     const int n_items = (int)p.h_items.size();
     for (int k = 0; k < d.max_iters; ++k) {
         Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
@@ -1298,15 +1459,15 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         n->tele = d.d_teleport;
         Workspace& w = n->w;
         alloc_common(w, L, *p, sizeof(double), d.max_iters, s, false);
-        w.buf[0].alloc(sizeof(V) * L.n, s);
-        w.buf[1].alloc(sizeof(V) * L.n, s);
+        w.buf[0].alloc(sizeof(V) * (L.n + kValPad), s);
+        w.buf[1].alloc(sizeof(V) * (L.n + kValPad), s);
         w.part.alloc(sizeof(double) * grid_for(L.n, 256, 1024), s);
         const VMap vm = vmap_of(g);
         if (vm) {
             w.mvals.alloc(sizeof(V) * L.n, s);
             if (d.d_teleport) w.mtele.alloc(sizeof(V) * L.n, s);
         }
-        const size_t lds = (size_t)L.T * sizeof(double);
+        const size_t lds = iter_lds(make_geo(L, *p, w, sizeof(double)), L, sizeof(double));
         if (weighted)
             prepare_iter<ProgPRW<V>, 1024>(lds);
         else
@@ -1372,8 +1533,8 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, L, *p, ab, max_iters, s, false);
-    w.buf[0].alloc(vb * L.n, s);
-    w.buf[1].alloc(vb * L.n, s);
+    w.buf[0].alloc(vb * (L.n + kValPad), s);
+    w.buf[1].alloc(vb * (L.n + kValPad), s);
     const int nb = grid_for(L.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
     // a relabeled build works on copies in internal ids
@@ -1397,8 +1558,8 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
                        w.stats.as<double>());
     NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(L, *p, w);
-    const size_t lds = (size_t)L.T * ab;
+    Geo geo = make_geo(L, *p, w, ab);
+    const size_t lds = iter_lds(geo, L, ab);
     const int n_items = (int)p->h_items.size();
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
@@ -1505,8 +1666,8 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, L, *p, 4, max_iters, s, true);
-    w.buf[0].alloc(sizeof(int32_t) * L.n, s);
-    w.buf[1].alloc(sizeof(int32_t) * L.n, s);
+    w.buf[0].alloc(sizeof(int32_t) * (L.n + kValPad), s);
+    w.buf[1].alloc(sizeof(int32_t) * (L.n + kValPad), s);
     w.act.alloc(2 * (size_t)L.P, s);
     w.apref.alloc(sizeof(int32_t) * (L.P + 1), s);
     w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
@@ -1519,10 +1680,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
                            s, L.n, w.buf[0].as<int32_t>(), act0, L.P, vm.n2o);
     NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(L, *p, w);
+    Geo geo = make_geo(L, *p, w, 4);
     geo.clist = w.clist.as<int64_t>();
     geo.ccount = w.ccount.as<int32_t>();
-    const size_t lds = (size_t)L.T * 4;
+    const size_t lds = iter_lds(geo, L, 4);
     const int n_items = (int)p->h_items.size();
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
@@ -1667,7 +1828,8 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, s, L.n, B, L.outdeg.as<int32_t>(),
                        seeds, w.stats.as<double>());
     NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(L, *p, w);
+    Geo geo = make_geo(L, *p, w, 8);
+    geo.win_on = 0;  // the batched kernel gathers whole rows
     const int n_items = (int)p->h_items.size();
     static size_t attr = 0;
     if (lds > attr) {
@@ -1763,7 +1925,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         chunks += g->fwd.n_chunks;
         maxT = std::max(maxT, g->fwd.T);
     }
-    const size_t lds = (size_t)maxT * 8;
+    size_t lds = (size_t)maxT * 8;
     if (lds > (size_t)lds_budget_bytes(device)) fail(NXG_EINVAL, "a tile does not fit in LDS");
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = (int)std::max<int64_t>(16, chunks / std::max(1, 4 * cus));
@@ -1781,8 +1943,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         Plan* p = get_plan(g, L, piece, false, s);
         Workspace& w = ws[i];
         alloc_common(w, L, *p, 8, iters, s, false);
-        w.buf[0].alloc(sizeof(float) * L.n, s);
-        w.buf[1].alloc(sizeof(float) * L.n, s);
+        w.buf[0].alloc(sizeof(float) * (L.n + kValPad), s);
+        w.buf[1].alloc(sizeof(float) * (L.n + kValPad), s);
         hipLaunchKernelGGL(k_init_pr<float>, dim3(nbp), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
                            (const float*)nullptr, (const float*)nullptr, 1, w.buf[0].as<float>(),
                            parts.as<double>() + (size_t)nbp * i);
@@ -1791,7 +1953,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
                            nbp, w.stats.as<double>());
         NXG_CHECK_LAUNCH();
         MultiGraph& m = hdesc[i];
-        m.geo = make_geo(L, *p, w);
+        m.geo = make_geo(L, *p, w, 8);
+        lds = std::max(lds, iter_lds(m.geo, L, 8));
         m.stats = w.stats.as<double>();
         m.buf0 = w.buf[0].as<float>();
         m.buf1 = w.buf[1].as<float>();
@@ -1876,8 +2039,8 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, R, *p, 8, max_iters, s, false);
-    w.buf[0].alloc(sizeof(double) * R.n, s);
-    w.buf[1].alloc(sizeof(double) * R.n, s);
+    w.buf[0].alloc(sizeof(double) * (R.n + kValPad), s);
+    w.buf[1].alloc(sizeof(double) * (R.n + kValPad), s);
     const int nb = grid_for(R.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
     // a relabeled build works on x* and g in internal ids
@@ -1898,9 +2061,9 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
                        w.stats.as<double>());
     NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(R, *p, w);
+    Geo geo = make_geo(R, *p, w, 8);
     geo.deg = F.outdeg.as<int32_t>();  // dangling set of the forward graph
-    const size_t lds = (size_t)R.T * 8;
+    const size_t lds = iter_lds(geo, R, 8);
     const int n_items = (int)p->h_items.size();
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));

@@ -13,19 +13,20 @@ pytestmark = pytest.mark.gpu
 D = 0.85
 
 
-def _problem(scale, ef, seed, device, interval=None):
+def _problem(scale, ef, seed, device, interval=None, order="dst"):
     n = 1 << scale
     src, dst = rmatgen.rmat_edges(scale, ef, seed)
     w = rmatgen.row_normalized_weights(src, n, seed=seed + 100)
     g = rmatgen.normal_f32(seed + 200, n).astype(np.float64)
     dsss = DSSS.build(to_dev(src, device), to_dev(dst, device), n, interval=interval,
-                      weights=torch.from_numpy(w), transpose=True, keep_perm=True)
+                      weights=torch.from_numpy(w), transpose=True, keep_perm=True, order=order)
     return n, src, dst, w, g, dsss
 
 
-@pytest.mark.parametrize("scale,interval", [(10, 256), (12, None)])
-def test_adjoint_matches_oracle(gpu_device, scale, interval):
-    n, src, dst, w, g, dsss = _problem(scale, 8, 30 + scale, gpu_device, interval)
+@pytest.mark.parametrize("scale,interval,order", [(10, 256, "dst"), (12, None, "dst"),
+                                                  (12, 512, "src")])
+def test_adjoint_matches_oracle(gpu_device, scale, interval, order):
+    n, src, dst, w, g, dsss = _problem(scale, 8, 30 + scale, gpu_device, interval, order)
     w64 = w.astype(np.float64)
     xs, _ = oracle.pagerank(n, src, dst, iters=5000, w=w64, tol=1e-15)
     lam_o, gw_o, gt_o, it_o = oracle.pagerank_adjoint(n, src, dst, w64, xs, g, tol=1e-14)
