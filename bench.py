@@ -48,7 +48,8 @@ def measured_traffic(cfg):
         return None
     if t.get("kernel_sha") != kernel_sha():
         return None
-    if any(t["config"].get(k) != cfg.get(k) for k in ("interval", "tile", "chunk", "piece_chunks", "order")):
+    if any(t["config"].get(k) != cfg.get(k)
+           for k in ("interval", "tile", "chunk", "piece_chunks", "order", "relabel")):
         return None
     return t.get("bytes_per_iter")
 
@@ -87,7 +88,8 @@ def bench_pagerank(args, dev):
     src, dst = rmat(args.scale, args.ef, args.seed, dev)
     if args.interval or args.tile or args.chunk:
         best = {"interval": args.interval, "tile": args.tile, "chunk": args.chunk,
-                "piece_chunks": args.piece, "order": 0, "candidates": 0}
+                "piece_chunks": args.piece, "order": ("dst", "src").index(args.order),
+                "relabel": int(args.relabel), "candidates": 0}
     else:
         t0 = time.perf_counter()
         os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "tune_cache.txt"))
@@ -95,8 +97,9 @@ def bench_pagerank(args, dev):
         best = tune(src, dst, n)
         log("tuned in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
     t0 = time.perf_counter()
+    order = ("dst", "src")[best["order"]]
     g = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"],
-                   chunk=best["chunk"], order=args.order)
+                   chunk=best["chunk"], order=order, relabel=bool(best["relabel"]))
     torch.cuda.synchronize()
     inf = g.info()
     log("built DSSS in %.2fs: %s" % (time.perf_counter() - t0, json.dumps(inf)))
@@ -121,10 +124,28 @@ def bench_pagerank(args, dev):
     b_iter = 4.0 * m + 12.0 * n
     achieved = b_iter / (kern_ms * 1e-3) / 1e9
     log("sum(x) = %.9f" % float(x.double().sum()))
+    x = None
+    # the paper's own order (natural ids, destination-sorted sub-shards), same geometry
+    dsss_ms = None
+    if not args.no_ablation and (order != "dst" or best["relabel"]):
+        del g, x
+        torch.cuda.empty_cache()
+        g2 = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"], chunk=best["chunk"])
+        out2 = torch.empty(n, dtype=torch.float32, device=dev)
+        g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
+        torch.cuda.synchronize()
+        dsss_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        log("destination-sorted sub-shards, natural ids: %.3f ms/step" % dsss_ms)
+        del g2
+        torch.cuda.empty_cache()
     copy_gbs = copy_probe(1 << 30, 10)
     log("copy probe: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic({"interval": inf["interval"], "tile": inf["tile"], "chunk": inf["chunk"],
-                                "piece_chunks": piece, "order": args.order})
+                                "piece_chunks": piece, "order": order,
+                                "relabel": bool(best["relabel"])})
     res = {
         "metric": "PageRank GTEPS per iteration (R-MAT scale %d, ef %d)" % (args.scale, args.ef),
         "value": m / (ms_step * 1e-3) / 1e9,
@@ -135,7 +156,9 @@ def bench_pagerank(args, dev):
         "config": {"workload": "pagerank-iteration rmat-s%d-ef%d" % (args.scale, args.ef),
                    "n": n, "m": m, "interval": inf["interval"], "P": inf["P"],
                    "tile": inf["tile"], "chunk": inf["chunk"], "piece_chunks": piece,
-                   "order": args.order, "damping": 0.85, "tuned_candidates": best["candidates"]},
+                   "order": order, "relabel": bool(best["relabel"]), "damping": 0.85,
+                   "tuned_candidates": best["candidates"],
+                   "dst_sorted_natural_ids_ms_per_step": dsss_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_iter": b_iter, "kernel_ms": kern_ms,
@@ -312,9 +335,12 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--piece", type=int, default=0, help="chunks per work item (0: automatic)")
-    ap.add_argument("--order", default="dst", choices=["dst", "src"])
+    ap.add_argument("--order", default="src", choices=["dst", "src"])
+    ap.add_argument("--relabel", type=int, default=1, help="with explicit layout flags: 1 = relabel")
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip timing the destination-sorted, natural-id layout beside the tuned one")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the DSSS iteration runs on a single MI355X "

@@ -74,7 +74,8 @@ def copy_probe(nbytes=1 << 30, reps=10):
 
 def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
     """Times candidate layouts for PageRank on this graph; returns a dict with
-    interval, tile, chunk, order, piece_chunks, ms_per_iter, candidates."""
+    interval, tile, chunk, order (0 dst, 1 src), relabel, piece_chunks,
+    ms_per_iter, candidates."""
     install_torch_allocator()
     src = _dev_i32(src, "src")
     dst = _dev_i32(dst, "dst")

@@ -80,13 +80,13 @@ const char* nxg_last_error(void) { return g_last_error.c_str(); }
 
 int nxg_abi_version(void) { return NXG_ABI_VERSION; }
 
-static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream);
 
 nxg_status nxg_dsss_build(const nxg_build_desc* desc, void* stream, nxg_dsss** out) {
     return guarded([&]() {
         if (!out) fail(NXG_EINVAL, "out is NULL");
         *out = nullptr;
-        *out = build_one(desc, stream);
+        if (!desc) fail(NXG_EINVAL, "desc is NULL");
+        *out = build_handle(*desc, (hipStream_t)stream);
         return NXG_OK;
     });
 }
@@ -98,7 +98,8 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
         if (count < 1 || !descs) fail(NXG_EINVAL, "count must be >= 1 and descs non-NULL");
         nxg_multi* mg = new nxg_multi();
         try {
-            for (int32_t i = 0; i < count; ++i) mg->graphs.push_back(build_one(&descs[i], stream));
+            for (int32_t i = 0; i < count; ++i)
+                mg->graphs.push_back(build_handle(descs[i], (hipStream_t)stream));
         } catch (...) {
             delete mg;
             throw;
@@ -123,10 +124,11 @@ nxg_status nxg_multi_destroy(nxg_multi* mg) {
     });
 }
 
-static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
+}  // extern "C"
+
+namespace nxg {
+nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
     {
-        if (!desc) fail(NXG_EINVAL, "desc is NULL");
-        const nxg_build_desc& d = *desc;
         if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
         if (d.m < 0) fail(NXG_EINVAL, "m must be >= 0");
         const bool sym = (d.flags & NXG_BUILD_SYMMETRIZE) != 0;
@@ -139,7 +141,6 @@ static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
         if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
             fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
         if (d.interval < 0 || d.interval > d.n) fail(NXG_EINVAL, "interval outside [0, n]");
-        hipStream_t s = (hipStream_t)stream;
         nxg_dsss* g = new nxg_dsss();
         try {
             NXG_HIP(hipGetDevice(&g->device));
@@ -165,6 +166,9 @@ static nxg_dsss* build_one(const nxg_build_desc* desc, void* stream) {
         return g;
     }
 }
+}  // namespace nxg
+
+extern "C" {
 
 nxg_status nxg_dsss_destroy(nxg_dsss* g) {
     return guarded([&]() {

@@ -178,6 +178,9 @@ void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t*
 // validates the ids, orders the vertices by decreasing degree and renames the edges
 void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevBuf& old2new,
                    DevBuf& src2, DevBuf& dst2);
+// validated build of a whole handle, with the optional relabeling and transpose
+// (capi.hip)
+nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s);
 // runtime entry (iterate.hip)
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);

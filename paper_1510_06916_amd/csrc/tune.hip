@@ -1,8 +1,9 @@
-// Autotuner: times candidate DSSS layouts (interval, tile, chunk) and work
-// splits (piece size) for one graph and program, and keeps the fastest. The
-// paper reports intervals between 12 and 48 as good choices on its CPU
-// (Sec. IV-B2); on the GPU the useful range is set by the LDS size and the
-// cache hierarchy, so it is measured instead of assumed.
+// Autotuner: times candidate DSSS layouts (vertex numbering, edge order inside
+// a sub-shard, interval, tile, chunk) and work splits (piece size) for one
+// graph and program, and keeps the fastest. The paper reports intervals
+// between 12 and 48 as good choices on its CPU (Sec. IV-B2); on the GPU the
+// useful range is set by the LDS size and the cache hierarchy, so it is
+// measured instead of assumed.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -23,8 +24,10 @@ std::string tune_key(const nxg_build_desc& d, int program, int dtype, int batch,
     std::string arch = "gpu";
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
     char buf[256];
+    // the numbering is tuned, so the caller's RELABEL bit is not part of the key
     snprintf(buf, sizeof buf, "%s n=%d m=%lld prog=%d dtype=%d batch=%d vb=%d flags=%u", arch.c_str(),
-             d.n, (long long)d.m, program, dtype, batch, d.value_bytes, d.flags);
+             d.n, (long long)d.m, program, dtype, batch, d.value_bytes,
+             d.flags & ~(uint32_t)NXG_BUILD_RELABEL);
     return buf;
 }
 
@@ -48,8 +51,8 @@ bool load_cached(const std::string& key, nxg_tune_result* out) {
         if (key != line) continue;
         nxg_tune_result r;
         memset(&r, 0, sizeof r);
-        if (sscanf(bar + 1, "%d %d %d %d %d %lf", &r.interval, &r.tile, &r.chunk, &r.order,
-                   &r.piece_chunks, &r.ms_per_iter) == 6) {
+        if (sscanf(bar + 1, "%d %d %d %d %d %lf %d", &r.interval, &r.tile, &r.chunk, &r.order,
+                   &r.piece_chunks, &r.ms_per_iter, &r.relabel) == 7) {
             *out = r;
             found = true;
         }
@@ -68,8 +71,8 @@ void store_cached(const std::string& key, const nxg_tune_result& r) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s|%d %d %d %d %d %.6f\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
-            r.piece_chunks, r.ms_per_iter);
+    fprintf(f, "%s|%d %d %d %d %d %.6f %d\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
+            r.piece_chunks, r.ms_per_iter, r.relabel);
     fclose(f);
 }
 
@@ -117,19 +120,19 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     memset(&best, 0, sizeof best);
     best.ms_per_iter = 1e300;
     int timed = 0;
-    auto try_layout = [&](int interval, int tile, int chunk, int order, const int* pieces, int np) {
+    auto try_layout = [&](int relabel, int order, int interval, int tile, int chunk,
+                          const int* pieces, int np) {
         nxg_build_desc d = desc;
         d.interval = interval;
         d.tile = tile;
         d.chunk = chunk;
         d.order = order;
         d.value_bytes = 8;
-        nxg_dsss* g = new nxg_dsss();
+        d.flags = relabel ? (d.flags | NXG_BUILD_RELABEL) : (d.flags & ~(uint32_t)NXG_BUILD_RELABEL);
+        d.flags &= ~(uint32_t)NXG_BUILD_TRANSPOSE;  // only the forward graph is timed
+        nxg_dsss* g = nullptr;
         try {
-            g->device = device;
-            g->value_bytes = 8;
-            g->flags = d.flags;
-            build_layout(d, false, s, g->fwd);
+            g = build_handle(d, s);
             for (int k = 0; k < np; ++k) {
                 const double ms = time_run(g, base, values.p, pieces[k], s);
                 ++timed;
@@ -139,6 +142,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
                     best.tile = g->fwd.T;
                     best.chunk = g->fwd.C;
                     best.order = order;
+                    best.relabel = relabel;
                     best.piece_chunks = pieces[k];
                 }
             }
@@ -152,26 +156,33 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
         delete g;
     };
     const int no_piece[1] = {0};
-    // stage 1: source interval x destination tile, default chunk and pieces
-    const int intervals[] = {2048, 4096, 8192, 16384, 32768};
+    const int I0 = std::min<int>(2048, desc.n);
+    // stage 1: vertex numbering x edge order inside a sub-shard
+    for (int relabel : {0, 1})
+        for (int order : {NXG_ORDER_DST, NXG_ORDER_SRC}) try_layout(relabel, order, I0, tmax, 1024, no_piece, 1);
+    if (best.ms_per_iter == 1e300) try_layout(0, NXG_ORDER_DST, 0, 0, 0, no_piece, 1);
+    const nxg_tune_result stage1 = best;
+    // stage 2: source interval x destination tile
+    const int intervals[] = {1024, 2048, 4096, 8192, 16384};
     for (int I : intervals) {
         if (I > desc.n) continue;
-        for (int T : {tmax, tmax / 2}) try_layout(I, T, 1024, NXG_ORDER_DST, no_piece, 1);
+        for (int T : {tmax, tmax / 2})
+            if (!(I == I0 && T == tmax))
+                try_layout(stage1.relabel, stage1.order, I, T, 1024, no_piece, 1);
     }
-    if (best.ms_per_iter == 1e300) try_layout(0, 0, 0, NXG_ORDER_DST, no_piece, 1);
-    // stage 2: chunk size and piece size for the best layout
+    // stage 3: chunk size and piece size for the best layout
     const int cus = [&] {
         int c = 0;
         return hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && c > 0
                    ? c
                    : 256;
     }();
-    const nxg_tune_result stage1 = best;
-    for (int C : {1024, 2048}) {
+    const nxg_tune_result stage2 = best;
+    for (int C : {512, 1024, 2048}) {
         const int64_t words = desc.m + (int64_t)desc.n;  // rough stream size for the piece grid
         const int autop = (int)std::max<int64_t>(16, words / C / (4 * cus));
         const int pieces[4] = {autop / 2, autop, 2 * autop, 4 * autop};
-        try_layout(stage1.interval, stage1.tile, C, NXG_ORDER_DST, pieces, 4);
+        try_layout(stage2.relabel, stage2.order, stage2.interval, stage2.tile, C, pieces, 4);
     }
     best.candidates = timed;
     store_cached(key, best);

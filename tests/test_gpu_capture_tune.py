@@ -59,11 +59,14 @@ def test_tune_picks_a_valid_layout_and_caches(gpu_device, tmp_path, monkeypatch)
     r = tune(s, d, n)
     say("tune: %s" % r)
     assert r["candidates"] > 4 and r["ms_per_iter"] > 0
-    assert r["interval"] >= 1 and r["tile"] >= 1 and r["chunk"] in (1024, 2048)
+    assert r["interval"] >= 1 and r["tile"] >= 1 and r["chunk"] in (512, 1024, 2048)
+    assert r["order"] in (0, 1) and r["relabel"] in (0, 1)
     r2 = tune(s, d, n)
     assert r2["candidates"] == 0 and r2["interval"] == r["interval"]
+    assert r2["order"] == r["order"] and r2["relabel"] == r["relabel"]
     assert (tmp_path / "tune.txt").read_text().count("|") == 1
-    g = DSSS.build(s, d, n, interval=r["interval"], tile=r["tile"], chunk=r["chunk"])
+    g = DSSS.build(s, d, n, interval=r["interval"], tile=r["tile"], chunk=r["chunk"],
+                   order=("dst", "src")[r["order"]], relabel=bool(r["relabel"]))
     x, _ = g.pagerank(10, dtype=torch.float32, piece_chunks=r["piece_chunks"])
     ref, _ = oracle.pagerank(n, src, dst, iters=10)
     assert rel_l1(x.cpu().numpy(), ref) <= 1e-5
