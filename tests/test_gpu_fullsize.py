@@ -1,0 +1,177 @@
+"""Parity at the full benchmark sizes, in the launch configurations bench.py
+times: R-MAT scale 25 / ef 48 PageRank (tuned layout), scale 22 BFS and WCC,
+64-seed batched PPR, 256 graphs in one launch per iteration, and the scale-20
+weighted-PageRank adjoint. Where the oracle would need minutes, the check is a
+full-vector comparison of single iterations from GPU-produced vectors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rmatgen
+from paper_1510_06916_amd import DSSS, MultiDSSS, WeightedPageRank, tune
+from gpu_util import rel_l1, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg3(gpu_device):
+    say("cfg3: generating R-MAT scale 25 ef 48 seed 3")
+    src_d, dst_d = rmatgen.rmat_edges_gpu(25, 48, 3, device=gpu_device)
+    yield src_d, dst_d, src_d.cpu().numpy(), dst_d.cpu().numpy(), 1 << 25
+    torch.cuda.empty_cache()
+
+
+def test_cfg3_pagerank_fp32_tuned_layout(gpu_device, cfg3):
+    src_d, dst_d, src, dst, n = cfg3
+    r = tune(src_d, dst_d, n)
+    say("cfg3 tuned layout: %s" % r)
+    g = DSSS.build(src_d, dst_d, n, interval=r["interval"], tile=r["tile"], chunk=r["chunk"],
+                   order=("dst", "src")[r["order"]], relabel=bool(r["relabel"]))
+    pc = r["piece_chunks"]
+    # one iteration from the uniform start, every vertex
+    x1, _ = g.pagerank(1, dtype=torch.float32, piece_chunks=pc)
+    say("cfg3: oracle iteration 1")
+    ref1, _ = oracle.pagerank(n, src, dst, iters=1)
+    e1 = rel_l1(x1.cpu().numpy(), ref1)
+    say("cfg3 iteration 1: rel L1 %.2e" % e1)
+    assert e1 <= 1e-5
+    # iteration 20 from the GPU's own iterate 19 (FP32 values upcast for the oracle)
+    x19, _ = g.pagerank(19, dtype=torch.float32, piece_chunks=pc)
+    x19h = x19.cpu().numpy().copy()
+    x20, _ = g.pagerank(1, dtype=torch.float32, x0=x19, piece_chunks=pc)
+    x20h = x20.cpu().numpy()
+    say("cfg3: oracle iteration 20 from the GPU iterate 19")
+    ref20, _ = oracle.pagerank(n, src, dst, iters=1, x0=x19h.astype(np.float64))
+    e20 = rel_l1(x20h, ref20)
+    say("cfg3 iteration 20: rel L1 %.2e, mass %.9f" % (e20, float(x20h.astype(np.float64).sum())))
+    assert e20 <= 1e-5
+    assert abs(float(x20h.astype(np.float64).sum()) - 1.0) <= 1e-5
+    # the captured 20-iteration run (what bench.py replays) gives the same vector
+    out = torch.empty(n, dtype=torch.float32, device=gpu_device)
+    xc, _ = g.pagerank(20, dtype=torch.float32, capture=True, out=out, piece_chunks=pc)
+    assert rel_l1(xc.cpu().numpy(), x20h) <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def cfg2(gpu_device):
+    src, dst = rmatgen.rmat_edges_gpu(22, 16, 2, device=gpu_device)
+    return src, dst, src.cpu().numpy(), dst.cpu().numpy(), 1 << 22
+
+
+def test_cfg2_bfs_bit_exact(gpu_device, cfg2):
+    src_d, dst_d, src, dst, n = cfg2
+    g = DSSS.build(src_d, dst_d, n, interval=n // 32, value_bytes=4)
+    deg = np.bincount(src, minlength=n)
+    roots = rmatgen.distinct_vertices(102, 16, n, eligible=deg > 0)
+    for r in roots[:3].tolist():
+        say("cfg2 bfs root=%d" % r)
+        ref, rounds, mx = oracle.bfs(n, src, dst, r)
+        lev, st = g.bfs(r)
+        assert np.array_equal(lev.cpu().numpy(), ref)
+        assert st["changed_rounds"] == rounds and st["max_level"] == mx
+
+
+def test_cfg2_wcc_bit_exact(gpu_device, cfg2):
+    src_d, dst_d, src, dst, n = cfg2
+    g = DSSS.build(src_d, dst_d, n, interval=n // 32, value_bytes=4, symmetrize=True)
+    say("cfg2 wcc")
+    ref, rounds = oracle.wcc(n, src, dst)
+    lab, st = g.wcc()
+    assert np.array_equal(lab.cpu().numpy(), ref)
+    assert st["changed_rounds"] == rounds
+
+
+def test_cfg4_batched_ppr_64_seeds(gpu_device):
+    n = 1 << 22
+    src_d, dst_d = rmatgen.rmat_edges_gpu(22, 16, 4, device=gpu_device)
+    seeds = rmatgen.distinct_vertices(104, 64, n)
+    gb = DSSS.build(src_d, dst_d, n, tile=256, interval=16384, value_bytes=8 * 64)
+    say("cfg4 ppr: batched 64 x 30 iterations")
+    xb, _ = gb.ppr(torch.from_numpy(seeds), 30)
+    gp = DSSS.build(src_d, dst_d, n)
+    tele = torch.zeros(n, dtype=torch.float32, device=gpu_device)
+    worst = 0.0
+    for b in range(64):
+        tele.zero_()
+        tele[int(seeds[b])] = 1.0
+        xp, _ = gp.pagerank(30, teleport=tele)
+        worst = max(worst, rel_l1(xb[:, b].cpu().numpy(), xp.cpu().numpy()))
+    say("cfg4 ppr: worst column vs plain %.2e" % worst)
+    assert worst <= 1e-6
+    t = np.zeros(n)
+    t[seeds[0]] = 1.0
+    ref, _ = oracle.pagerank(n, src_d.cpu().numpy(), dst_d.cpu().numpy(), iters=30, t=t)
+    assert rel_l1(xb[:, 0].cpu().numpy(), ref) <= 1e-5
+
+
+def test_cfg4_256_graphs(gpu_device):
+    rng = np.random.default_rng(4000)
+    graphs = []
+    for gi in range(256):
+        scale = int(rng.integers(10, 19))
+        ef = int(rng.integers(8, 33))
+        s, d = rmatgen.rmat_edges_gpu(scale, ef, 4000 + gi, device=gpu_device)
+        graphs.append((s, d, 1 << scale))
+    say("cfg4 multi: 256 graphs, %d edges" % sum(int(s.numel()) for s, _, _ in graphs))
+    mg = MultiDSSS.build(graphs)
+    xs, _ = mg.pagerank(30)
+    worst = 0.0
+    for gi, (s, d, n) in enumerate(graphs):
+        xp, _ = DSSS.build(s, d, n).pagerank(30)
+        worst = max(worst, rel_l1(xs[gi].cpu().numpy(), xp.cpu().numpy()))
+    say("cfg4 multi: worst graph vs plain %.2e" % worst)
+    assert worst <= 1e-6
+    for gi in (0, 255):
+        s, d, n = graphs[gi]
+        ref, _ = oracle.pagerank(n, s.cpu().numpy(), d.cpu().numpy(), iters=30)
+        assert rel_l1(xs[gi].cpu().numpy(), ref) <= 1e-5
+
+
+def test_cfg5_adjoint_oracle_gradient_and_fd(gpu_device):
+    n = 1 << 20
+    src_d, dst_d = rmatgen.rmat_edges_gpu(20, 16, 5, device=gpu_device)
+    src, dst = src_d.cpu().numpy(), dst_d.cpu().numpy()
+    w = rmatgen.row_normalized_weights(src, n, seed=105)
+    gvec = rmatgen.normal_f32(205, n).astype(np.float64)
+    g = DSSS.build(src_d, dst_d, n, weights=torch.from_numpy(w), transpose=True, keep_perm=True)
+    wt = torch.from_numpy(w).to(gpu_device).requires_grad_(True)
+    tt = torch.full((n,), 1.0 / n, dtype=torch.float64, device=gpu_device, requires_grad=True)
+    say("cfg5: forward to 1e-8 and backward")
+    x = WeightedPageRank.apply(wt, tt, g, 0.85, 1e-8)
+    (x * torch.from_numpy(gvec).to(gpu_device)).sum().backward()
+    say("cfg5: oracle forward to 1e-15 and adjoint")
+    w64 = w.astype(np.float64)
+    xs_ref, _ = oracle.pagerank(n, src, dst, iters=100000, w=w64, tol=1e-15)
+    _, gw_ref, gt_ref, _ = oracle.pagerank_adjoint(n, src, dst, w64, xs_ref, gvec, tol=1e-12)
+    ex = rel_l1(x.detach().cpu().numpy(), xs_ref)
+    egw = rel_l1(wt.grad.cpu().numpy(), gw_ref)
+    egt = rel_l1(tt.grad.cpu().numpy(), gt_ref)
+    say("cfg5: x* %.2e  dL/dw %.2e  dL/dt %.2e" % (ex, egw, egt))
+    # the forward stops at residual 1e-8: x* carries ~d/(1-d) * 1e-8 of error
+    assert ex <= 1e-7
+    assert egw <= 1e-6 and egt <= 1e-6
+    # central differences on sampled edges; FP64 forwards warm-started from x* to 1e-15
+    xstar = x.detach()
+    gd = torch.from_numpy(gvec).to(gpu_device)
+    picks = np.random.default_rng(5).choice(len(src), 100, replace=False)
+    # h = 1e-3 keeps the noise of L left by a 1e-15 residual small against
+    # lp - lm ~ 2h dL/dw, while the O(h^2) truncation term stays small too
+    h = 1e-3
+    fd = []
+    for e in picks:
+        le = []
+        for sgn in (1.0, -1.0):
+            wp = wt.detach().clone()
+            wp[e] += sgn * h
+            g.set_weights(wp)
+            xp, st = g.pagerank(2000, dtype=torch.float64, tol=1e-15, weighted=True, x0=xstar)
+            le.append(float((xp * gd).sum()))
+        he = float(np.float32(w[e] + h)) - float(np.float32(w[e] - h))
+        fd.append((le[0] - le[1]) / he)
+    fd = np.array(fd)
+    ad = wt.grad.cpu().numpy().astype(np.float64)[picks]
+    err = np.linalg.norm(fd - ad) / np.linalg.norm(fd)
+    say("cfg5: central differences on 100 edges, rel L2 %.2e" % err)
+    assert err <= 1e-4
