@@ -17,7 +17,6 @@ constexpr int kRsBlock = 256;  // threads of the radix-sort kernels (4 wavefront
 constexpr int kRsItems = 8;    // keys per thread per step
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 constexpr uint32_t kMarker = 0x80000000u;
-constexpr int kChunkWindow = 256;  // sources per chunk window (1 KB of 4-byte values)
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
@@ -369,47 +368,6 @@ __global__ void k_chunk_rows(const int64_t* __restrict__ tchunk,
         crow[c] = (int32_t)(last_group_at(gword, g0, P, first) - g0);
         int64_t last = min(first + C - 1, real_end - 1);
         crow_last[c] = (int32_t)(last_group_at(gword, g0, P, last) - g0);
-    }
-}
-
-// Source window of each chunk of a source-major stream (one wavefront per
-// chunk): the source of the chunk's first edge rounded down to a multiple of
-// 32, kept when at least half of the chunk's edges have their source among the
-// kChunkWindow sources from there (the iteration kernel then copies those
-// values into LDS once per chunk); -1 otherwise.
-__global__ __launch_bounds__(256) void k_chunk_window(const uint32_t* __restrict__ words,
-                                                      const int32_t* __restrict__ crow,
-                                                      int64_t n_chunks, int C, int I, int L,
-                                                      int sshift, int32_t* __restrict__ sbase) {
-    const int lane = lane_id();
-    const uint32_t lmask = (1u << L) - 1u;
-    const uint64_t upto_me = lanemask_lt() | (1ull << lane);
-    for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks;
-         c += (int64_t)gridDim.x * 4) {
-        uint32_t row = (uint32_t)crow[c];
-        int64_t base = -1;
-        uint32_t total = 0, inside = 0;
-        for (int k = 0; k < C; k += 64) {
-            const uint32_t w = words[c * (int64_t)C + k + lane];
-            const uint64_t mm = __ballot((w >> 31) != 0);
-            uint32_t r = row;
-            if (mm) {
-                const uint64_t upto = mm & upto_me;
-                const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
-                r = upto ? got : row;
-                row = __shfl(w & ~kMarker, 63 - __clzll(mm));
-            }
-            const bool edge = (w >> 31) == 0;
-            const int64_t src = (int64_t)r * I + ((w >> sshift) & lmask);
-            const uint64_t eb = __ballot(edge);
-            if (base < 0 && eb) {
-                const int first = __ffsll((long long)eb) - 1;
-                base = __shfl(src, first) & ~(int64_t)31;
-            }
-            total += __popcll(eb);
-            inside += __popcll(__ballot(edge && base >= 0 && src >= base && src < base + kChunkWindow));
-        }
-        if (lane == 0) sbase[c] = (base >= 0 && 2 * inside >= total) ? (int32_t)base : -1;
     }
 }
 
@@ -791,13 +749,6 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
                            L.group_word.as<int64_t>(), L.P,
                            L.C, L.n_chunks, L.chunk_row.as<int32_t>(),
                            L.chunk_row_last.as<int32_t>());
-        NXG_CHECK_LAUNCH();
-    }
-    if (L.order == NXG_ORDER_SRC && L.n_chunks > 0) {
-        L.chunk_sbase.alloc(sizeof(int32_t) * L.n_chunks, s);
-        hipLaunchKernelGGL(k_chunk_window, dim3(grid_for((L.n_chunks + 3) / 4)), dim3(256), 0, s,
-                           L.words.as<uint32_t>(), L.chunk_row.as<int32_t>(), L.n_chunks, L.C, L.I,
-                           L.L, L.t, L.chunk_sbase.as<int32_t>());
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipStreamSynchronize(s));

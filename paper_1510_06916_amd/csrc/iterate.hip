@@ -25,9 +25,6 @@ namespace {
 
 constexpr uint32_t kMarker = 0x80000000u;
 constexpr int32_t kInf = INT32_MAX;
-constexpr int kWinBytes = 1024;  // LDS window slot of one wavefront (source-major streams)
-constexpr int kValPad = 256;     // vertex-value buffers hold n + kValPad elements so a
-                                 // window that starts near n stays inside them
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -43,11 +40,6 @@ struct Geo {
     int32_t n, I, P, L, T, t, n_tiles, C;
     int32_t sshift, dshift;  // bit offsets of the source and destination fields
     int32_t order;           // NXG_ORDER_* of the stream
-    // source windows of a source-major stream: chunk_sbase[c] >= 0 names the
-    // first source of chunk c's window; win_on enables the window path and
-    // win_off is the byte offset of the per-wave window slots in LDS
-    const int32_t* chunk_sbase;
-    int32_t win_on, win_off;
     // two-phase partials
     void* partial;
     int32_t* tile_ctr;
@@ -308,7 +300,9 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     if (threadIdx.x == 0) sflag = 0;
     __syncthreads();
 
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    // the wave index is uniform: chunk indices, rows and windows then live in
+    // scalar registers and their loads go through the scalar cache
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint32_t lmask = (1u << g.L) - 1u;
     const uint32_t tmask = (1u << g.t) - 1u;
@@ -386,7 +380,7 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
                         const int from = prev ? 63 - __clzll(prev) : lane;
                         const uint32_t got = __shfl(last, from);
                         uint32_t r = prev ? got : row;
-                        row = __shfl(last, 63 - __clzll(mm));
+                        row = (uint32_t)__builtin_amdgcn_readlane((int)(last), 63 - __clzll(mm));
                         uint32_t rb = r * (uint32_t)g.I;
                         bool on = prog.row_active(r);
     #pragma unroll
@@ -434,130 +428,99 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     } else {
         // Source-major groups. Load k of a lane reads word 64k + lane of a 256-word
         // sub-block, so each gather serves 64 consecutive edges, whose sources
-        // are adjacent. A chunk whose edges mostly come from the window of
-        // kWinBytes of values starting at chunk_sbase[c] first copies that window
-        // into this wave's LDS slot (one 16-byte load per lane) and gathers from
-        // there. The next step's words (and window) are loaded before this
-        // step's LDS reductions, so their latency overlaps the gathers'.
+        // are adjacent. The wave walks its units (kU sub-blocks of one chunk)
+        // through two word buffers: the loads of unit u + 2 are issued right
+        // after the gathers of unit u, so every unit's words have a whole unit of
+        // work to arrive, and waiting for a unit's gathers never waits for them.
         using val_t = typename Prog::val_t;
-        // 16 edges per lane and step; 8 when weights or 8-byte values need the registers
+        // 16 edges per lane and unit; 8 when weights or 8-byte values need the registers
         constexpr int kU = (Prog::kWeights || sizeof(val_t) > 4) ? 2 : 4, kQ = 4 * kU;
-        constexpr uint32_t W = kWinBytes / sizeof(val_t);
-        val_t* win = reinterpret_cast<val_t*>(smem + g.win_off + wave * kWinBytes);
-        int64_t ci = c_lo + wave;
-        int s = 0;
-        uint32_t wd[kQ];
-        float wf[kQ];
-        u32x4 wv = {0u, 0u, 0u, 0u};
-        int32_t wb = -1;
-        auto fetch = [&](int64_t ci_, int s_, uint32_t* wo, float* fo) {
+        const uint32_t* const wordsp = g.words;
+        const int64_t Cw = g.C;
+        const int32_t* const rowp = g.chunk_row;
+        const val_t* const curp = prog.cur;
+        const float* wtsp = nullptr;
+        if constexpr (Prog::kWeights) wtsp = prog.w;
+        // loader cursor: chunk (index into the item's range or list) and sub-block
+        int64_t lci = c_lo + wave;
+        int ls = 0;
+        // issues the loads of the next unit into wo/fo; returns whether it started a
+        // chunk (then *row0 receives the chunk's first interval)
+        auto load_unit = [=](int64_t ci_, int s_, uint32_t* wo, float* fo) {
             const int64_t c_ = list ? list[ci_] : ci_;
-            const int64_t base = c_ * (int64_t)g.C + (int64_t)s_ * 256 + lane;
+            const int64_t base = c_ * Cw + (int64_t)s_ * 256 + lane;
 #pragma unroll
             for (int u = 0; u < kU; ++u)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool in = s_ + u < steps;
                     wo[4 * u + k] =
-                        in ? __builtin_nontemporal_load(g.words + base + u * 256 + k * 64) : kNone;
+                        in ? __builtin_nontemporal_load(wordsp + base + u * 256 + k * 64) : kNone;
                     if constexpr (Prog::kWeights)
                         fo[4 * u + k] =
-                            in ? __builtin_nontemporal_load(prog.w + base + u * 256 + k * 64) : 0.f;
+                            in ? __builtin_nontemporal_load(wtsp + base + u * 256 + k * 64) : 0.f;
                     else
                         fo[4 * u + k] = 0.f;
                 }
         };
-        auto fetch_win = [&](int64_t ci_, u32x4& v, int32_t& b) {
-            b = -1;
-            if (g.win_on) {
-                const int64_t c_ = list ? list[ci_] : ci_;
-                b = g.chunk_sbase[c_];
-                if (b >= 0) v = reinterpret_cast<const u32x4*>(prog.cur + b)[lane];
+        uint32_t wA[kQ], wB[kQ];
+        float fA[kQ], fB[kQ];
+        bool vA = false, vB = false, nA = false, nB = false;  // valid, starts a chunk
+        uint32_t rA = 0, rB = 0;                              // chunk's first interval
+        auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0) {
+            valid = lci < c_hi;
+            if (!valid) return;
+            starts = ls == 0;
+            if (starts) r0 = (uint32_t)rowp[list ? list[lci] : lci];
+            load_unit(lci, ls, wo, fo);
+            ls += kU;
+            if (ls >= steps) {
+                ls = 0;
+                lci += WG / 64;
             }
         };
+        next(wA, fA, vA, nA, rA);
+        next(wB, fB, vB, nB, rB);
         uint32_t row = 0;
-        if (ci < c_hi) {
-            fetch(ci, 0, wd, wf);
-            fetch_win(ci, wv, wb);
-            row = (uint32_t)g.chunk_row[list ? list[ci] : ci];
-        }
-        while (ci < c_hi) {
-            int64_t nci = ci;
-            int ns = s + kU;
-            if (ns >= steps) {
-                nci = ci + WG / 64;
-                ns = 0;
-            }
-            if (s == 0 && wb >= 0) reinterpret_cast<u32x4*>(win)[lane] = wv;
-            // decode in edge order: source index, destination (kNone for markers,
-            // padding and edges out of inactive source intervals)
+        // one unit: decode, gathers, loads of the unit two ahead, LDS reductions
+        auto unit = [&](uint32_t* w_, float* f_, bool& valid, bool& starts, uint32_t& r0) {
+            if (starts) row = r0;
             uint32_t sidx[kQ], dl[kQ];
-            bool far = false;
-            const uint32_t wbase = (uint32_t)wb;
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const uint32_t w = wd[q];
+                const uint32_t w = w_[q];
                 const uint64_t mm = __ballot((w >> 31) != 0);
                 uint32_t r = row;
                 if (mm) {
                     const uint64_t upto = mm & (lt | (1ull << lane));
                     const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
                     r = upto ? got : row;
-                    row = __shfl(w & ~kMarker, 63 - __clzll(mm));
+                    row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
                 }
                 const bool edge = (w >> 31) == 0 && prog.row_active(r);
                 sidx[q] = edge ? r * (uint32_t)g.I + ((w >> g.sshift) & lmask) : 0u;
                 dl[q] = edge ? ((w >> g.dshift) & tmask) : kNone;
-                far |= edge && !(wb >= 0 && sidx[q] - wbase < W);
             }
             val_t raw[kQ];
-            if (__ballot(far) == 0) {
-                // every edge of the step reads the LDS window
+            float wq[kQ];
 #pragma unroll
-                for (int q = 0; q < kQ; ++q)
-                    if (dl[q] != kNone) raw[q] = win[sidx[q] - wbase];
-            } else {
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) {
-                    if (dl[q] != kNone) {
-                        const uint32_t off = sidx[q] - wbase;
-                        if (wb >= 0 && off < W)
-                            raw[q] = win[off];
-                        else
-                            raw[q] = prog.cur[sidx[q]];
-                    }
-                }
+            for (int q = 0; q < kQ; ++q) {
+                wq[q] = f_[q];
+                raw[q] = curp[sidx[q]];  // non-edges read vertex 0: no divergent branch
             }
-            uint32_t wn[kQ];
-            float fn[kQ];
-            u32x4 wvn = wv;
-            int32_t wbn = wb;
-            const bool more = nci < c_hi;
-            if (more) {
-                fetch(nci, ns, wn, fn);
-                if (ns == 0) fetch_win(nci, wvn, wbn);
-            }
+            next(w_, f_, valid, starts, r0);
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 if (dl[q] != kNone) {
-                    const acc_t v = prog.from_val(raw[q], wf[q]);
+                    const acc_t v = prog.from_val(raw[q], wq[q]);
                     if (Prog::kSum || v != prog.identity()) lds_combine(&acc[dl[q]], v, Prog::kSum);
                 }
             }
-            if (more) {
-#pragma unroll
-                for (int q = 0; q < kQ; ++q) {
-                    wd[q] = wn[q];
-                    wf[q] = fn[q];
-                }
-                if (ns == 0) {
-                    row = (uint32_t)g.chunk_row[list ? list[nci] : nci];
-                    wv = wvn;
-                    wb = wbn;
-                }
-            }
-            ci = nci;
-            s = ns;
+        };
+        while (vA) {
+            unit(wA, fA, vA, nA, rA);
+            if (!vB) break;
+            unit(wB, fB, vB, nB, rB);
         }
     }
     __syncthreads();
@@ -895,7 +858,7 @@ __global__ __launch_bounds__(256) void k_edge_grad(
                 const uint64_t prev = mm & lt;
                 const uint32_t got = __shfl(last, prev ? 63 - __clzll(prev) : lane);
                 r = prev ? got : row;
-                row = __shfl(last, 63 - __clzll(mm));
+                row = (uint32_t)__builtin_amdgcn_readlane((int)(last), 63 - __clzll(mm));
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -962,7 +925,9 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
     const int64_t base = (int64_t)tile << g.t;
     int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
     if (len < 0) len = 0;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    // the wave index is uniform: chunk indices, rows and windows then live in
+    // scalar registers and their loads go through the scalar cache
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t lt = (1ull << lane) - 1ull;
     const bool col = lane < B;
     if (*ctl.done) {  // converged earlier: carry the vectors over
@@ -994,7 +959,7 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
                 const uint64_t upto = mm & (lt | (1ull << lane));
                 const uint32_t got = __shfl(wl & ~kMarker, upto ? 63 - __clzll(upto) : lane);
                 r = upto ? got : row;
-                row = __shfl(wl & ~kMarker, 63 - __clzll(mm));
+                row = (uint32_t)__builtin_amdgcn_readlane((int)(wl & ~kMarker), 63 - __clzll(mm));
             }
             const bool edge = (wl >> 31) == 0;
             const uint32_t src_l = r * (uint32_t)g.I + ((wl >> g.sshift) & lmask);
@@ -1315,13 +1280,6 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     g.sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
     g.dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
     g.order = L.order;
-    g.chunk_sbase = L.chunk_sbase.as<int32_t>();
-    g.win_off = (int32_t)(((size_t)L.T * ab + 15) & ~(size_t)15);
-    int dev = 0;
-    NXG_HIP(hipGetDevice(&dev));
-    g.win_on = (L.order == NXG_ORDER_SRC && L.chunk_sbase.p &&
-                (size_t)g.win_off + (size_t)(1024 / 64) * kWinBytes <= (size_t)lds_budget_bytes(dev))
-                   ? 1 : 0;
     g.n_tiles = L.n_tiles;
     g.C = L.C;
     g.partial = w.partial.p;
@@ -1334,11 +1292,8 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     return g;
 }
 
-// Dynamic LDS of one iteration launch: the tile's accumulators, plus the
-// per-wave window slots when the window path is on.
-size_t iter_lds(const Geo& g, const Layout& L, size_t ab) {
-    return g.win_on ? (size_t)g.win_off + (size_t)(1024 / 64) * kWinBytes : (size_t)L.T * ab;
-}
+// Dynamic LDS of one iteration launch: the tile's accumulators.
+size_t iter_lds(const Geo&, const Layout& L, size_t ab) { return (size_t)L.T * ab; }
 
 void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
                   hipStream_t s, bool min_identity) {
@@ -1459,8 +1414,8 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         n->tele = d.d_teleport;
         Workspace& w = n->w;
         alloc_common(w, L, *p, sizeof(double), d.max_iters, s, false);
-        w.buf[0].alloc(sizeof(V) * (L.n + kValPad), s);
-        w.buf[1].alloc(sizeof(V) * (L.n + kValPad), s);
+        w.buf[0].alloc(sizeof(V) * (L.n), s);
+        w.buf[1].alloc(sizeof(V) * (L.n), s);
         w.part.alloc(sizeof(double) * grid_for(L.n, 256, 1024), s);
         const VMap vm = vmap_of(g);
         if (vm) {
@@ -1533,8 +1488,8 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, L, *p, ab, max_iters, s, false);
-    w.buf[0].alloc(vb * (L.n + kValPad), s);
-    w.buf[1].alloc(vb * (L.n + kValPad), s);
+    w.buf[0].alloc(vb * (L.n), s);
+    w.buf[1].alloc(vb * (L.n), s);
     const int nb = grid_for(L.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
     // a relabeled build works on copies in internal ids
@@ -1666,8 +1621,8 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, L, *p, 4, max_iters, s, true);
-    w.buf[0].alloc(sizeof(int32_t) * (L.n + kValPad), s);
-    w.buf[1].alloc(sizeof(int32_t) * (L.n + kValPad), s);
+    w.buf[0].alloc(sizeof(int32_t) * (L.n), s);
+    w.buf[1].alloc(sizeof(int32_t) * (L.n), s);
     w.act.alloc(2 * (size_t)L.P, s);
     w.apref.alloc(sizeof(int32_t) * (L.P + 1), s);
     w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
@@ -1829,7 +1784,6 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                        seeds, w.stats.as<double>());
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w, 8);
-    geo.win_on = 0;  // the batched kernel gathers whole rows
     const int n_items = (int)p->h_items.size();
     static size_t attr = 0;
     if (lds > attr) {
@@ -1943,8 +1897,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         Plan* p = get_plan(g, L, piece, false, s);
         Workspace& w = ws[i];
         alloc_common(w, L, *p, 8, iters, s, false);
-        w.buf[0].alloc(sizeof(float) * (L.n + kValPad), s);
-        w.buf[1].alloc(sizeof(float) * (L.n + kValPad), s);
+        w.buf[0].alloc(sizeof(float) * (L.n), s);
+        w.buf[1].alloc(sizeof(float) * (L.n), s);
         hipLaunchKernelGGL(k_init_pr<float>, dim3(nbp), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
                            (const float*)nullptr, (const float*)nullptr, 1, w.buf[0].as<float>(),
                            parts.as<double>() + (size_t)nbp * i);
@@ -2039,8 +1993,8 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, R, *p, 8, max_iters, s, false);
-    w.buf[0].alloc(sizeof(double) * (R.n + kValPad), s);
-    w.buf[1].alloc(sizeof(double) * (R.n + kValPad), s);
+    w.buf[0].alloc(sizeof(double) * (R.n), s);
+    w.buf[1].alloc(sizeof(double) * (R.n), s);
     const int nb = grid_for(R.n, 256, 1024);
     w.part.alloc(sizeof(double) * nb, s);
     // a relabeled build works on x* and g in internal ids

@@ -110,8 +110,6 @@ struct Layout {
     DevBuf perm;           // int32  [n_words] input index of the edge in that word, -1 otherwise
     DevBuf weight;         // float  [n_words] weight of the edge in that word, 0 otherwise
     DevBuf outdeg;         // int32  [n] out-degree in this (possibly reversed) graph
-    DevBuf chunk_sbase;    // int32  [n_chunks] source window of each chunk (source-major
-                           //        order only): first source of the window, or -1
     std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
     std::vector<int64_t> h_tile_edges;  // edges per tile (host)
     bool has_perm = false, has_weight = false;
