@@ -25,6 +25,7 @@ namespace {
 
 constexpr uint32_t kMarker = 0x80000000u;
 constexpr int32_t kInf = INT32_MAX;
+constexpr int kSpill = 64;  // LDS accumulators past the tile: lane l's discard slot T + l
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -444,51 +445,65 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
         // loader cursor: chunk (index into the item's range or list) and sub-block
         int64_t lci = c_lo + wave;
         int ls = 0;
-        // issues the loads of the next unit into wo/fo; returns whether it started a
-        // chunk (then *row0 receives the chunk's first interval)
-        auto load_unit = [=](int64_t ci_, int s_, uint32_t* wo, float* fo) {
-            const int64_t c_ = list ? list[ci_] : ci_;
-            const int64_t base = c_ * Cw + (int64_t)s_ * 256 + lane;
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool in = s_ + u < steps;
-                    wo[4 * u + k] =
-                        in ? __builtin_nontemporal_load(wordsp + base + u * 256 + k * 64) : kNone;
-                    if constexpr (Prog::kWeights)
-                        fo[4 * u + k] =
-                            in ? __builtin_nontemporal_load(wtsp + base + u * 256 + k * 64) : 0.f;
-                    else
-                        fo[4 * u + k] = 0.f;
-                }
-        };
+        int64_t lprev = lci;  // chunk of the last unit loaded (a valid address)
         uint32_t wA[kQ], wB[kQ];
         float fA[kQ], fB[kQ];
         bool vA = false, vB = false, nA = false, nB = false;  // valid, starts a chunk
         uint32_t rA = 0, rB = 0;                              // chunk's first interval
-        auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0) {
+        uint32_t iA = 0, iB = 0;  // sub-blocks of the unit that hold stream words (bit u)
+        // Issues the loads of the next unit. Every load is unconditional (past the
+        // end it reads a chunk this wave owns and the words become padding), so
+        // the code has no branch around memory operations and the compiler keeps
+        // exact counts of the loads in flight.
+        auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0,
+                        uint32_t& inm) {
             valid = lci < c_hi;
-            if (!valid) return;
-            starts = ls == 0;
-            if (starts) r0 = (uint32_t)rowp[list ? list[lci] : lci];
-            load_unit(lci, ls, wo, fo);
-            ls += kU;
-            if (ls >= steps) {
-                ls = 0;
-                lci += WG / 64;
+            const int64_t cl = valid ? lci : lprev;
+            const int sl = valid ? ls : 0;
+            starts = sl == 0;
+            int64_t c_ = cl;
+            if constexpr (Prog::kActivity) c_ = list ? list[cl] : cl;
+            r0 = (uint32_t)rowp[c_];
+            const int64_t base = c_ * Cw + (int64_t)sl * 256 + lane;
+            inm = 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const bool in = valid && sl + u < steps;
+                inm |= (in ? 1u : 0u) << u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    // words of a sub-block outside the stream are loaded from sub-block
+                    // 0 and treated as padding by the decode
+                    const int64_t off = base + (in ? u * 256 : 0) + k * 64;
+                    wo[4 * u + k] = __builtin_nontemporal_load(wordsp + off);
+                    if constexpr (Prog::kWeights)
+                        fo[4 * u + k] = __builtin_nontemporal_load(wtsp + off);
+                    else
+                        fo[4 * u + k] = 0.f;
+                }
+            }
+            if (valid) {
+                lprev = lci;
+                ls += kU;
+                if (ls >= steps) {
+                    ls = 0;
+                    lci += WG / 64;
+                }
             }
         };
-        next(wA, fA, vA, nA, rA);
-        next(wB, fB, vB, nB, rB);
+        if (lci < c_hi) {
+        next(wA, fA, vA, nA, rA, iA);
+        next(wB, fB, vB, nB, rB, iB);
         uint32_t row = 0;
         // one unit: decode, gathers, loads of the unit two ahead, LDS reductions
-        auto unit = [&](uint32_t* w_, float* f_, bool& valid, bool& starts, uint32_t& r0) {
+        auto unit = [&](uint32_t* w_, float* f_, bool& valid, bool& starts, uint32_t& r0,
+                        uint32_t& inm) {
             if (starts) row = r0;
+            const uint32_t in_now = inm;
             uint32_t sidx[kQ], dl[kQ];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const uint32_t w = w_[q];
+                const uint32_t w = ((in_now >> (q >> 2)) & 1u) ? w_[q] : kNone;
                 const uint64_t mm = __ballot((w >> 31) != 0);
                 uint32_t r = row;
                 if (mm) {
@@ -508,19 +523,22 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
                 wq[q] = f_[q];
                 raw[q] = curp[sidx[q]];  // non-edges read vertex 0: no divergent branch
             }
-            next(w_, f_, valid, starts, r0);
+            next(w_, f_, valid, starts, r0, inm);
+            // branch-free reductions: markers and padding add the identity to
+            // the lane's own discard slot (a conditional block here would let the
+            // compiler sink a gather into it and wait on every load in flight)
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                if (dl[q] != kNone) {
-                    const acc_t v = prog.from_val(raw[q], wq[q]);
-                    if (Prog::kSum || v != prog.identity()) lds_combine(&acc[dl[q]], v, Prog::kSum);
-                }
+                const bool e = dl[q] != kNone;
+                const acc_t v = e ? prog.from_val(raw[q], wq[q]) : prog.identity();
+                lds_combine(&acc[e ? dl[q] : (uint32_t)g.T + lane], v, Prog::kSum);
             }
         };
         while (vA) {
-            unit(wA, fA, vA, nA, rA);
+            unit(wA, fA, vA, nA, rA, iA);
             if (!vB) break;
-            unit(wB, fB, vB, nB, rB);
+            unit(wB, fB, vB, nB, rB, iB);
+        }
         }
     }
     __syncthreads();
@@ -1292,8 +1310,9 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     return g;
 }
 
-// Dynamic LDS of one iteration launch: the tile's accumulators.
-size_t iter_lds(const Geo&, const Layout& L, size_t ab) { return (size_t)L.T * ab; }
+// Dynamic LDS of one iteration launch: the tile's accumulators plus one
+// discard slot per lane.
+size_t iter_lds(const Geo&, const Layout& L, size_t ab) { return ((size_t)L.T + kSpill) * ab; }
 
 void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
                   hipStream_t s, bool min_identity) {
@@ -1477,7 +1496,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
     const size_t vb = sizeof(V);
     const size_t ab = sizeof(double);  // LDS accumulator bytes per destination
-    if ((size_t)L.T * ab > (size_t)lds_budget_bytes(g->device))
+    if (((size_t)L.T + kSpill) * ab > (size_t)lds_budget_bytes(g->device))
         fail(NXG_EINVAL, "destination tile does not fit in LDS (PageRank accumulates 8 bytes per "
                          "vertex); rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
@@ -1613,7 +1632,8 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         NXG_HIP(hipMemcpyAsync(&root, vm.o2n + root, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
     }
-    if ((size_t)L.T * 4 > (size_t)lds_budget_bytes(g->device)) fail(NXG_EINVAL, "tile does not fit in LDS");
+    if (((size_t)L.T + kSpill) * 4 > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "tile does not fit in LDS");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
@@ -1879,7 +1899,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         chunks += g->fwd.n_chunks;
         maxT = std::max(maxT, g->fwd.T);
     }
-    size_t lds = (size_t)maxT * 8;
+    size_t lds = ((size_t)maxT + kSpill) * 8;
     if (lds > (size_t)lds_budget_bytes(device)) fail(NXG_EINVAL, "a tile does not fit in LDS");
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = (int)std::max<int64_t>(16, chunks / std::max(1, 4 * cus));
@@ -1984,7 +2004,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     if (d.max_iters < 1) fail(NXG_EINVAL, "max_iters must be >= 1");
     const Layout& R = g->rev;
     const Layout& F = g->fwd;
-    if ((size_t)R.T * 8 > (size_t)lds_budget_bytes(g->device))
+    if (((size_t)R.T + kSpill) * 8 > (size_t)lds_budget_bytes(g->device))
         fail(NXG_EINVAL, "destination tile does not fit in LDS; rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
