@@ -180,7 +180,8 @@ def bench_bfs_wcc(args, dev, which):
     src, dst = rmat(scale, ef, seed, dev)
     interval = n // P
     if which == "bfs":
-        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4)
+        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, order=args.order,
+                       relabel=bool(args.relabel))
         deg = torch.bincount(src.long(), minlength=n).cpu().numpy()
         roots = rmatgen.distinct_vertices(seed + 100, 16, n, eligible=deg > 0)
         g.bfs(int(roots[0]))  # warm-up
@@ -199,7 +200,8 @@ def bench_bfs_wcc(args, dev, which):
                "config": {"workload": "bfs rmat-s22-ef16 P=32", "n": n, "m": g.m,
                           "mean_ms": 1e3 * float(np.mean(times)), "roots": len(roots)}}
     else:
-        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, symmetrize=True)
+        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, symmetrize=True,
+                       order=args.order, relabel=bool(args.relabel))
         g.wcc()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

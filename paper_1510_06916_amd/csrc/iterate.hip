@@ -153,17 +153,18 @@ struct ProgBFS {
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t from_val(int32_t l, float) const { return l == kInf ? kInf : l + 1; }
     __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
-    __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
+    // Inactive source intervals are skipped a chunk at a time (the compacted
+    // chunk list); edges of an inactive interval inside a kept chunk are
+    // processed anyway: their sources have not changed since they were last
+    // propagated, so they cannot lower a destination (Sec. II-B activity).
+    __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
     __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) {
-            flag = 1;
-            act_nxt[v / I] = 1;
-        }
+        if (nv != o) flag = 1;  // the caller raises the interval's activity flag
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -181,17 +182,18 @@ struct ProgWCC {
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t from_val(int32_t l, float) const { return l; }
     __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
-    __device__ bool row_active(uint32_t r) const { return r < (uint32_t)P && act[r]; }
+    // Inactive source intervals are skipped a chunk at a time (the compacted
+    // chunk list); edges of an inactive interval inside a kept chunk are
+    // processed anyway: their sources have not changed since they were last
+    // propagated, so they cannot lower a destination (Sec. II-B activity).
+    __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
     __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = cur[v];
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) {
-            flag = 1;
-            act_nxt[v / I] = 1;
-        }
+        if (nv != o) flag = 1;  // the caller raises the interval's activity flag
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -584,8 +586,25 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     const double scal = ctl.stats[ctl.k * 4 + 0];
     double sv[3] = {0.0, 0.0, 0.0};
     int flag = 0;
-    for (int64_t x = threadIdx.x; x < len; x += WG)
-        prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, flag);
+    for (int64_t x = threadIdx.x; x < len; x += WG) {
+        if constexpr (Prog::kActivity) {
+            // interval activity (Sec. II-B): one flag store per interval and wave
+            // (a changed lane stores unless a lower changed lane of the wave has
+            // the same interval; a wave's vertices are consecutive)
+            int ch = 0;
+            prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, ch);
+            const uint64_t cm = __ballot(ch != 0);
+            if (ch) {
+                flag = 1;
+                const int32_t iv = (int32_t)((base + x) / prog.I);
+                const uint64_t lower = cm & lt;
+                const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
+                if (!lower || piv != iv) prog.act_nxt[iv] = 1;
+            }
+        } else {
+            prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, flag);
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         sv[q] = wave_sum(sv[q]);
@@ -1203,7 +1222,9 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
         int64_t c0 = L.h_tile_chunk[tau], c1 = L.h_tile_chunk[tau + 1];
         int64_t nc = c1 - c0;
         int np = 1;
-        if (piece_chunks > 0 && nc > piece_chunks) np = (int)((nc + piece_chunks - 1) / piece_chunks);
+        // (a negative piece_chunks only keys the whole-tile plans apart)
+        const int64_t pcs = piece_chunks < 0 ? -(int64_t)piece_chunks : piece_chunks;
+        if (pcs > 0 && nc > pcs) np = (int)((nc + pcs - 1) / pcs);
         int slot = np > 1 ? slots : -1;
         if (np > 1) slots += np;
         for (int pc = 0; pc < np; ++pc) {
@@ -1640,7 +1661,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     Plan* p = get_plan(g, L, -piece, true, s);  // whole-tile ranges; pieces split the active list
     Workspace w;
     const int max_iters = d.max_iters;
-    alloc_common(w, L, *p, 4, max_iters, s, true);
+    // the host reads the per-round stats a block of rounds at a time, so the
+    // device keeps one block of them (max_iters may be as large as n + 1)
+    const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
+    alloc_common(w, L, *p, 4, block, s, true);
     w.buf[0].alloc(sizeof(int32_t) * (L.n), s);
     w.buf[1].alloc(sizeof(int32_t) * (L.n), s);
     w.act.alloc(2 * (size_t)L.P, s);
@@ -1665,8 +1689,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     NXG_HIP(hipEventCreate(&e1));
     NXG_HIP(hipEventRecord(e0, s));
     int k = 0;
-    const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
-    std::vector<double> hs(4 * (size_t)(max_iters + 2));
+    std::vector<double> hs(4 * (size_t)(block + 2));
     bool fixed = false;
     int last_changed = 0;
     while (k < max_iters && !fixed) {
@@ -1682,7 +1705,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                                L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
                                w.apref.as<int32_t>(), w.clist.as<int64_t>(), w.ccount.as<int32_t>());
             NXG_CHECK_LAUNCH();
-            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
+            Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k - kb, 0.0};
             const int32_t* cur = w.buf[k & 1].as<int32_t>();
             int32_t* nxt = w.buf[(k + 1) & 1].as<int32_t>();
             if (bfs) {
@@ -1693,11 +1716,11 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                 launch_iter<ProgWCC, 1024>(geo, ctl, pr, n_items, lds, s);
             }
         }
-        NXG_HIP(hipMemcpyAsync(hs.data() + 4 * kb, w.stats.as<double>() + 4 * kb,
-                               sizeof(double) * 4 * (k - kb), hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.as<double>(), sizeof(double) * 4 * (k - kb),
+                               hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
         for (int i = kb; i < k; ++i) {
-            if (hs[4 * i + 3] == 0.0) {
+            if (hs[4 * (i - kb) + 3] == 0.0) {
                 fixed = true;
                 break;
             }
