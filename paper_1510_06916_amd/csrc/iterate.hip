@@ -24,6 +24,7 @@ namespace nxg {
 namespace {
 
 constexpr uint32_t kMarker = 0x80000000u;
+constexpr uint32_t kNoDst = 0xFFFFFFFFu;  // decoded destination of a marker or padding word
 constexpr int32_t kInf = INT32_MAX;
 constexpr int kSpill = 64;  // LDS accumulators past the tile: lane l's discard slot T + l
 
@@ -85,11 +86,16 @@ struct ProgPR {
     __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
+    // the apply's loads, issued for several vertices before any is used
+    struct Ld {
+        V c, t;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v], tele ? tele[v] : (V)0}; }
     // sv[0]: dangling mass of x^{k+1}; sv[1]: |x^{k+1} - x^k|_1; sv[2]: sum of x^{k+1}
-    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
-                          int&) const {
-        double xo = dg ? (double)cur[v] * dg : (double)cur[v];
-        double tv = tele ? (double)tele[v] : 1.0 / n;
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t dg, double scal, int32_t n,
+                          double* sv, int&) const {
+        double xo = dg ? (double)l.c * dg : (double)l.c;
+        double tv = tele ? (double)l.t : 1.0 / n;
         double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
         V xr = (V)xn;
         sv[1] += fabs((double)xr - xo);
@@ -122,10 +128,14 @@ struct ProgPRW {
     __device__ acc_t gather(uint32_t src, float we) const { return from_val(cur[src], we); }
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double resid, double, double tol) { return resid <= tol; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
-                          int&) const {
-        double xo = (double)cur[v];
-        double tv = tele ? (double)tele[v] : 1.0 / n;
+    struct Ld {
+        V c, t;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v], tele ? tele[v] : (V)0}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t dg, double scal, int32_t n,
+                          double* sv, int&) const {
+        double xo = (double)l.c;
+        double tv = tele ? (double)l.t : 1.0 / n;
         double xn = d * ((double)acc + scal / n) + (1.0 - d) * tv;
         V xr = (V)xn;
         sv[1] += fabs((double)xr - xo);
@@ -159,9 +169,13 @@ struct ProgBFS {
     // propagated, so they cannot lower a destination (Sec. II-B activity).
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
+    struct Ld {
+        int32_t c;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
-        int32_t o = cur[v];
+        int32_t o = l.c;
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
         if (nv != o) flag = 1;  // the caller raises the interval's activity flag
@@ -188,9 +202,13 @@ struct ProgWCC {
     // propagated, so they cannot lower a destination (Sec. II-B activity).
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
-    __device__ void apply(int64_t v, acc_t acc, int32_t, double, int32_t, double*,
+    struct Ld {
+        int32_t c;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
-        int32_t o = cur[v];
+        int32_t o = l.c;
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
         if (nv != o) flag = 1;  // the caller raises the interval's activity flag
@@ -221,10 +239,14 @@ struct ProgADJ {
     static __device__ bool converged(double resid, double norm, double tol) {
         return resid <= tol * norm;
     }
-    __device__ void apply(int64_t v, acc_t acc, int32_t dg, double scal, int32_t n, double* sv,
-                          int&) const {
-        double lo = cur[v];
-        double ln = gvec[v] + d * acc + (dg == 0 ? d * scal / n : 0.0);
+    struct Ld {
+        double c, g;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v], gvec[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t dg, double scal, int32_t n,
+                          double* sv, int&) const {
+        double lo = l.c;
+        double ln = l.g + d * acc + (dg == 0 ? d * scal / n : 0.0);
         sv[0] += ln;
         sv[1] += fabs(ln - lo);
         sv[2] += fabs(ln);
@@ -303,7 +325,7 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     if (threadIdx.x == 0) sflag = 0;
     __syncthreads();
 
-    // the wave index is uniform: chunk indices, rows and windows then live in
+    // the wave index is uniform: chunk indices and interval rows then live in
     // scalar registers and their loads go through the scalar cache
     const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -586,23 +608,39 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     const double scal = ctl.stats[ctl.k * 4 + 0];
     double sv[3] = {0.0, 0.0, 0.0};
     int flag = 0;
-    for (int64_t x = threadIdx.x; x < len; x += WG) {
-        if constexpr (Prog::kActivity) {
-            // interval activity (Sec. II-B): one flag store per interval and wave
-            // (a changed lane stores unless a lower changed lane of the wave has
-            // the same interval; a wave's vertices are consecutive)
-            int ch = 0;
-            prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, ch);
-            const uint64_t cm = __ballot(ch != 0);
-            if (ch) {
-                flag = 1;
-                const int32_t iv = (int32_t)((base + x) / prog.I);
-                const uint64_t lower = cm & lt;
-                const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
-                if (!lower || piv != iv) prog.act_nxt[iv] = 1;
+    // kAR vertices per thread at a time: all their loads are issued (vertices
+    // past the tile reload the first one) before the first update is computed
+    constexpr int kAR = 4;
+    for (int64_t x0 = threadIdx.x; x0 < len; x0 += kAR * WG) {
+        typename Prog::Ld ld[kAR];
+        int32_t dgv[kAR];
+#pragma unroll
+        for (int r = 0; r < kAR; ++r) {
+            const int64_t x = x0 + r * WG < len ? x0 + r * WG : x0;
+            ld[r] = prog.load(base + x);
+            dgv[r] = g.deg[base + x];
+        }
+#pragma unroll
+        for (int r = 0; r < kAR; ++r) {
+            const int64_t x = x0 + r * WG;
+            if (x >= len) break;
+            if constexpr (Prog::kActivity) {
+                // interval activity (Sec. II-B): one flag store per interval and wave
+                // (a changed lane stores unless a lower changed lane of the wave has
+                // the same interval; a wave's vertices are consecutive)
+                int ch = 0;
+                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, ch);
+                const uint64_t cm = __ballot(ch != 0);
+                if (ch) {
+                    flag = 1;
+                    const int32_t iv = (int32_t)((base + x) / prog.I);
+                    const uint64_t lower = cm & lt;
+                    const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
+                    if (!lower || piv != iv) prog.act_nxt[iv] = 1;
+                }
+            } else {
+                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, flag);
             }
-        } else {
-            prog.apply(base + x, acc[x], g.deg[base + x], scal, g.n, sv, flag);
         }
     }
 #pragma unroll
@@ -858,6 +896,25 @@ __global__ __launch_bounds__(256) void k_init_adj(int32_t n, const double* __res
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Extrapolation of a geometrically converging iterate along its last step:
+// cur <- cur + c * (cur - prev), plus per-block partial sums of the result.
+__global__ __launch_bounds__(256) void k_extrapolate(int32_t n, double* __restrict__ cur,
+                                                     const double* __restrict__ prev, double c,
+                                                     double* __restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const double x = cur[v];
+        const double y = x + c * (x - prev[v]);
+        cur[v] = y;
+        s += y;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // dL/dw_e = d * x*[src_e] * lambda[dst_e], written at the input position of
 // edge e (through the kept permutation). One wavefront per chunk; the source
 // interval of every word is recovered from the markers as in k_iterate.
@@ -962,7 +1019,7 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
     const int64_t base = (int64_t)tile << g.t;
     int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
     if (len < 0) len = 0;
-    // the wave index is uniform: chunk indices, rows and windows then live in
+    // the wave index is uniform: chunk indices and interval rows then live in
     // scalar registers and their loads go through the scalar cache
     const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -983,12 +1040,23 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
     for (int64_t x = threadIdx.x; x < len * B; x += WG) acc[x] = 0.0;
     __syncthreads();
     const uint32_t lmask = (1u << g.L) - 1u, tmask = (1u << g.t) - 1u;
-    constexpr int kG = 16;  // row gathers in flight per lane
+    // Each 64-word slice of a chunk is decoded lane-parallel (one word per lane);
+    // its edges are then taken kG at a time with the edge fields read out as
+    // wave-uniform scalars, so a gather is one coalesced row load (lane = column)
+    // from a scalar base. The kG gathers are unconditional (non-edges read row 0)
+    // and all issued before the first is used; the next slice's words are loaded
+    // before this slice's gathers. A run of equal destinations is summed in
+    // registers and reaches the LDS accumulator once.
+    constexpr int kG = 32;
+    const int cl = col ? lane : B - 1;  // lanes past B read a valid column and discard it
     for (int64_t c = it.c0 + wave; c < it.c1; c += WG / 64) {
         uint32_t row = (uint32_t)g.chunk_row[c];
         const uint32_t* wp = g.words + c * (int64_t)g.C;
+        uint32_t pd = kNoDst;
+        double pv = 0.0;
+        uint32_t wn = __builtin_nontemporal_load(wp + lane);
         for (int s0 = 0; s0 < g.C; s0 += 64) {
-            const uint32_t wl = wp[s0 + lane];  // 64 words, one per lane
+            const uint32_t wl = wn;
             // source interval in effect at each lane's word
             const uint64_t mm = __ballot((wl >> 31) != 0);
             uint32_t r = row;
@@ -999,32 +1067,32 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
                 row = (uint32_t)__builtin_amdgcn_readlane((int)(wl & ~kMarker), 63 - __clzll(mm));
             }
             const bool edge = (wl >> 31) == 0;
-            const uint32_t src_l = r * (uint32_t)g.I + ((wl >> g.sshift) & lmask);
-            const uint32_t dst_l = edge ? ((wl >> g.dshift) & tmask) : 0xFFFFFFFFu;
-            uint32_t pd = 0xFFFFFFFFu;
-            double pv = 0.0;
+            const uint32_t src_l = edge ? r * (uint32_t)g.I + ((wl >> g.sshift) & lmask) : 0u;
+            const uint32_t dst_l = edge ? ((wl >> g.dshift) & tmask) : kNoDst;
+            // next slice's words (the last slice reloads itself)
+            wn = __builtin_nontemporal_load(wp + (s0 + 64 < g.C ? s0 + 64 : s0) + lane);
+#pragma unroll
             for (int j0 = 0; j0 < 64; j0 += kG) {
                 float v[kG];
-                uint32_t dj[kG];
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
-                    dj[q] = __shfl(dst_l, j0 + q);
-                    const uint32_t sj = __shfl(src_l, j0 + q);
-                    v[q] = (dj[q] != 0xFFFFFFFFu && col) ? cur[(int64_t)sj * B + lane] : 0.f;
+                    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)src_l, j0 + q);
+                    v[q] = cur[(int64_t)sj * B + cl];
                 }
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
-                    if (dj[q] == 0xFFFFFFFFu) continue;
-                    if (dj[q] != pd) {
-                        if (pd != 0xFFFFFFFFu && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
-                        pd = dj[q];
+                    const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)dst_l, j0 + q);
+                    if (dj == kNoDst) continue;
+                    if (dj != pd) {
+                        if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
+                        pd = dj;
                         pv = 0.0;
                     }
                     pv += (double)v[q];
                 }
             }
-            if (pd != 0xFFFFFFFFu && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
         }
+        if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
     }
     __syncthreads();
     if (it.npieces > 1) {
@@ -1055,20 +1123,35 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
     const double delta = col ? sc[lane] : 0.0;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int32_t seed = (col && seeds) ? seeds[lane] : -1;
-    for (int64_t v = wave; v < len; v += WG / 64) {
-        if (!col) continue;
-        const int64_t gv = base + v;
-        const int64_t o = gv * B + lane;
-        const int32_t dg = g.deg[gv];
-        const double xo = dg ? (double)cur[o] * dg : (double)cur[o];
-        const double tv = seeds ? (gv == seed ? 1.0 : 0.0) : 1.0 / g.n;
-        const double xn = d * (acc[v * B + lane] + delta / g.n) + (1.0 - d) * tv;
-        const float xr = (float)xn;
-        s1 += fabs((double)xr - xo);
-        s2 += (double)xr;
-        if (dg == 0) s0 += (double)xr;
-        nxt[o] = dg ? (float)((double)xr / dg) : xr;
-        if (xout) xout[o] = xr;
+    // kR rows per wave at a time, their loads issued before the first update
+    // (rows past the tile reload the wave's first row)
+    constexpr int kR = 8;
+    for (int64_t v0 = wave; v0 < len; v0 += kR * (WG / 64)) {
+        float cv[kR];
+        int32_t dgv[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int64_t v = v0 + r * (WG / 64) < len ? v0 + r * (WG / 64) : v0;
+            cv[r] = cur[(base + v) * B + cl];
+            dgv[r] = g.deg[base + v];
+        }
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int64_t v = v0 + r * (WG / 64);
+            if (v >= len || !col) continue;
+            const int64_t gv = base + v;
+            const int64_t o = gv * B + lane;
+            const int32_t dg = dgv[r];
+            const double xo = dg ? (double)cv[r] * dg : (double)cv[r];
+            const double tv = seeds ? (gv == seed ? 1.0 : 0.0) : 1.0 / g.n;
+            const double xn = d * (acc[v * B + lane] + delta / g.n) + (1.0 - d) * tv;
+            const float xr = (float)xn;
+            s1 += fabs((double)xr - xo);
+            s2 += (double)xr;
+            if (dg == 0) s0 += (double)xr;
+            nxt[o] = dg ? (float)((double)xr / dg) : xr;
+            if (xout) xout[o] = xr;
+        }
     }
     __syncthreads();  // acc is reused as the reduction buffer
     double* red = acc;
@@ -1203,6 +1286,16 @@ int num_cus(int device) {
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1)
         cu = 256;
     return cu;
+}
+
+// Chunks per work item when the caller does not choose: about one item per
+// CU's share of the stream, but never so few that a piece's partial sums
+// (slot_bytes, written and read back once) exceed an eighth of the stream
+// bytes it covers.
+int default_piece(int64_t chunks, int C, size_t slot_bytes, int cus) {
+    const int64_t share = chunks / std::max(1, cus);
+    const int64_t floor_ = (int64_t)(8 * slot_bytes / (4 * (size_t)C)) + 1;
+    return (int)std::max<int64_t>(16, std::max(share, floor_));
 }
 
 // Splits every tile into pieces of at most piece_chunks chunks; heavy tiles
@@ -1522,7 +1615,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
                          "vertex); rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
     int piece = d.piece_chunks > 0 ? d.piece_chunks : env_int("NXG_PIECE_CHUNKS", 0);
-    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * ab, cus);
     if (d.flags & NXG_RUN_CAPTURE) return run_pagerank_captured<V>(g, d, s, st, piece);
     Plan* p = get_plan(g, L, piece, false, s);
     Workspace w;
@@ -1657,7 +1750,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         fail(NXG_EINVAL, "tile does not fit in LDS");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
-    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * 4, cus);
     Plan* p = get_plan(g, L, -piece, true, s);  // whole-tile ranges; pieces split the active list
     Workspace w;
     const int max_iters = d.max_iters;
@@ -1779,7 +1872,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if ((size_t)(3 * 16) * 64 * 8 > lds) fail(NXG_EINVAL, "tile too small for the batched reduction");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
-    if (piece <= 0) piece = (int)std::max<int64_t>(16, L.n_chunks / std::max(1, 4 * cus));
+    if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * B * 8, cus);
     Plan* p = get_plan(g, L, piece, false, s);
     Workspace w;
     const int max_iters = d.max_iters;
@@ -1925,7 +2018,11 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     size_t lds = ((size_t)maxT + kSpill) * 8;
     if (lds > (size_t)lds_budget_bytes(device)) fail(NXG_EINVAL, "a tile does not fit in LDS");
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
-    if (piece <= 0) piece = (int)std::max<int64_t>(16, chunks / std::max(1, 4 * cus));
+    if (piece <= 0) {
+        int minC = 65536;
+        for (nxg_dsss* g : mg->graphs) minC = std::min(minC, g->fwd.C);
+        piece = default_piece(chunks, minC, (size_t)maxT * 8, cus);
+    }
     // per-graph plans, workspaces and descriptors
     std::vector<Item> all_items;
     std::vector<int32_t> prefix(1, 0);
@@ -2031,7 +2128,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
         fail(NXG_EINVAL, "destination tile does not fit in LDS; rebuild with value_bytes = 8");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
-    if (piece <= 0) piece = (int)std::max<int64_t>(16, R.n_chunks / std::max(1, 4 * cus));
+    if (piece <= 0) piece = default_piece(R.n_chunks, R.C, (size_t)R.T * 8, cus);
     Plan* p = get_plan(g, R, piece, false, s);
     Workspace w;
     const int max_iters = d.max_iters;
@@ -2068,7 +2165,9 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     NXG_HIP(hipEventRecord(e0, s));
     const double tol = d.tol > 0 ? d.tol : 0.0;
     const int block = tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
-    int k = 0, done_h = 0;
+    const bool accel = tol > 0 && env_int("NXG_ADJOINT_EXTRAPOLATE", 1) != 0;
+    int k = 0, done_h = 0, last_x = 0;
+    double rh[4];
     while (k < max_iters) {
         const int kend = std::min(max_iters, k + block);
         for (; k < kend; ++k) {
@@ -2079,8 +2178,33 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
         }
         if (tol > 0 && k < max_iters) {
             NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (accel && k >= 4)
+                for (int i = 0; i < 3; ++i)
+                    NXG_HIP(hipMemcpyAsync(&rh[i], w.stats.as<double>() + 4 * (k - 3 + i) + 1,
+                                           sizeof(double), hipMemcpyDeviceToHost, s));
             NXG_HIP(hipStreamSynchronize(s));
             if (done_h) break;
+            // The error of lambda = g + d M^T lambda decays as d^k along M^T's
+            // dominant eigenvector (the all-ones vector for row-stochastic
+            // weights) and much faster elsewhere. Once the step norms shrink at
+            // a steady ratio rho, that mode is removed by one extrapolation
+            // lambda += rho / (1 - rho) * (lambda_k - lambda_{k-1}); the
+            // iteration then continues from there, and convergence is still
+            // judged on plain steps.
+            if (accel && k >= 4 && k - last_x >= 8) {
+                const double r1 = rh[2] / rh[1], r2 = rh[1] / rh[0];
+                if (rh[0] > 0 && rh[1] > 0 && r1 > 0.05 && r1 < 0.99 && std::fabs(r1 - r2) <= 0.01 * r1) {
+                    const int nbx = grid_for(R.n, 256, 1024);
+                    hipLaunchKernelGGL(k_extrapolate, dim3(nbx), dim3(256), 0, s, R.n,
+                                       w.buf[k & 1].as<double>(), w.buf[(k + 1) & 1].as<double>(),
+                                       r1 / (1.0 - r1), w.part.as<double>());
+                    NXG_CHECK_LAUNCH();
+                    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nbx,
+                                       w.stats.as<double>() + 4 * k);
+                    NXG_CHECK_LAUNCH();
+                    last_x = k;
+                }
+            }
         }
     }
     const double* lam = w.buf[k & 1].as<double>();

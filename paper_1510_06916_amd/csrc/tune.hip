@@ -180,9 +180,9 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     const nxg_tune_result stage2 = best;
     for (int C : {512, 1024, 2048}) {
         const int64_t words = desc.m + (int64_t)desc.n;  // rough stream size for the piece grid
-        const int autop = (int)std::max<int64_t>(16, words / C / (4 * cus));
-        const int pieces[4] = {autop / 2, autop, 2 * autop, 4 * autop};
-        try_layout(stage2.relabel, stage2.order, stage2.interval, stage2.tile, C, pieces, 4);
+        const int autop = (int)std::max<int64_t>(16, words / C / cus);
+        const int pieces[5] = {0, std::max(16, autop / 4), std::max(16, autop / 2), autop, 2 * autop};
+        try_layout(stage2.relabel, stage2.order, stage2.interval, stage2.tile, C, pieces, 5);
     }
     best.candidates = timed;
     store_cached(key, best);
