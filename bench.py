@@ -247,6 +247,7 @@ def bench_ppr(args, dev):
     res = {"metric": "batched PPR edge-vector updates per second", "value": B * gb.m * iters / tb / 1e9,
            "unit": "G updates/s", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
            "config": {"workload": "ppr rmat-s22-ef16 B=64 30 iterations", "n": n, "m": gb.m,
+                      "plain_order": args.order, "plain_relabel": int(args.relabel),
                       "batched_ms": tb * 1e3, "plain_64_runs_ms": tp * 1e3,
                       "speedup_vs_plain": tp / tb}}
     print(json.dumps(res), flush=True)
@@ -265,7 +266,7 @@ def bench_multi(args, dev):
         s, d = rmatgen.rmat_edges_gpu(scale, ef, 4000 + g, device=dev)
         graphs.append((s, d, 1 << scale))
     m_total = sum(int(s.numel()) for s, _, _ in graphs)
-    mg = MultiDSSS.build(graphs)
+    mg = MultiDSSS.build(graphs, order=args.order, relabel=bool(args.relabel))
     mg.pagerank(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -285,6 +286,7 @@ def bench_multi(args, dev):
     res = {"metric": "256-graph PageRank (30 iterations) edges per second", "value": m_total * 30 / tm / 1e9,
            "unit": "GTEPS", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
            "config": {"workload": "multi 256 rmat graphs s10..18 ef8..32", "m_total": m_total,
+                      "order": args.order, "relabel": int(args.relabel),
                       "one_launch_per_iteration_ms": tm * 1e3, "plain_captured_runs_ms": tp * 1e3,
                       "speedup_vs_plain": tp / tm}}
     print(json.dumps(res), flush=True)

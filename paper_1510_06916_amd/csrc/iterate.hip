@@ -44,8 +44,6 @@ struct Geo {
     int32_t order;           // NXG_ORDER_* of the stream
     // two-phase partials
     void* partial;
-    int32_t* tile_ctr;
-    int32_t* all_ctr;
     double* tile_s;      // [n_tiles * 3]
     int32_t* tile_flag;  // [n_tiles]
     // compacted active chunk lists (BFS/WCC), nullable
@@ -294,19 +292,157 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // The edge kernel
 // ---------------------------------------------------------------------------
-// Processes one work item (a piece of a destination tile) of one iteration.
-// Returns 1 in the workgroup that applied the last tile of the iteration (it
-// has then reduced the per-iteration scalars), 0 otherwise. Every thread of
-// the workgroup returns the same value.
+// One iteration is three launches, ordered by the stream, so no workgroup
+// ever waits for another and no workgroup needs a device-scope fence (on
+// gfx950 each one writes back the XCD's L2):
+//   k_iterate  one workgroup per work item (a tile, or a piece of a heavy
+//              tile): streams the item's chunks into LDS accumulators; a whole
+//              tile applies the update at once, a piece stores its partial in
+//              its slot of the tile's hub (Alg. 6 ToHub);
+//   k_finish   one workgroup per split tile: sums the hub slots in piece order
+//              (FromHub) and applies the update;
+//   k_reduce   one workgroup: sums the per-tile scalars in tile order into the
+//              next iteration's dangling mass, the residual and the stop flag.
+
+// Applies the update to the tile's vertices from the accumulators in LDS and
+// stores the tile's scalars (dangling mass, residual, norm, changed flag).
 template <class Prog, int WG>
-__device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, const Item& it,
-                            unsigned char* smem) {
-    using acc_t = typename Prog::acc_t;
-    acc_t* acc = reinterpret_cast<acc_t*>(smem);
+__device__ void apply_tile(const Geo& g, const Ctl& ctl, const Prog& prog, int tile,
+                           typename Prog::acc_t* acc) {
     __shared__ double red[3][WG / 64];
     __shared__ int sflag;
-    __shared__ int slast;
-    __syncthreads();  // shared state of a previous item in this workgroup is dead
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+    if (threadIdx.x == 0) sflag = 0;
+    __syncthreads();
+    const double scal = ctl.stats[ctl.k * 4 + 0];
+    double sv[3] = {0.0, 0.0, 0.0};
+    int flag = 0;
+    // kAR vertices per thread at a time: all their loads are issued (vertices
+    // past the tile reload the first one) before the first update is computed
+    constexpr int kAR = 4;
+    for (int64_t x0 = threadIdx.x; x0 < len; x0 += kAR * WG) {
+        typename Prog::Ld ld[kAR];
+        int32_t dgv[kAR];
+#pragma unroll
+        for (int r = 0; r < kAR; ++r) {
+            const int64_t x = x0 + r * WG < len ? x0 + r * WG : x0;
+            ld[r] = prog.load(base + x);
+            dgv[r] = g.deg[base + x];
+        }
+#pragma unroll
+        for (int r = 0; r < kAR; ++r) {
+            const int64_t x = x0 + r * WG;
+            if (x >= len) break;
+            if constexpr (Prog::kActivity) {
+                // interval activity (Sec. II-B): one flag store per interval and wave
+                // (a changed lane stores unless a lower changed lane of the wave has
+                // the same interval; a wave's vertices are consecutive)
+                int ch = 0;
+                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, ch);
+                const uint64_t cm = __ballot(ch != 0);
+                if (ch) {
+                    flag = 1;
+                    const int32_t iv = (int32_t)((base + x) / prog.I);
+                    const uint64_t lower = cm & lt;
+                    const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
+                    if (!lower || piv != iv) prog.act_nxt[iv] = 1;
+                }
+            } else {
+                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, flag);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sv[q] = wave_sum(sv[q]);
+        if (lane == 0) red[q][wave] = sv[q];
+    }
+    if (flag) sflag = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double a = 0.0;
+            for (int w = 0; w < WG / 64; ++w) a += red[q][w];
+            g.tile_s[3 * tile + q] = a;
+        }
+        g.tile_flag[tile] = sflag;
+    }
+}
+
+// Sums the tile scalars of one iteration in tile order (k_reduce's body).
+template <class Prog, int WG>
+__device__ void reduce_tiles(const Geo& g, const Ctl& ctl) {
+    __shared__ double red[3][WG / 64];
+    __shared__ int sflag;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) sflag = 0;
+    __syncthreads();
+    double tv[3] = {0.0, 0.0, 0.0};
+    int f = 0;
+    for (int x = threadIdx.x; x < g.n_tiles; x += WG) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) tv[q] += g.tile_s[3 * x + q];
+        f |= g.tile_flag[x];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        tv[q] = wave_sum(tv[q]);
+        if (lane == 0) red[q][wave] = tv[q];
+    }
+    if (f) sflag = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t3[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            t3[q] = 0.0;
+            for (int w = 0; w < WG / 64; ++w) t3[q] += red[q][w];
+        }
+        ctl.stats[(ctl.k + 1) * 4 + 0] = t3[0];
+        ctl.stats[ctl.k * 4 + 1] = t3[1];
+        ctl.stats[ctl.k * 4 + 2] = t3[2];
+        ctl.stats[ctl.k * 4 + 3] = sflag ? 1.0 : 0.0;
+        if (ctl.tol > 0.0 && Prog::converged(t3[1], t3[2], ctl.tol)) *ctl.done = 1;
+    }
+}
+
+// Sums the hub slots of a split tile in piece order into LDS (FromHub).
+template <class Prog, int WG>
+__device__ void gather_hub(const Geo& g, const Prog& prog, const Item& it, typename Prog::acc_t* acc) {
+    using acc_t = typename Prog::acc_t;
+    const int64_t base = (int64_t)it.tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+    // eight slots per pass so the loads of a thread are independent
+    const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
+    for (int64_t x = threadIdx.x; x < len; x += WG) {
+        acc_t sum = prog.identity();
+        int p = 0;
+        for (; p + 8 <= it.npieces; p += 8) {
+            acc_t v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = __builtin_nontemporal_load(p0 + (int64_t)(p + q) * g.T + x);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sum = combine<Prog::kSum>(sum, v[q]);
+        }
+        for (; p < it.npieces; ++p)
+            sum = combine<Prog::kSum>(sum, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
+        acc[x] = sum;
+    }
+    __syncthreads();
+}
+
+// Processes one work item (a tile, or a piece of a heavy tile) of one iteration.
+template <class Prog, int WG>
+__device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, const Item& it,
+                             unsigned char* smem) {
+    using acc_t = typename Prog::acc_t;
+    acc_t* acc = reinterpret_cast<acc_t*>(smem);
 
     const int tile = it.tile;
     const int64_t base = (int64_t)tile << g.t;
@@ -318,11 +454,10 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     if (*ctl.done) {
         if (it.piece == 0)
             for (int64_t x = threadIdx.x; x < len; x += WG) prog.pass(base + x, g.deg[base + x]);
-        return 0;
+        return;
     }
 
     for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
-    if (threadIdx.x == 0) sflag = 0;
     __syncthreads();
 
     // the wave index is uniform: chunk indices and interval rows then live in
@@ -567,134 +702,13 @@ __device__ int iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, cons
     }
     __syncthreads();
 
-    // ---- two-phase: every piece writes its partial to its slot of the tile's
-    // hub (Alg. 6 ToHub); the last piece to arrive sums the slots in piece order
-    // (FromHub) into LDS and applies the update --------------------------------
+    // a piece stores its partial in its hub slot; k_finish combines them
     if (it.npieces > 1) {
         acc_t* part = reinterpret_cast<acc_t*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T;
         for (int64_t x = threadIdx.x; x < len; x += WG) part[x] = acc[x];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int old = __hip_atomic_fetch_add(&g.tile_ctr[tile], 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            slast = (old == it.npieces - 1);
-        }
-        __syncthreads();
-        if (!slast) return 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        // eight slots per pass so the loads of a thread are independent
-        const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
-        for (int64_t x = threadIdx.x; x < len; x += WG) {
-            acc_t sum = prog.identity();
-            int p = 0;
-            for (; p + 8 <= it.npieces; p += 8) {
-                acc_t v[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    v[q] = __builtin_nontemporal_load(p0 + (int64_t)(p + q) * g.T + x);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) sum = combine<Prog::kSum>(sum, v[q]);
-            }
-            for (; p < it.npieces; ++p)
-                sum = combine<Prog::kSum>(sum, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
-            acc[x] = sum;
-        }
-        if (threadIdx.x == 0) g.tile_ctr[tile] = 0;
-        __syncthreads();
+        return;
     }
-
-    // ---- apply ------------------------------------------------------------
-    const double scal = ctl.stats[ctl.k * 4 + 0];
-    double sv[3] = {0.0, 0.0, 0.0};
-    int flag = 0;
-    // kAR vertices per thread at a time: all their loads are issued (vertices
-    // past the tile reload the first one) before the first update is computed
-    constexpr int kAR = 4;
-    for (int64_t x0 = threadIdx.x; x0 < len; x0 += kAR * WG) {
-        typename Prog::Ld ld[kAR];
-        int32_t dgv[kAR];
-#pragma unroll
-        for (int r = 0; r < kAR; ++r) {
-            const int64_t x = x0 + r * WG < len ? x0 + r * WG : x0;
-            ld[r] = prog.load(base + x);
-            dgv[r] = g.deg[base + x];
-        }
-#pragma unroll
-        for (int r = 0; r < kAR; ++r) {
-            const int64_t x = x0 + r * WG;
-            if (x >= len) break;
-            if constexpr (Prog::kActivity) {
-                // interval activity (Sec. II-B): one flag store per interval and wave
-                // (a changed lane stores unless a lower changed lane of the wave has
-                // the same interval; a wave's vertices are consecutive)
-                int ch = 0;
-                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, ch);
-                const uint64_t cm = __ballot(ch != 0);
-                if (ch) {
-                    flag = 1;
-                    const int32_t iv = (int32_t)((base + x) / prog.I);
-                    const uint64_t lower = cm & lt;
-                    const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
-                    if (!lower || piv != iv) prog.act_nxt[iv] = 1;
-                }
-            } else {
-                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, flag);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        sv[q] = wave_sum(sv[q]);
-        if (lane == 0) red[q][wave] = sv[q];
-    }
-    if (flag) sflag = 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            double a = 0.0;
-            for (int w = 0; w < WG / 64; ++w) a += red[q][w];
-            g.tile_s[3 * tile + q] = a;
-        }
-        g.tile_flag[tile] = sflag;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        int old = __hip_atomic_fetch_add(g.all_ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        slast = (old == g.n_tiles - 1);
-    }
-    __syncthreads();
-    if (!slast) return 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // ---- last tile: per-iteration scalars in tile order ---------------------
-    double tv[3] = {0.0, 0.0, 0.0};
-    int f = 0;
-    for (int x = threadIdx.x; x < g.n_tiles; x += WG) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) tv[q] += __builtin_nontemporal_load(&g.tile_s[3 * x + q]);
-        f |= __builtin_nontemporal_load(&g.tile_flag[x]);
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        tv[q] = wave_sum(tv[q]);
-        if (lane == 0) red[q][wave] = tv[q];
-    }
-    if (f) sflag = 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t3[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            t3[q] = 0.0;
-            for (int w = 0; w < WG / 64; ++w) t3[q] += red[q][w];
-        }
-        ctl.stats[(ctl.k + 1) * 4 + 0] = t3[0];
-        ctl.stats[ctl.k * 4 + 1] = t3[1];
-        ctl.stats[ctl.k * 4 + 2] = t3[2];
-        ctl.stats[ctl.k * 4 + 3] = sflag ? 1.0 : 0.0;
-        if (ctl.tol > 0.0 && Prog::converged(t3[1], t3[2], ctl.tol)) *ctl.done = 1;
-        *g.all_ctr = 0;
-    }
-    return 1;
+    apply_tile<Prog, WG>(g, ctl, prog, tile, acc);
 }
 
 template <class Prog, int WG>
@@ -703,12 +717,29 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     iterate_item<Prog, WG>(g, ctl, prog, g.items[blockIdx.x], smem);
 }
 
+// One workgroup per split tile (fin[b] is the tile's piece 0).
+template <class Prog, int WG>
+__global__ __launch_bounds__(WG) void k_finish(Geo g, Ctl ctl, Prog prog, const Item* __restrict__ fin) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (*ctl.done) return;  // converged: the pieces have carried the vectors over
+    const Item it = fin[blockIdx.x];
+    typename Prog::acc_t* acc = reinterpret_cast<typename Prog::acc_t*>(smem);
+    gather_hub<Prog, WG>(g, prog, it, acc);
+    apply_tile<Prog, WG>(g, ctl, prog, it.tile, acc);
+}
+
+template <class Prog, int WG>
+__global__ __launch_bounds__(WG) void k_reduce(Geo g, Ctl ctl) {
+    if (*ctl.done) return;
+    reduce_tiles<Prog, WG>(g, ctl);
+}
+
 // ---------------------------------------------------------------------------
 // Many graphs per launch: one launch per iteration covers the work items (tile
 // pieces) of every graph; workgroup w finds its graph by a search over the
-// per-graph item prefix. Iterations are ordered by the stream, so no
-// workgroup ever waits for another; each graph's last tile reduces that
-// graph's scalars exactly as in a single-graph launch.
+// per-graph item prefix. As for one graph, the split tiles of all graphs are
+// finished by a second launch and each graph's scalars are reduced by a third
+// (one workgroup per graph), so no workgroup ever waits for another.
 // ---------------------------------------------------------------------------
 struct MultiGraph {
     Geo geo;
@@ -742,6 +773,34 @@ __global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict_
                        k == iters - 1 ? mg.xout : nullptr, damping};
     iterate_item<ProgPR<float>, WG>(mg.geo, ctl, prog, items[mg.item_base + (r - item_prefix[lo])],
                                     smem);
+}
+
+// A split tile of graph `graph` (its piece 0).
+struct MultiFin {
+    int32_t graph;
+    Item it;
+};
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_multi_finish(const MultiGraph* __restrict__ graphs,
+                                                     const MultiFin* __restrict__ fin, int k, int iters,
+                                                     double damping) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const MultiFin f = fin[blockIdx.x];
+    const MultiGraph& mg = graphs[f.graph];
+    Ctl ctl{mg.stats, mg.done0, k, 0.0};
+    ProgPR<float> prog{(k & 1) ? mg.buf1 : mg.buf0, (k & 1) ? mg.buf0 : mg.buf1, nullptr,
+                       k == iters - 1 ? mg.xout : nullptr, damping};
+    double* acc = reinterpret_cast<double*>(smem);
+    gather_hub<ProgPR<float>, WG>(mg.geo, prog, f.it, acc);
+    apply_tile<ProgPR<float>, WG>(mg.geo, ctl, prog, f.it.tile, acc);
+}
+
+// One workgroup per graph: that graph's scalars in tile order.
+__global__ __launch_bounds__(1024) void k_multi_reduce(const MultiGraph* __restrict__ graphs, int k) {
+    const MultiGraph& mg = graphs[blockIdx.x];
+    Ctl ctl{mg.stats, mg.done0, k, 0.0};
+    reduce_tiles<ProgPR<float>, 1024>(mg.geo, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,119 +1065,19 @@ struct BCtl {
     double tol;
 };
 
+// The update of one tile from its accumulators acc[T][B] (lane = column), and
+// the tile's per-column scalars (dangling mass, residual, sum) in tile_sb.
 template <int WG>
-__global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const float* __restrict__ cur,
-                                                        float* __restrict__ nxt, float* __restrict__ xout,
-                                                        const int32_t* __restrict__ seeds, int B,
-                                                        double d, double* __restrict__ tile_sb) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* acc = reinterpret_cast<double*>(smem);  // [T][B]
-    __shared__ int slast;
-    const Item it = g.items[blockIdx.x];
-    const int tile = it.tile;
+__device__ void apply_batched(const Geo& g, const BCtl& ctl, const float* __restrict__ cur,
+                              float* __restrict__ nxt, float* __restrict__ xout,
+                              const int32_t* __restrict__ seeds, int B, double d,
+                              double* __restrict__ tile_sb, int tile, double* acc) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const bool col = lane < B;
+    const int cl = col ? lane : B - 1;
     const int64_t base = (int64_t)tile << g.t;
     int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
     if (len < 0) len = 0;
-    // the wave index is uniform: chunk indices and interval rows then live in
-    // scalar registers and their loads go through the scalar cache
-    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t lt = (1ull << lane) - 1ull;
-    const bool col = lane < B;
-    if (*ctl.done) {  // converged earlier: carry the vectors over
-        if (it.piece == 0)
-            for (int64_t v = wave; v < len; v += WG / 64)
-                if (col) {
-                    const int64_t o = (base + v) * B + lane;
-                    nxt[o] = cur[o];
-                    if (xout) {
-                        const int32_t dg = g.deg[base + v];
-                        xout[o] = dg ? (float)((double)cur[o] * dg) : cur[o];
-                    }
-                }
-        return;
-    }
-    for (int64_t x = threadIdx.x; x < len * B; x += WG) acc[x] = 0.0;
-    __syncthreads();
-    const uint32_t lmask = (1u << g.L) - 1u, tmask = (1u << g.t) - 1u;
-    // Each 64-word slice of a chunk is decoded lane-parallel (one word per lane);
-    // its edges are then taken kG at a time with the edge fields read out as
-    // wave-uniform scalars, so a gather is one coalesced row load (lane = column)
-    // from a scalar base. The kG gathers are unconditional (non-edges read row 0)
-    // and all issued before the first is used; the next slice's words are loaded
-    // before this slice's gathers. A run of equal destinations is summed in
-    // registers and reaches the LDS accumulator once.
-    constexpr int kG = 32;
-    const int cl = col ? lane : B - 1;  // lanes past B read a valid column and discard it
-    for (int64_t c = it.c0 + wave; c < it.c1; c += WG / 64) {
-        uint32_t row = (uint32_t)g.chunk_row[c];
-        const uint32_t* wp = g.words + c * (int64_t)g.C;
-        uint32_t pd = kNoDst;
-        double pv = 0.0;
-        uint32_t wn = __builtin_nontemporal_load(wp + lane);
-        for (int s0 = 0; s0 < g.C; s0 += 64) {
-            const uint32_t wl = wn;
-            // source interval in effect at each lane's word
-            const uint64_t mm = __ballot((wl >> 31) != 0);
-            uint32_t r = row;
-            if (mm) {
-                const uint64_t upto = mm & (lt | (1ull << lane));
-                const uint32_t got = __shfl(wl & ~kMarker, upto ? 63 - __clzll(upto) : lane);
-                r = upto ? got : row;
-                row = (uint32_t)__builtin_amdgcn_readlane((int)(wl & ~kMarker), 63 - __clzll(mm));
-            }
-            const bool edge = (wl >> 31) == 0;
-            const uint32_t src_l = edge ? r * (uint32_t)g.I + ((wl >> g.sshift) & lmask) : 0u;
-            const uint32_t dst_l = edge ? ((wl >> g.dshift) & tmask) : kNoDst;
-            // next slice's words (the last slice reloads itself)
-            wn = __builtin_nontemporal_load(wp + (s0 + 64 < g.C ? s0 + 64 : s0) + lane);
-#pragma unroll
-            for (int j0 = 0; j0 < 64; j0 += kG) {
-                float v[kG];
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)src_l, j0 + q);
-                    v[q] = cur[(int64_t)sj * B + cl];
-                }
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)dst_l, j0 + q);
-                    if (dj == kNoDst) continue;
-                    if (dj != pd) {
-                        if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
-                        pd = dj;
-                        pv = 0.0;
-                    }
-                    pv += (double)v[q];
-                }
-            }
-        }
-        if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
-    }
-    __syncthreads();
-    if (it.npieces > 1) {
-        double* part = reinterpret_cast<double*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T * B;
-        for (int64_t x = threadIdx.x; x < len * B; x += WG) part[x] = acc[x];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int old = __hip_atomic_fetch_add(&g.tile_ctr[tile], 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            slast = (old == it.npieces - 1);
-        }
-        __syncthreads();
-        if (!slast) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const double* p0 = reinterpret_cast<const double*>(g.partial) + (int64_t)it.slot * g.T * B;
-        for (int64_t x = threadIdx.x; x < len * B; x += WG) {
-            double sum = 0.0;
-            for (int p = 0; p < it.npieces; ++p)
-                sum += __builtin_nontemporal_load(p0 + (int64_t)p * g.T * B + x);
-            acc[x] = sum;
-        }
-        if (threadIdx.x == 0) g.tile_ctr[tile] = 0;
-        __syncthreads();
-    }
-    // apply, lane = column; per-column partial sums reduced across waves in LDS
     const double* sc = ctl.stats + (int64_t)ctl.k * 3 * B;
     const double delta = col ? sc[lane] : 0.0;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1165,46 +1124,189 @@ __global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const f
         for (int w = 0; w < WG / 64; ++w) a += red[(q * (WG / 64) + w) * 64 + b];
         if (b < B) tile_sb[((int64_t)tile * 3 + q) * B + b] = a;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int old = __hip_atomic_fetch_add(g.all_ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        slast = (old == g.n_tiles - 1);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_iterate_batched(Geo g, BCtl ctl, const float* __restrict__ cur,
+                                                        float* __restrict__ nxt, float* __restrict__ xout,
+                                                        const int32_t* __restrict__ seeds, int B,
+                                                        double d, double* __restrict__ tile_sb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* acc = reinterpret_cast<double*>(smem);  // [T][B]
+    const Item it = g.items[blockIdx.x];
+    const int tile = it.tile;
+    const int64_t base = (int64_t)tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+    // the wave index is uniform: chunk indices and interval rows then live in
+    // scalar registers and their loads go through the scalar cache
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const bool col = lane < B;
+    if (*ctl.done) {  // converged earlier: carry the vectors over
+        if (it.piece == 0)
+            for (int64_t v = wave; v < len; v += WG / 64)
+                if (col) {
+                    const int64_t o = (base + v) * B + lane;
+                    nxt[o] = cur[o];
+                    if (xout) {
+                        const int32_t dg = g.deg[base + v];
+                        xout[o] = dg ? (float)((double)cur[o] * dg) : cur[o];
+                    }
+                }
+        return;
     }
+    for (int64_t x = threadIdx.x; x < len * B; x += WG) acc[x] = 0.0;
     __syncthreads();
-    if (!slast) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // last tile: per-column scalars; wave w sums tiles w, w+16, ... (lane = column,
-    // coalesced), then the 16 wave partials are summed in wave order
-    {
-        double t3[3] = {0.0, 0.0, 0.0};
-        if (col)
-            for (int64_t x = wave; x < g.n_tiles; x += WG / 64) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    t3[q] += __builtin_nontemporal_load(&tile_sb[((int64_t)x * 3 + q) * B + lane]);
+    const uint32_t lmask = (1u << g.L) - 1u, tmask = (1u << g.t) - 1u;
+    // The wave walks the 64-word slices of its chunks (all in this item's tile).
+    // A slice is decoded lane-parallel (one word per lane); its 64 edges are then
+    // taken in two halves of 32, with the edge fields read out as wave-uniform
+    // scalars, so a gather is one coalesced row load (lane = column) from a scalar
+    // base. Gathers are unconditional (non-edges read row 0), and the next half's
+    // 32 are issued before the current half's are used, so up to 64 rows per
+    // wave are in flight; words are loaded two slices ahead. A run of equal
+    // destinations is summed in registers and reaches the LDS accumulator once.
+    constexpr int kH = 32;
+    const int cl = col ? lane : B - 1;  // lanes past B read a valid column and discard it
+    const int spc = g.C >> 6;           // slices per chunk
+    const int64_t nch = it.c1 - it.c0 > wave ? (it.c1 - it.c0 - wave + WG / 64 - 1) / (WG / 64) : 0;
+    const int64_t K = nch * spc;        // slices of this wave
+    if (K > 0) {
+        const uint32_t* const wbase = g.words;
+        // word address of this wave's slice k (k clamped to the last one)
+        auto slice_ptr = [&](int64_t k) -> const uint32_t* {
+            const int64_t kc = k < K ? k : K - 1;
+            const int64_t c = it.c0 + wave + (kc / spc) * (WG / 64);
+            return wbase + c * (int64_t)g.C + (kc % spc) * 64;
+        };
+        uint32_t row = 0;
+        // decodes slice k's words into per-lane source index and tile-local destination
+        auto decode = [&](int64_t k, uint32_t wl, uint32_t& src_l, uint32_t& dst_l) {
+            if (k % spc == 0) row = (uint32_t)g.chunk_row[it.c0 + wave + (k / spc) * (WG / 64)];
+            const uint64_t mm = __ballot((wl >> 31) != 0);
+            uint32_t r = row;
+            if (mm) {
+                const uint64_t upto = mm & (lt | (1ull << lane));
+                const uint32_t got = __shfl(wl & ~kMarker, upto ? 63 - __clzll(upto) : lane);
+                r = upto ? got : row;
+                row = (uint32_t)__builtin_amdgcn_readlane((int)(wl & ~kMarker), 63 - __clzll(mm));
             }
+            const bool edge = (wl >> 31) == 0;
+            src_l = edge ? r * (uint32_t)g.I + ((wl >> g.sshift) & lmask) : 0u;
+            dst_l = edge ? ((wl >> g.dshift) & tmask) : kNoDst;
+        };
+        auto issue = [&](float* v, uint32_t src_l, int j0) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) red[(q * (WG / 64) + wave) * 64 + lane] = t3[q];
+            for (int q = 0; q < kH; ++q) {
+                const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)src_l, j0 + q);
+                v[q] = cur[(int64_t)sj * B + cl];
+            }
+        };
+        uint32_t pd = kNoDst;
+        double pv = 0.0;
+        auto consume = [&](const float* v, uint32_t dst_l, int j0) {
+#pragma unroll
+            for (int q = 0; q < kH; ++q) {
+                const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)dst_l, j0 + q);
+                if (dj == kNoDst) continue;
+                if (dj != pd) {
+                    if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
+                    pd = dj;
+                    pv = 0.0;
+                }
+                pv += (double)v[q];
+            }
+        };
+        float vA[kH], vB[kH];
+        uint32_t sc, dc;
+        uint32_t w0 = __builtin_nontemporal_load(slice_ptr(0) + lane);
+        uint32_t wn = __builtin_nontemporal_load(slice_ptr(1) + lane);
+        decode(0, w0, sc, dc);
+        issue(vA, sc, 0);
+        for (int64_t k = 0; k < K; ++k) {
+            issue(vB, sc, kH);  // second half of slice k
+            consume(vA, dc, 0);
+            // first half of slice k + 1; after the last slice the (discarded)
+            // gathers all read row 0, with no branch around them
+            const bool more = k + 1 < K;
+            uint32_t sn, dn;
+            decode(more ? k + 1 : k, wn, sn, dn);
+            sn = more ? sn : 0u;
+            wn = __builtin_nontemporal_load(slice_ptr(k + 2) + lane);
+            issue(vA, sn, 0);
+            consume(vB, dc, kH);
+            sc = sn;
+            dc = dn;
+        }
+        if (pd != kNoDst && col) atomicAdd(&acc[(int64_t)pd * B + lane], pv);
     }
     __syncthreads();
-    if (threadIdx.x < 3 * 64) {
-        const int q = threadIdx.x >> 6, b = threadIdx.x & 63;
-        if (b < B) {
-            double a = 0.0;
-            for (int w = 0; w < WG / 64; ++w) a += red[(q * (WG / 64) + w) * 64 + b];
-            double* so = ctl.stats + (int64_t)(q == 0 ? ctl.k + 1 : ctl.k) * 3 * B;
-            so[q * B + b] = a;  // q=0: delta entering k+1 at [k+1][0][b]; q=1,2: [k][q][b]
-        }
+    if (it.npieces > 1) {  // partial to the hub slot; k_finish_batched combines them
+        double* part = reinterpret_cast<double*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T * B;
+        for (int64_t x = threadIdx.x; x < len * B; x += WG) part[x] = acc[x];
+        return;
+    }
+    apply_batched<WG>(g, ctl, cur, nxt, xout, seeds, B, d, tile_sb, tile, acc);
+}
+
+// One workgroup per split tile: hub slots summed in piece order, then the update.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_finish_batched(Geo g, BCtl ctl, const float* __restrict__ cur,
+                                                       float* __restrict__ nxt, float* __restrict__ xout,
+                                                       const int32_t* __restrict__ seeds, int B,
+                                                       double d, double* __restrict__ tile_sb,
+                                                       const Item* __restrict__ fin) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* acc = reinterpret_cast<double*>(smem);  // [T][B]
+    if (*ctl.done) return;
+    const Item it = fin[blockIdx.x];
+    const int64_t base = (int64_t)it.tile << g.t;
+    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
+    if (len < 0) len = 0;
+    const double* p0 = reinterpret_cast<const double*>(g.partial) + (int64_t)it.slot * g.T * B;
+    for (int64_t x = threadIdx.x; x < len * B; x += WG) {
+        double sum = 0.0;
+        for (int p = 0; p < it.npieces; ++p) sum += __builtin_nontemporal_load(p0 + (int64_t)p * g.T * B + x);
+        acc[x] = sum;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (ctl.tol > 0.0) {
-            double mx = 0.0;
-            for (int b = 0; b < B; ++b) mx = fmax(mx, ctl.stats[(int64_t)ctl.k * 3 * B + B + b]);
-            if (mx <= ctl.tol) *ctl.done = 1;
-        }
-        *g.all_ctr = 0;
+    apply_batched<WG>(g, ctl, cur, nxt, xout, seeds, B, d, tile_sb, it.tile, acc);
+}
+
+// Per-column scalars of one iteration, in two deterministic passes: block r sums
+// tiles [r*per, (r+1)*per) in tile order (thread = (scalar, column)); then one
+// block sums the block partials in order and sets the stop flag.
+__global__ __launch_bounds__(256) void k_reduce_batched1(const double* __restrict__ tile_sb, int n_tiles,
+                                                         int B, int per, const int32_t* __restrict__ done,
+                                                         double* __restrict__ part) {
+    if (*done) return;
+    const int j = threadIdx.x;  // (q, b) = (j / B, j % B)
+    if (j >= 3 * B) return;
+    const int t0 = blockIdx.x * per, t1 = min(n_tiles, t0 + per);
+    double a = 0.0;
+    for (int x = t0; x < t1; ++x) a += tile_sb[(int64_t)x * 3 * B + j];
+    part[(int64_t)blockIdx.x * 3 * B + j] = a;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_batched2(const double* __restrict__ part, int nblocks, int B,
+                                                         BCtl ctl) {
+    __shared__ double res[64];
+    if (*ctl.done) return;
+    const int j = threadIdx.x;
+    if (j < 3 * B) {
+        double a = 0.0;
+        for (int r = 0; r < nblocks; ++r) a += part[(int64_t)r * 3 * B + j];
+        const int q = j / B, b = j % B;
+        double* so = ctl.stats + (int64_t)(q == 0 ? ctl.k + 1 : ctl.k) * 3 * B;
+        so[q * B + b] = a;  // q=0: delta entering k+1 at [k+1][0][b]; q=1,2: [k][q][b]
+        if (q == 1) res[b] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && ctl.tol > 0.0) {
+        double mx = 0.0;
+        for (int b = 0; b < B; ++b) mx = fmax(mx, res[b]);
+        if (mx <= ctl.tol) *ctl.done = 1;
     }
 }
 
@@ -1346,13 +1448,19 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
     p->items.alloc(sizeof(Item) * std::max<size_t>(items.size(), 1), s);
     NXG_HIP(hipMemcpyAsync(p->items.p, items.data(), sizeof(Item) * items.size(),
                            hipMemcpyHostToDevice, s));
+    for (const Item& it : items)
+        if (it.npieces > 1 && it.piece == 0) p->h_fin.push_back(it);
+    p->fin.alloc(sizeof(Item) * std::max<size_t>(p->h_fin.size(), 1), s);
+    if (!p->h_fin.empty())
+        NXG_HIP(hipMemcpyAsync(p->fin.p, p->h_fin.data(), sizeof(Item) * p->h_fin.size(),
+                               hipMemcpyHostToDevice, s));
     NXG_HIP(hipStreamSynchronize(s));
     g->plans.push_back(p);
     return p;
 }
 
 struct Workspace {
-    DevBuf buf[2], partial, tile_ctr, all_ctr, tile_s, tile_flag, stats, done, act, apref, clist,
+    DevBuf buf[2], partial, tile_s, tile_flag, stats, done, act, apref, clist,
         ccount, part, bfsout;
     DevBuf mtele, mvals, mseeds, mgx, mxs;  // caller data in internal ids (relabeled builds)
 };
@@ -1383,15 +1491,34 @@ void permute_rows(const T* in, const int32_t* idx, int64_t n, int w, T* out, hip
 }
 
 template <class Prog, int WG>
-void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, int n_items, size_t lds,
-                 hipStream_t s) {
+void prepare_iter(size_t lds) {
     static size_t attr_lds = 0;
     if (lds > attr_lds) {
         NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        NXG_HIP(hipFuncSetAttribute((const void*)k_finish<Prog, WG>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_lds = lds;
     }
-    hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
+}
+
+// One iteration: the items, the split tiles, the scalar reduction (no memsets,
+// so it can be recorded into a hipGraph).
+template <class Prog, int WG>
+void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p, size_t lds,
+                 hipStream_t s) {
+    prepare_iter<Prog, WG>(lds);
+    const int n_items = (int)p.h_items.size();
+    if (n_items > 0) {
+        hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
+        NXG_CHECK_LAUNCH();
+    }
+    if (!p.h_fin.empty()) {
+        hipLaunchKernelGGL((k_finish<Prog, WG>), dim3((int)p.h_fin.size()), dim3(WG), lds, s, geo, ctl,
+                           prog, p.fin.as<Item>());
+        NXG_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL((k_reduce<Prog, 1024>), dim3(1), dim3(1024), 0, s, geo, ctl);
     NXG_CHECK_LAUNCH();
 }
 
@@ -1415,8 +1542,6 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     g.n_tiles = L.n_tiles;
     g.C = L.C;
     g.partial = w.partial.p;
-    g.tile_ctr = w.tile_ctr.as<int32_t>();
-    g.all_ctr = w.all_ctr.as<int32_t>();
     g.tile_s = w.tile_s.as<double>();
     g.tile_flag = w.tile_flag.as<int32_t>();
     g.clist = nullptr;
@@ -1434,10 +1559,6 @@ void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int m
     (void)min_identity;
     const int64_t hub_elems = (int64_t)std::max(p.n_slots, 1) * L.T;
     w.partial.alloc((size_t)hub_elems * vb, s);
-    w.tile_ctr.alloc(sizeof(int32_t) * L.n_tiles, s);
-    NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
-    w.all_ctr.alloc(sizeof(int32_t), s);
-    NXG_HIP(hipMemsetAsync(w.all_ctr.p, 0, sizeof(int32_t), s));
     w.tile_s.alloc(sizeof(double) * 3 * L.n_tiles, s);
     w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
     w.stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
@@ -1463,16 +1584,6 @@ struct CapturedPR : Cached {
     }
 };
 
-template <class Prog, int WG>
-void prepare_iter(size_t lds) {
-    static size_t attr_lds = 0;
-    if (lds > attr_lds) {
-        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_lds = lds;
-    }
-}
-
 // Enqueues x^0 and max_iters iterations of (weighted) PageRank; no syncs.
 template <typename V>
 void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_run_desc& d,
@@ -1497,7 +1608,6 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, p, w, sizeof(double));
     const size_t lds = iter_lds(geo, L, sizeof(double));
-    const int n_items = (int)p.h_items.size();
     for (int k = 0; k < d.max_iters; ++k) {
         Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
         const V* cur = w.buf[k & 1].as<V>();
@@ -1505,14 +1615,11 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
         V* xout = (k == d.max_iters - 1) ? vals : nullptr;
         if (weighted) {
             ProgPRW<V> pr{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
-            hipLaunchKernelGGL((k_iterate<ProgPRW<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
-                               ctl, pr);
+            launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, p, lds, s);
         } else {
             ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
-            hipLaunchKernelGGL((k_iterate<ProgPR<V>, 1024>), dim3(n_items), dim3(1024), lds, s, geo,
-                               ctl, pr);
+            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, p, lds, s);
         }
-        NXG_CHECK_LAUNCH();
     }
     if (vm) permute_rows<V>(vals, vm.o2n, L.n, 1, (V*)d.d_values, s);
 }
@@ -1665,10 +1772,10 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             V* xout = (k == max_iters - 1) ? vals : nullptr;
             if (weighted) {
                 ProgPRW<V> pr{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
-                launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+                launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, *p, lds, s);
             } else {
                 ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
-                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s);
             }
         }
         if (d.tol > 0 && k < max_iters) {
@@ -1688,7 +1795,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, vals, d.damping};
             NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
-            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, n_items, lds, s);
+            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s);
         }
         NXG_CHECK_LAUNCH();
     }
@@ -1803,10 +1910,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             int32_t* nxt = w.buf[(k + 1) & 1].as<int32_t>();
             if (bfs) {
                 ProgBFS pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
-                launch_iter<ProgBFS, 1024>(geo, ctl, pr, n_items, lds, s);
+                launch_iter<ProgBFS, 1024>(geo, ctl, pr, *p, lds, s);
             } else {
                 ProgWCC pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
-                launch_iter<ProgWCC, 1024>(geo, ctl, pr, n_items, lds, s);
+                launch_iter<ProgWCC, 1024>(geo, ctl, pr, *p, lds, s);
             }
         }
         NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.as<double>(), sizeof(double) * 4 * (k - kb),
@@ -1879,10 +1986,6 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     // partial slots hold T*B doubles each
     const int64_t hub = (int64_t)std::max(p->n_slots, 1) * L.T * B;
     w.partial.alloc(sizeof(double) * hub, s);
-    w.tile_ctr.alloc(sizeof(int32_t) * L.n_tiles, s);
-    NXG_HIP(hipMemsetAsync(w.tile_ctr.p, 0, sizeof(int32_t) * L.n_tiles, s));
-    w.all_ctr.alloc(sizeof(int32_t), s);
-    NXG_HIP(hipMemsetAsync(w.all_ctr.p, 0, sizeof(int32_t), s));
     w.tile_s.alloc(sizeof(double) * 3 * B * (size_t)L.n_tiles, s);
     w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
     const size_t nstat = (size_t)(max_iters + 2) * 3 * B;
@@ -1921,12 +2024,37 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w, 8);
     const int n_items = (int)p->h_items.size();
+    const int n_fin = (int)p->h_fin.size();
     static size_t attr = 0;
     if (lds > attr) {
         NXG_HIP(hipFuncSetAttribute((const void*)k_iterate_batched<1024>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        NXG_HIP(hipFuncSetAttribute((const void*)k_finish_batched<1024>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = lds;
     }
+    // the scalar reduction: blocks of `per` tiles, then one block over the block sums
+    const int rblocks = std::min(L.n_tiles, 256);
+    const int rper = (L.n_tiles + rblocks - 1) / rblocks;
+    w.part.alloc(sizeof(double) * 3 * B * (size_t)rblocks, s);
+    auto one_iteration = [&](const BCtl& ctl, const float* cur, float* nxt, float* xout) {
+        if (n_items > 0) {
+            hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl, cur,
+                               nxt, xout, seeds, B, d.damping, w.tile_s.as<double>());
+            NXG_CHECK_LAUNCH();
+        }
+        if (n_fin > 0) {
+            hipLaunchKernelGGL(k_finish_batched<1024>, dim3(n_fin), dim3(1024), lds, s, geo, ctl, cur, nxt,
+                               xout, seeds, B, d.damping, w.tile_s.as<double>(), p->fin.as<Item>());
+            NXG_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_reduce_batched1, dim3(rblocks), dim3(256), 0, s, w.tile_s.as<double>(),
+                           L.n_tiles, B, rper, ctl.done, w.part.as<double>());
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_reduce_batched2, dim3(1), dim3(256), 0, s, w.part.as<double>(), rblocks, B,
+                           ctl);
+        NXG_CHECK_LAUNCH();
+    };
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
     NXG_HIP(hipEventCreate(&e1));
@@ -1938,10 +2066,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         for (; k < kend; ++k) {
             BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             float* xout = (k == max_iters - 1) ? vals : nullptr;
-            hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl,
-                               w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout, seeds,
-                               B, d.damping, w.tile_s.as<double>());
-            NXG_CHECK_LAUNCH();
+            one_iteration(ctl, w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout);
         }
         if (d.tol > 0 && k < max_iters) {
             NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -2025,6 +2150,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     }
     // per-graph plans, workspaces and descriptors
     std::vector<Item> all_items;
+    std::vector<MultiFin> all_fin;
     std::vector<int32_t> prefix(1, 0);
     std::vector<MultiGraph> hdesc(G);
     std::vector<Workspace> ws(G);
@@ -2061,9 +2187,14 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         m.item_base = (int32_t)all_items.size();
         m.n_items = (int32_t)p->h_items.size();
         all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
+        for (const Item& it : p->h_fin) all_fin.push_back(MultiFin{i, it});
         prefix.push_back((int32_t)all_items.size());
     }
-    DevBuf ditems, dprefix, ddesc;
+    DevBuf ditems, dprefix, ddesc, dfin;
+    dfin.alloc(sizeof(MultiFin) * std::max<size_t>(all_fin.size(), 1), s);
+    if (!all_fin.empty())
+        NXG_HIP(hipMemcpyAsync(dfin.p, all_fin.data(), sizeof(MultiFin) * all_fin.size(),
+                               hipMemcpyHostToDevice, s));
     ditems.alloc(sizeof(Item) * all_items.size(), s);
     dprefix.alloc(sizeof(int32_t) * prefix.size(), s);
     ddesc.alloc(sizeof(MultiGraph) * G, s);
@@ -2073,6 +2204,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     static size_t attr = 0;
     if (lds > attr) {
         NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_finish<1024>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = lds;
     }
@@ -2085,6 +2218,13 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         hipLaunchKernelGGL(k_multi_iter<1024>, dim3(per_iter), dim3(1024), lds, s,
                            ddesc.as<MultiGraph>(), G, dprefix.as<int32_t>(), ditems.as<Item>(), k,
                            iters, d.damping);
+        NXG_CHECK_LAUNCH();
+        if (!all_fin.empty()) {
+            hipLaunchKernelGGL(k_multi_finish<1024>, dim3((int)all_fin.size()), dim3(1024), lds, s,
+                               ddesc.as<MultiGraph>(), dfin.as<MultiFin>(), k, iters, d.damping);
+            NXG_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, s, ddesc.as<MultiGraph>(), k);
         NXG_CHECK_LAUNCH();
     }
     for (int i = 0; i < G; ++i) {
@@ -2174,7 +2314,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, tol};
             ProgADJ pr{w.buf[k & 1].as<double>(), w.buf[(k + 1) & 1].as<double>(), gx, nullptr,
                        R.weight.as<float>(), d.damping};
-            launch_iter<ProgADJ, 1024>(geo, ctl, pr, n_items, lds, s);
+            launch_iter<ProgADJ, 1024>(geo, ctl, pr, *p, lds, s);
         }
         if (tol > 0 && k < max_iters) {
             NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -137,6 +137,8 @@ struct Plan {
     std::vector<Item> h_items;
     DevBuf items;
     int32_t n_slots = 0;  // partial-buffer slots (one tile-sized array each)
+    std::vector<Item> h_fin;  // piece 0 of every split tile (the finishing launch)
+    DevBuf fin;
 };
 
 }  // namespace nxg

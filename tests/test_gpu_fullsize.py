@@ -115,7 +115,8 @@ def test_cfg4_256_graphs(gpu_device):
         s, d = rmatgen.rmat_edges_gpu(scale, ef, 4000 + gi, device=gpu_device)
         graphs.append((s, d, 1 << scale))
     say("cfg4 multi: 256 graphs, %d edges" % sum(int(s.numel()) for s, _, _ in graphs))
-    mg = MultiDSSS.build(graphs)
+    # the layout bench.py times: source order, out-degree numbering
+    mg = MultiDSSS.build(graphs, order="src", relabel=True)
     xs, _ = mg.pagerank(30)
     worst = 0.0
     for gi, (s, d, n) in enumerate(graphs):
@@ -135,7 +136,8 @@ def test_cfg5_adjoint_oracle_gradient_and_fd(gpu_device):
     src, dst = src_d.cpu().numpy(), dst_d.cpu().numpy()
     w = rmatgen.row_normalized_weights(src, n, seed=105)
     gvec = rmatgen.normal_f32(205, n).astype(np.float64)
-    g = DSSS.build(src_d, dst_d, n, weights=torch.from_numpy(w), transpose=True, keep_perm=True)
+    g = DSSS.build(src_d, dst_d, n, weights=torch.from_numpy(w), transpose=True, keep_perm=True,
+                   order="src", relabel=True)
     wt = torch.from_numpy(w).to(gpu_device).requires_grad_(True)
     tt = torch.full((n,), 1.0 / n, dtype=torch.float64, device=gpu_device, requires_grad=True)
     say("cfg5: forward to 1e-8 and backward")

@@ -42,6 +42,19 @@ def test_multi_batch_matches_plain_and_oracle(gpu_device):
             assert rel_l1(xs[i].cpu().numpy(), xp.cpu().numpy()) <= 1e-6
 
 
+@pytest.mark.parametrize("order,relabel", [("src", False), ("src", True)])
+def test_multi_source_order_and_relabel(gpu_device, order, relabel):
+    gs = _graphs(12, gpu_device)
+    say("multi: order=%s relabel=%s" % (order, relabel))
+    mg = MultiDSSS.build([(to_dev(s, gpu_device), to_dev(d, gpu_device), n) for s, d, n in gs],
+                         order=order, relabel=relabel)
+    xs, st = mg.pagerank(25)
+    assert st["iterations"] == 25
+    for i, (s, d, n) in enumerate(gs):
+        ref, _ = oracle.pagerank(n, s, d, iters=25)
+        assert rel_l1(xs[i].cpu().numpy(), ref) <= 1e-5, i
+
+
 def test_multi_persistent_flag_is_refused(gpu_device):
     gs = _graphs(2, gpu_device)
     mg = MultiDSSS.build([(to_dev(s, gpu_device), to_dev(d, gpu_device), n) for s, d, n in gs])
