@@ -233,10 +233,11 @@ typedef struct nxg_tune_result {
     int32_t relabel;       /* 1 if the best layout uses NXG_BUILD_RELABEL */
 } nxg_tune_result;
 
-/* Times PageRank iterations of the graph in desc under candidate layouts
- * (vertex numbering x edge order inside a sub-shard, then source interval x
- * destination tile, then chunk and piece size) and returns the fastest. The paper picks the interval count from experience (Sec.
- * IV-B2); here it is measured. Results are cached per process and, when the
+/* Times captured PageRank iterations (NXG_RUN_CAPTURE) of the graph in desc
+ * under candidate layouts (vertex numbering x edge order inside a sub-shard,
+ * then source interval x destination tile, then chunk and piece size) and
+ * returns the fastest. The paper picks the interval count from experience
+ * (Sec. IV-B2); here it is measured. Results are cached per process and, when the
  * environment variable NXG_TUNE_CACHE names a file, appended to it and read
  * back, keyed by device, n, m, program, dtype, batch, value_bytes and flags.
  * Builds and runs on `stream` and synchronises it; never use under capture.

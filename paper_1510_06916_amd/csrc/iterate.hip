@@ -44,7 +44,8 @@ struct Geo {
     int32_t order;           // NXG_ORDER_* of the stream
     // two-phase partials
     void* partial;
-    double* tile_s;      // [n_tiles * 3]
+    double* tile_s;      // [n_sslots * 3]: per tile, then per finishing segment
+    int32_t n_sslots;
     int32_t* tile_flag;  // [n_tiles]
     // compacted active chunk lists (BFS/WCC), nullable
     const int64_t* clist;
@@ -304,18 +305,16 @@ __device__ inline double wave_sum(double v) {
 //   k_reduce   one workgroup: sums the per-tile scalars in tile order into the
 //              next iteration's dangling mass, the residual and the stop flag.
 
-// Applies the update to the tile's vertices from the accumulators in LDS and
-// stores the tile's scalars (dangling mass, residual, norm, changed flag).
+// Applies the update to vertices [base, base + len) from the accumulators
+// acc[0, len) in LDS and stores their scalars (dangling mass, residual, norm,
+// changed flag) in scalar slot `slot`.
 template <class Prog, int WG>
-__device__ void apply_tile(const Geo& g, const Ctl& ctl, const Prog& prog, int tile,
-                           typename Prog::acc_t* acc) {
+__device__ void apply_range(const Geo& g, const Ctl& ctl, const Prog& prog, int64_t base, int64_t len,
+                            int slot, typename Prog::acc_t* acc) {
     __shared__ double red[3][WG / 64];
     __shared__ int sflag;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int64_t base = (int64_t)tile << g.t;
-    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
-    if (len < 0) len = 0;
     if (threadIdx.x == 0) sflag = 0;
     __syncthreads();
     const double scal = ctl.stats[ctl.k * 4 + 0];
@@ -368,13 +367,13 @@ __device__ void apply_tile(const Geo& g, const Ctl& ctl, const Prog& prog, int t
         for (int q = 0; q < 3; ++q) {
             double a = 0.0;
             for (int w = 0; w < WG / 64; ++w) a += red[q][w];
-            g.tile_s[3 * tile + q] = a;
+            g.tile_s[3 * slot + q] = a;
         }
-        g.tile_flag[tile] = sflag;
+        g.tile_flag[slot] = sflag;
     }
 }
 
-// Sums the tile scalars of one iteration in tile order (k_reduce's body).
+// Sums the scalar slots of one iteration in slot order (k_reduce's body).
 template <class Prog, int WG>
 __device__ void reduce_tiles(const Geo& g, const Ctl& ctl) {
     __shared__ double red[3][WG / 64];
@@ -384,7 +383,7 @@ __device__ void reduce_tiles(const Geo& g, const Ctl& ctl) {
     __syncthreads();
     double tv[3] = {0.0, 0.0, 0.0};
     int f = 0;
-    for (int x = threadIdx.x; x < g.n_tiles; x += WG) {
+    for (int x = threadIdx.x; x < g.n_sslots; x += WG) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) tv[q] += g.tile_s[3 * x + q];
         f |= g.tile_flag[x];
@@ -411,15 +410,14 @@ __device__ void reduce_tiles(const Geo& g, const Ctl& ctl) {
     }
 }
 
-// Sums the hub slots of a split tile in piece order into LDS (FromHub).
+// Sums the hub slots of a split tile in piece order into LDS (FromHub), over
+// the segment's vertices.
 template <class Prog, int WG>
-__device__ void gather_hub(const Geo& g, const Prog& prog, const Item& it, typename Prog::acc_t* acc) {
+__device__ void gather_hub(const Geo& g, const Prog& prog, const FinSeg& it, typename Prog::acc_t* acc) {
     using acc_t = typename Prog::acc_t;
-    const int64_t base = (int64_t)it.tile << g.t;
-    int64_t len = min((int64_t)g.T, (int64_t)g.n - base);
-    if (len < 0) len = 0;
+    const int64_t len = it.vlen;
     // eight slots per pass so the loads of a thread are independent
-    const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T;
+    const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T + it.v0;
     for (int64_t x = threadIdx.x; x < len; x += WG) {
         acc_t sum = prog.identity();
         int p = 0;
@@ -702,13 +700,18 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
     }
     __syncthreads();
 
-    // a piece stores its partial in its hub slot; k_finish combines them
+    // a piece stores its partial in its hub slot; k_finish combines them (its
+    // segments carry the tile's scalars, the tile's own slot holds zeros)
     if (it.npieces > 1) {
         acc_t* part = reinterpret_cast<acc_t*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T;
         for (int64_t x = threadIdx.x; x < len; x += WG) part[x] = acc[x];
+        if (it.piece == 0 && threadIdx.x == 0) {
+            for (int q = 0; q < 3; ++q) g.tile_s[3 * tile + q] = 0.0;
+            g.tile_flag[tile] = 0;
+        }
         return;
     }
-    apply_tile<Prog, WG>(g, ctl, prog, tile, acc);
+    apply_range<Prog, WG>(g, ctl, prog, base, len, tile, acc);
 }
 
 template <class Prog, int WG>
@@ -717,15 +720,15 @@ __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     iterate_item<Prog, WG>(g, ctl, prog, g.items[blockIdx.x], smem);
 }
 
-// One workgroup per split tile (fin[b] is the tile's piece 0).
+// One workgroup per vertex segment of a split tile.
 template <class Prog, int WG>
-__global__ __launch_bounds__(WG) void k_finish(Geo g, Ctl ctl, Prog prog, const Item* __restrict__ fin) {
+__global__ __launch_bounds__(WG) void k_finish(Geo g, Ctl ctl, Prog prog, const FinSeg* __restrict__ fin) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (*ctl.done) return;  // converged: the pieces have carried the vectors over
-    const Item it = fin[blockIdx.x];
+    const FinSeg f = fin[blockIdx.x];
     typename Prog::acc_t* acc = reinterpret_cast<typename Prog::acc_t*>(smem);
-    gather_hub<Prog, WG>(g, prog, it, acc);
-    apply_tile<Prog, WG>(g, ctl, prog, it.tile, acc);
+    gather_hub<Prog, WG>(g, prog, f, acc);
+    apply_range<Prog, WG>(g, ctl, prog, ((int64_t)f.tile << g.t) + f.v0, f.vlen, f.sslot, acc);
 }
 
 template <class Prog, int WG>
@@ -775,10 +778,10 @@ __global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict_
                                     smem);
 }
 
-// A split tile of graph `graph` (its piece 0).
+// A finishing segment of graph `graph`.
 struct MultiFin {
     int32_t graph;
-    Item it;
+    FinSeg f;
 };
 
 template <int WG>
@@ -792,8 +795,9 @@ __global__ __launch_bounds__(WG) void k_multi_finish(const MultiGraph* __restric
     ProgPR<float> prog{(k & 1) ? mg.buf1 : mg.buf0, (k & 1) ? mg.buf0 : mg.buf1, nullptr,
                        k == iters - 1 ? mg.xout : nullptr, damping};
     double* acc = reinterpret_cast<double*>(smem);
-    gather_hub<ProgPR<float>, WG>(mg.geo, prog, f.it, acc);
-    apply_tile<ProgPR<float>, WG>(mg.geo, ctl, prog, f.it.tile, acc);
+    gather_hub<ProgPR<float>, WG>(mg.geo, prog, f.f, acc);
+    apply_range<ProgPR<float>, WG>(mg.geo, ctl, prog, ((int64_t)f.f.tile << mg.geo.t) + f.f.v0, f.f.vlen,
+                                   f.f.sslot, acc);
 }
 
 // One workgroup per graph: that graph's scalars in tile order.
@@ -1454,6 +1458,27 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
     if (!p->h_fin.empty())
         NXG_HIP(hipMemcpyAsync(p->fin.p, p->h_fin.data(), sizeof(Item) * p->h_fin.size(),
                                hipMemcpyHostToDevice, s));
+    // segments of kFinSeg vertices, so a heavy tile's FromHub is spread over
+    // many workgroups; scalar slots n_tiles, n_tiles + 1, ... in list order
+    constexpr int kFinSeg = 2048;
+    for (const Item& it : p->h_fin) {
+        const int64_t base = (int64_t)it.tile * L.T;
+        const int64_t len = std::max<int64_t>(0, std::min<int64_t>(L.T, (int64_t)L.n - base));
+        for (int64_t v0 = 0; v0 < len; v0 += kFinSeg) {
+            FinSeg f;
+            f.tile = it.tile;
+            f.npieces = it.npieces;
+            f.slot = it.slot;
+            f.v0 = (int32_t)v0;
+            f.vlen = (int32_t)std::min<int64_t>(kFinSeg, len - v0);
+            f.sslot = L.n_tiles + (int32_t)p->h_fseg.size();
+            p->h_fseg.push_back(f);
+        }
+    }
+    p->fseg.alloc(sizeof(FinSeg) * std::max<size_t>(p->h_fseg.size(), 1), s);
+    if (!p->h_fseg.empty())
+        NXG_HIP(hipMemcpyAsync(p->fseg.p, p->h_fseg.data(), sizeof(FinSeg) * p->h_fseg.size(),
+                               hipMemcpyHostToDevice, s));
     NXG_HIP(hipStreamSynchronize(s));
     g->plans.push_back(p);
     return p;
@@ -1513,9 +1538,9 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p
         hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
         NXG_CHECK_LAUNCH();
     }
-    if (!p.h_fin.empty()) {
-        hipLaunchKernelGGL((k_finish<Prog, WG>), dim3((int)p.h_fin.size()), dim3(WG), lds, s, geo, ctl,
-                           prog, p.fin.as<Item>());
+    if (!p.h_fseg.empty()) {
+        hipLaunchKernelGGL((k_finish<Prog, WG>), dim3((int)p.h_fseg.size()), dim3(WG), lds, s, geo, ctl,
+                           prog, p.fseg.as<FinSeg>());
         NXG_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL((k_reduce<Prog, 1024>), dim3(1), dim3(1024), 0, s, geo, ctl);
@@ -1544,6 +1569,7 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     g.partial = w.partial.p;
     g.tile_s = w.tile_s.as<double>();
     g.tile_flag = w.tile_flag.as<int32_t>();
+    g.n_sslots = L.n_tiles + (int32_t)p.h_fseg.size();
     g.clist = nullptr;
     g.ccount = nullptr;
     return g;
@@ -1559,8 +1585,9 @@ void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int m
     (void)min_identity;
     const int64_t hub_elems = (int64_t)std::max(p.n_slots, 1) * L.T;
     w.partial.alloc((size_t)hub_elems * vb, s);
-    w.tile_s.alloc(sizeof(double) * 3 * L.n_tiles, s);
-    w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+    const size_t slots = (size_t)L.n_tiles + p.h_fseg.size();
+    w.tile_s.alloc(sizeof(double) * 3 * slots, s);
+    w.tile_flag.alloc(sizeof(int32_t) * slots, s);
     w.stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
     NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * 4 * (size_t)(max_iters + 2), s));
     w.done.alloc(sizeof(int32_t), s);
@@ -2187,7 +2214,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         m.item_base = (int32_t)all_items.size();
         m.n_items = (int32_t)p->h_items.size();
         all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
-        for (const Item& it : p->h_fin) all_fin.push_back(MultiFin{i, it});
+        for (const FinSeg& f : p->h_fseg) all_fin.push_back(MultiFin{i, f});
         prefix.push_back((int32_t)all_items.size());
     }
     DevBuf ditems, dprefix, ddesc, dfin;

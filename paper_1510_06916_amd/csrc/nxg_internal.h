@@ -129,6 +129,13 @@ struct Cached {
     virtual ~Cached() {}
 };
 
+// A vertex segment [v0, v0 + vlen) of a split tile, finished by one
+// workgroup: it sums the tile's npieces hub slots (from `slot`) over the
+// segment, applies the update and stores its scalars in scalar slot sslot.
+struct FinSeg {
+    int32_t tile, npieces, slot, v0, vlen, sslot;
+};
+
 struct Layout;
 struct Plan {
     const Layout* layout = nullptr;
@@ -139,6 +146,8 @@ struct Plan {
     int32_t n_slots = 0;  // partial-buffer slots (one tile-sized array each)
     std::vector<Item> h_fin;  // piece 0 of every split tile (the finishing launch)
     DevBuf fin;
+    std::vector<FinSeg> h_fseg;  // the split tiles cut into vertex segments
+    DevBuf fseg;
 };
 
 }  // namespace nxg

@@ -76,17 +76,17 @@ void store_cached(const std::string& key, const nxg_tune_result& r) {
     fclose(f);
 }
 
-// Mean milliseconds per iteration of `iters` PageRank iterations (after one
-// warm-up run) on a built handle.
+// Mean milliseconds per iteration of a captured 6-iteration PageRank run (the
+// first call records and replays it, the second one is timed).
 double time_run(nxg_dsss* g, const nxg_run_desc& base, void* values, int piece, hipStream_t s) {
     nxg_run_desc d = base;
     d.d_values = values;
     d.piece_chunks = piece;
     d.tol = 0.0;
-    nxg_run_stats st;
-    d.max_iters = 2;
-    run_program(g, d, s, &st);
+    d.flags |= NXG_RUN_CAPTURE;
     d.max_iters = 6;
+    nxg_run_stats st;
+    run_program(g, d, s, &st);
     run_program(g, d, s, &st);
     return st.device_ms / d.max_iters;
 }
@@ -166,7 +166,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     const int intervals[] = {1024, 2048, 4096, 8192, 16384};
     for (int I : intervals) {
         if (I > desc.n) continue;
-        for (int T : {tmax, tmax / 2})
+        for (int T : {tmax, tmax / 2, tmax / 4})
             if (!(I == I0 && T == tmax))
                 try_layout(stage1.relabel, stage1.order, I, T, 1024, no_piece, 1);
     }
