@@ -38,20 +38,22 @@ def kernel_sha():
 
 
 def measured_traffic(cfg):
-    """HBM bytes per iteration (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe's
-    reading) from committed rocprofv3 counter runs, if they were taken on the
-    current kernel source with the same layout (else None)."""
+    """HBM bytes per iteration (FETCH_SIZE + WRITE_SIZE of the iteration's three
+    kernels, scaled by the copy probe's reading) from committed rocprofv3 counter
+    runs, if one was taken on the current kernel source with the same layout
+    (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            entries = json.load(f).get("entries", [])
+    except (OSError, ValueError, AttributeError):
         return None
-    if t.get("kernel_sha") != kernel_sha():
-        return None
-    if any(t["config"].get(k) != cfg.get(k)
-           for k in ("interval", "tile", "chunk", "piece_chunks", "order", "relabel")):
-        return None
-    return t.get("bytes_per_iter")
+    sha = kernel_sha()
+    for t in entries:
+        if t.get("kernel_sha") == sha and all(
+                t["config"].get(k) == cfg.get(k)
+                for k in ("interval", "tile", "chunk", "piece_chunks", "order", "relabel")):
+            return t.get("bytes_per_iter")
+    return None
 
 
 def cpu_baseline_pagerank(src_d, dst_d, n, stride):

@@ -21,6 +21,16 @@
 #include "nxg_internal.h"
 
 namespace nxg {
+// Chunks per work item when the caller does not choose: about one item per
+// CU's share of the stream, but never so few that a piece's partial sums
+// (slot_bytes, written and read back once) exceed an eighth of the stream
+// bytes it covers.
+int default_piece(int64_t chunks, int C, size_t slot_bytes, int cus) {
+    const int64_t share = chunks / std::max(1, cus);
+    const int64_t floor_ = (int64_t)(8 * slot_bytes / (4 * (size_t)C)) + 1;
+    return (int)std::max<int64_t>(16, std::max(share, floor_));
+}
+
 namespace {
 
 constexpr uint32_t kMarker = 0x80000000u;
@@ -1392,16 +1402,6 @@ int num_cus(int device) {
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1)
         cu = 256;
     return cu;
-}
-
-// Chunks per work item when the caller does not choose: about one item per
-// CU's share of the stream, but never so few that a piece's partial sums
-// (slot_bytes, written and read back once) exceed an eighth of the stream
-// bytes it covers.
-int default_piece(int64_t chunks, int C, size_t slot_bytes, int cus) {
-    const int64_t share = chunks / std::max(1, cus);
-    const int64_t floor_ = (int64_t)(8 * slot_bytes / (4 * (size_t)C)) + 1;
-    return (int)std::max<int64_t>(16, std::max(share, floor_));
 }
 
 // Splits every tile into pieces of at most piece_chunks chunks; heavy tiles

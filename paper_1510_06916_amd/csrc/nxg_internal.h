@@ -199,5 +199,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
 nxg_status multi_run(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values, hipStream_t s,
                      nxg_run_stats* st);
 int lds_budget_bytes(int device);
+// Chunks per work item when a run does not choose (see iterate.hip).
+int default_piece(int64_t chunks, int C, size_t slot_bytes, int cus);
 nxg_status copy_probe(int64_t bytes, int reps, hipStream_t s, double* gbps);
 }  // namespace nxg
