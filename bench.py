@@ -143,6 +143,21 @@ def bench_pagerank(args, dev):
         log("destination-sorted sub-shards, natural ids: %.3f ms/step" % dsss_ms)
         del g2
         torch.cuda.empty_cache()
+    # the paper's comparison scheme: the edge list sorted by source, pushed into
+    # global sums with atomics (coarse-grained, Sec. IV-B1)
+    scatter_ms = None
+    if not args.no_ablation:
+        g3 = DSSS.build(src, dst, n, scatter=True)
+        out3 = torch.empty(n, dtype=torch.float32, device=dev)
+        g3.pagerank(1, dtype=torch.float32, out=out3, scatter=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g3.pagerank(4, dtype=torch.float32, out=out3, scatter=True)
+        torch.cuda.synchronize()
+        scatter_ms = (time.perf_counter() - t0) * 1e3 / 4
+        log("coarse-grained source-sorted scatter (I=%d): %.3f ms/step" % (g3.info()["interval"], scatter_ms))
+        del g3, out3
+        torch.cuda.empty_cache()
     copy_gbs = copy_probe(1 << 30, 10)
     log("copy probe: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic({"interval": inf["interval"], "tile": inf["tile"], "chunk": inf["chunk"],
@@ -160,7 +175,8 @@ def bench_pagerank(args, dev):
                    "tile": inf["tile"], "chunk": inf["chunk"], "piece_chunks": piece,
                    "order": order, "relabel": bool(best["relabel"]), "damping": 0.85,
                    "tuned_candidates": best["candidates"],
-                   "dst_sorted_natural_ids_ms_per_step": dsss_ms},
+                   "dst_sorted_natural_ids_ms_per_step": dsss_ms,
+                   "coarse_scatter_ms_per_step": scatter_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_iter": b_iter, "kernel_ms": kern_ms,

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 2
+#define NXG_ABI_VERSION 3
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -84,6 +84,16 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                                      run still takes and returns vertex data in
                                      the caller's ids (WCC labels stay the minimum
                                      caller id of the component) */
+#define NXG_BUILD_SCATTER 0x20u   /* the coarse-grained, source-sorted layout the
+                                     paper compares DSSS against (Sec. IV-B1,
+                                     Table IV): one destination tile spanning all
+                                     vertices and NXG_ORDER_SRC, so the stream is
+                                     the whole edge list in (source, destination)
+                                     order; I is capped at 2^(31 - ceil(log2 n))
+                                     so both fields fit one word. Only
+                                     NXG_RUN_SCATTER PageRank runs use it (the
+                                     tile has no LDS bound); not combinable with
+                                     NXG_BUILD_RELABEL or NXG_BUILD_TRANSPOSE */
 
 /* Order of the edges inside one sub-shard. */
 #define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */
@@ -180,6 +190,13 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
                                    hipGraph kept by the handle (with its workspace) and replay
                                    it when a later run has the same program, dtype, iteration
                                    count, damping, flags, buffers and piece size */
+#define NXG_RUN_SCATTER 0x8u    /* PageRank (plain or weighted, F32 or F64, batch 1) on a
+                                   NXG_BUILD_SCATTER layout, coarse-grained: every edge adds
+                                   its source's share to its destination with a device-scope
+                                   FP64 atomic in global memory, the GPU form of the paper's
+                                   lock-based source-sorted comparison (Sec. IV-B1). Same
+                                   results as the DSSS runs up to the order of the additions;
+                                   not combinable with NXG_RUN_CAPTURE */
 
 typedef struct nxg_run_desc {
     nxg_program program;

@@ -105,7 +105,9 @@ class DSSS:
     @classmethod
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
               value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
-              order="dst", relabel=False, stream=None):
+              order="dst", relabel=False, scatter=False, stream=None):
+        """scatter=True builds the coarse-grained source-sorted layout
+        (NXG_BUILD_SCATTER) that only pagerank(..., scatter=True) runs."""
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -123,7 +125,8 @@ class DSSS:
                  (_lib.NXG_BUILD_TRANSPOSE if transpose else 0) |
                  (_lib.NXG_BUILD_SYMMETRIZE if symmetrize else 0) |
                  (_lib.NXG_BUILD_DEDUP if dedup else 0) |
-                 (_lib.NXG_BUILD_RELABEL if relabel else 0))
+                 (_lib.NXG_BUILD_RELABEL if relabel else 0) |
+                 (_lib.NXG_BUILD_SCATTER if scatter else 0))
         d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,
@@ -198,7 +201,7 @@ class DSSS:
         return out
 
     def pagerank(self, iters, damping=0.85, dtype=torch.float32, tol=0.0, teleport=None,
-                 x0=None, weighted=False, out=None, capture=False, piece_chunks=0):
+                 x0=None, weighted=False, out=None, capture=False, piece_chunks=0, scatter=False):
         n = self.n
         if dtype not in _DT:
             raise ValueError("dtype must be float32 or float64")
@@ -210,6 +213,8 @@ class DSSS:
         tp = None
         if teleport is not None:
             tp = teleport.to(device=self.device, dtype=dtype).contiguous()
+        if scatter:
+            flags |= _lib.NXG_RUN_SCATTER
         if capture:
             flags |= _lib.NXG_RUN_CAPTURE
             self._keep = getattr(self, "_keep", [])

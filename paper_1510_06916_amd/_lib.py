@@ -14,12 +14,14 @@ NXG_BUILD_TRANSPOSE = 0x2
 NXG_BUILD_SYMMETRIZE = 0x4
 NXG_BUILD_DEDUP = 0x8
 NXG_BUILD_RELABEL = 0x10
+NXG_BUILD_SCATTER = 0x20
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
 NXG_RUN_WARM_START = 0x1
 NXG_RUN_PERSISTENT = 0x2
 NXG_RUN_CAPTURE = 0x4
+NXG_RUN_SCATTER = 0x8
 NXG_ORDER_DST, NXG_ORDER_SRC = 0, 1
 
 

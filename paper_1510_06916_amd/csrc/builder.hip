@@ -581,6 +581,27 @@ void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     if (tmax * vb > budget) fail(NXG_EINVAL, "value_bytes too large for the LDS of one workgroup");
     int64_t I = d.interval;
     if (I < 0) fail(NXG_EINVAL, "interval must be >= 0");
+    if (d.flags & NXG_BUILD_SCATTER) {
+        // one tile over all vertices, source order; the interval shrinks until
+        // the source and destination fields fit one word
+        const int t = ceil_log2(n);
+        if (t > 30) fail(NXG_EINVAL, "n too large for a SCATTER layout");
+        const int64_t imax = std::min<int64_t>(n, (int64_t)1 << (31 - t));
+        if (I == 0 || I > imax) I = imax;
+        L.n = (int32_t)n;
+        L.I = (int32_t)I;
+        L.P = (int32_t)((n + I - 1) / I);
+        L.L = ceil_log2(I);
+        L.T = (int32_t)1 << t;
+        L.t = t;
+        L.n_tiles = 1;
+        if (L.P > (1 << 27)) fail(NXG_EINVAL, "too many source intervals");
+        L.order = NXG_ORDER_SRC;
+        int64_t C = d.chunk ? d.chunk : 2048;
+        if (C < 256 || C > 65536 || (C & (C - 1))) fail(NXG_EINVAL, "chunk must be a power of two in [256, 65536]");
+        L.C = (int32_t)C;
+        return;
+    }
     if (I == 0) {
         // square DSSS with the interval equal to the largest tile that fits in LDS,
         // but never fewer than ~sqrt(n) vertices per interval (keeps P <= I)

@@ -136,8 +136,10 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
             fail(NXG_EINVAL, "too many edges");
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
-                                  NXG_BUILD_DEDUP | NXG_BUILD_RELABEL))
+                                  NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER))
             fail(NXG_EINVAL, "unknown build flag");
+        if ((d.flags & NXG_BUILD_SCATTER) && (d.flags & (NXG_BUILD_RELABEL | NXG_BUILD_TRANSPOSE)))
+            fail(NXG_EINVAL, "SCATTER cannot be combined with RELABEL or TRANSPOSE");
         if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
             fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
         if (d.interval < 0 || d.interval > d.n) fail(NXG_EINVAL, "interval outside [0, n]");

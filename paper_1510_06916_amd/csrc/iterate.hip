@@ -850,6 +850,104 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Coarse-grained, source-sorted comparison (NXG_RUN_SCATTER): the stream is the
+// whole edge list in (source, destination) order, one wave per chunk, and every
+// edge adds its source's share to its destination with a device-scope FP64
+// atomic in global memory (the paper's lock-based scheme of Sec. IV-B1).
+// ---------------------------------------------------------------------------
+template <typename V, bool kW>
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t* __restrict__ words,
+                                                 const int32_t* __restrict__ chunk_row, int64_t n_chunks,
+                                                 int C, int I, int Lb, int t, const V* __restrict__ cur,
+                                                 const float* __restrict__ wts, double* __restrict__ y) {
+    const int lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t lmask = (1u << Lb) - 1u, tmask = (1u << t) - 1u;
+    const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+    for (int64_t c = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6));
+         c < n_chunks; c += nwaves) {
+        uint32_t row = (uint32_t)chunk_row[c];
+        const int64_t base = c * (int64_t)C;
+        for (int s0 = 0; s0 < C; s0 += 64) {
+            const uint32_t w = __builtin_nontemporal_load(words + base + s0 + lane);
+            const uint64_t mm = __ballot((w >> 31) != 0);
+            uint32_t r = row;
+            if (mm) {
+                const uint64_t upto = mm & (lt | (1ull << lane));
+                const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
+                r = upto ? got : row;
+                row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
+            }
+            if ((w >> 31) == 0) {
+                const uint32_t src = r * (uint32_t)I + ((w >> t) & lmask);
+                double v = (double)cur[src];
+                if constexpr (kW) v *= (double)wts[base + s0 + lane];
+                unsafeAtomicAdd(&y[w & tmask], v);
+            }
+        }
+    }
+}
+
+// The update of every vertex from the global sums y (which it clears for the
+// next iteration), with per-block partial scalars [3] (dangling mass, residual,
+// sum) as in the tiled apply. divide: the gathered array is x / outdeg.
+template <typename V>
+__global__ __launch_bounds__(256) void k_scatter_apply(int32_t n, double* __restrict__ y,
+                                                       const int32_t* __restrict__ deg,
+                                                       const V* __restrict__ cur, V* __restrict__ nxt,
+                                                       const V* __restrict__ tele, V* __restrict__ xout,
+                                                       double d, int divide, const double* __restrict__ scal,
+                                                       double* __restrict__ part) {
+    __shared__ double red[3][4];
+    double sv[3] = {0.0, 0.0, 0.0};
+    const double delta = *scal;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const double acc = y[v];
+        y[v] = 0.0;
+        const int32_t dg = deg[v];
+        const double c = (double)cur[v];
+        const double xo = (divide && dg) ? c * dg : c;
+        const double tv = tele ? (double)tele[v] : 1.0 / n;
+        const V xr = (V)(d * (acc + delta / n) + (1.0 - d) * tv);
+        sv[1] += fabs((double)xr - xo);
+        sv[2] += (double)xr;
+        if (dg == 0) sv[0] += (double)xr;
+        nxt[v] = (divide && dg) ? (V)((double)xr / dg) : xr;
+        if (xout) xout[v] = xr;
+    }
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sv[q] = wave_sum(sv[q]);
+        if (lane == 0) red[q][wave] = sv[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] +
+                                                              red[threadIdx.x][2] + red[threadIdx.x][3];
+}
+
+// Block partials in block order: delta entering k + 1, residual and sum of k.
+__global__ void k_scatter_reduce(const double* __restrict__ part, int nb, double* __restrict__ stats, int k,
+                                 double tol, int32_t* __restrict__ done) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t3[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 3; ++q) t3[q] += part[b * 3 + q];
+    stats[(k + 1) * 4 + 0] = t3[0];
+    stats[k * 4 + 1] = t3[1];
+    stats[k * 4 + 2] = t3[2];
+    if (tol > 0.0 && t3[1] <= tol) *done = 1;
+}
+
+// x from the gathered array (x / outdeg where divide is set).
+template <typename V>
+__global__ void k_unscale(int32_t n, const int32_t* __restrict__ deg, const V* __restrict__ cur, int divide,
+                          V* __restrict__ out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = (divide && deg[v]) ? (V)((double)cur[v] * deg[v]) : cur[v];
+}
+
 __global__ void k_init_bfs(int32_t n, int32_t root, int32_t* __restrict__ lev,
                            uint8_t* __restrict__ act, int P, int I) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -1737,6 +1835,98 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
     return NXG_OK;
 }
 
+// PageRank by coarse-grained push over the source-sorted stream (NXG_RUN_SCATTER).
+template <typename V>
+nxg_status run_scatter(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const Layout& L = g->fwd;
+    const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
+    if (!(g->flags & NXG_BUILD_SCATTER)) fail(NXG_EINVAL, "NXG_RUN_SCATTER needs a NXG_BUILD_SCATTER layout");
+    if (d.flags & NXG_RUN_CAPTURE) fail(NXG_EINVAL, "NXG_RUN_SCATTER runs cannot be captured");
+    if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
+    const int max_iters = d.max_iters;
+    Workspace w;
+    w.buf[0].alloc(sizeof(V) * L.n, s);
+    w.buf[1].alloc(sizeof(V) * L.n, s);
+    w.partial.alloc(sizeof(double) * L.n, s);  // the global sums y
+    NXG_HIP(hipMemsetAsync(w.partial.p, 0, sizeof(double) * L.n, s));
+    const int nb = grid_for(L.n, 256, 1024);
+    w.part.alloc(sizeof(double) * 3 * nb, s);
+    const size_t nstat = 4 * (size_t)(max_iters + 2);
+    w.stats.alloc(sizeof(double) * nstat, s);
+    NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * nstat, s));
+    w.done.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
+    const V* tele = (const V*)d.d_teleport;
+    V* vals = (V*)d.d_values;
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? vals : nullptr;
+    const int divide = weighted ? 0 : 1;
+    hipLaunchKernelGGL(k_init_pr<V>, dim3(nb), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(), tele, x0, divide,
+                       w.buf[0].as<V>(), w.part.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb, w.stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    const int sgrid = grid_for(L.n_chunks * 64, 256, 16384);
+    hipEvent_t e0, e1;
+    NXG_HIP(hipEventCreate(&e0));
+    NXG_HIP(hipEventCreate(&e1));
+    NXG_HIP(hipEventRecord(e0, s));
+    int k = 0, done_h = 0;
+    for (; k < max_iters; ++k) {
+        const V* cur = w.buf[k & 1].as<V>();
+        V* nxt = w.buf[(k + 1) & 1].as<V>();
+        if (L.n_chunks > 0) {
+            if (weighted)
+                hipLaunchKernelGGL((k_scatter<V, true>), dim3(sgrid), dim3(256), 0, s, L.words.as<uint32_t>(),
+                                   L.chunk_row.as<int32_t>(), L.n_chunks, L.C, L.I, L.L, L.t, cur,
+                                   L.weight.as<float>(), w.partial.as<double>());
+            else
+                hipLaunchKernelGGL((k_scatter<V, false>), dim3(sgrid), dim3(256), 0, s, L.words.as<uint32_t>(),
+                                   L.chunk_row.as<int32_t>(), L.n_chunks, L.C, L.I, L.L, L.t, cur,
+                                   (const float*)nullptr, w.partial.as<double>());
+            NXG_CHECK_LAUNCH();
+        }
+        // with a tolerance every iteration writes x, so the last one run is the result
+        V* xout = (d.tol > 0 || k == max_iters - 1) ? vals : nullptr;
+        hipLaunchKernelGGL(k_scatter_apply<V>, dim3(nb), dim3(256), 0, s, L.n, w.partial.as<double>(),
+                           L.outdeg.as<int32_t>(), cur, nxt, tele, xout, d.damping, divide,
+                           w.stats.as<double>() + 4 * k, w.part.as<double>());
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_scatter_reduce, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb,
+                           w.stats.as<double>(), k, d.tol, w.done.as<int32_t>());
+        NXG_CHECK_LAUNCH();
+        if (d.tol > 0) {
+            NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (done_h) {
+                ++k;
+                break;
+            }
+        }
+    }
+    if (max_iters == 0) {
+        hipLaunchKernelGGL(k_unscale<V>, dim3(grid_for(L.n)), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
+                           w.buf[0].as<V>(), divide, vals);
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipEventRecord(e1, s));
+    std::vector<double> hs(nstat);
+    NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    NXG_HIP(hipEventDestroy(e0));
+    NXG_HIP(hipEventDestroy(e1));
+    const bool conv = d.tol > 0 && done_h;
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = k;
+        st->converged = conv ? 1 : 0;
+        st->residual = k > 0 ? hs[4 * (k - 1) + 1] : 0.0;
+        st->device_ms = ms;
+    }
+    return (d.tol > 0 && !conv) ? NXG_ENOTCONV : NXG_OK;
+}
+
 template <typename V>
 nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     const Layout& L = g->fwd;
@@ -2494,6 +2684,16 @@ int lds_budget_bytes(int device) {
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
     if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    if ((d.flags & NXG_RUN_SCATTER) || (g->flags & NXG_BUILD_SCATTER)) {
+        if (!(d.flags & NXG_RUN_SCATTER)) fail(NXG_EINVAL, "a NXG_BUILD_SCATTER layout runs only NXG_RUN_SCATTER PageRank");
+        if (d.batch > 1 || d.d_seeds) fail(NXG_EUNSUPPORTED, "NXG_RUN_SCATTER runs one column");
+        if (d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED)
+            fail(NXG_EUNSUPPORTED, "NXG_RUN_SCATTER runs PageRank");
+        if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+        if (d.dtype == NXG_F32) return run_scatter<float>(g, d, s, st);
+        if (d.dtype == NXG_F64) return run_scatter<double>(g, d, s, st);
+        fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
+    }
     if (d.batch > 1 || d.d_seeds) {
         if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
         return run_batched(g, d, s, st);

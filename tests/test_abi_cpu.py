@@ -53,6 +53,8 @@ def test_host_side_argument_errors(L):
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
     d = _lib.BuildDesc(n=10, m=0, flags=_lib.NXG_BUILD_SYMMETRIZE | _lib.NXG_BUILD_KEEP_PERM)
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
+    d = _lib.BuildDesc(n=10, m=0, flags=_lib.NXG_BUILD_SCATTER | _lib.NXG_BUILD_RELABEL)
+    assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
     d = _lib.BuildDesc(n=10, m=0, interval=11)
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
     assert L.nxg_dsss_destroy(None) == _lib.NXG_OK
