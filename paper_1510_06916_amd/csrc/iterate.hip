@@ -37,6 +37,10 @@ constexpr uint32_t kMarker = 0x80000000u;
 constexpr uint32_t kNoDst = 0xFFFFFFFFu;  // decoded destination of a marker or padding word
 constexpr int32_t kInf = INT32_MAX;
 constexpr int kSpill = 64;  // LDS accumulators past the tile: lane l's discard slot T + l
+// A split tile is finished in segments of kFinSeg vertices, one workgroup of
+// kFinWG threads (one vertex per thread) each, so a heavy tile's FromHub is
+// spread over many CUs and needs only kFinSeg accumulators of LDS.
+constexpr int kFinSeg = 256, kFinWG = 256;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -426,17 +430,17 @@ template <class Prog, int WG>
 __device__ void gather_hub(const Geo& g, const Prog& prog, const FinSeg& it, typename Prog::acc_t* acc) {
     using acc_t = typename Prog::acc_t;
     const int64_t len = it.vlen;
-    // eight slots per pass so the loads of a thread are independent
+    // sixteen slots per pass so the loads of a thread are independent
     const acc_t* p0 = reinterpret_cast<const acc_t*>(g.partial) + (int64_t)it.slot * g.T + it.v0;
     for (int64_t x = threadIdx.x; x < len; x += WG) {
         acc_t sum = prog.identity();
         int p = 0;
-        for (; p + 8 <= it.npieces; p += 8) {
-            acc_t v[8];
+        for (; p + 16 <= it.npieces; p += 16) {
+            acc_t v[16];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = __builtin_nontemporal_load(p0 + (int64_t)(p + q) * g.T + x);
+            for (int q = 0; q < 16; ++q) v[q] = __builtin_nontemporal_load(p0 + (int64_t)(p + q) * g.T + x);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) sum = combine<Prog::kSum>(sum, v[q]);
+            for (int q = 0; q < 16; ++q) sum = combine<Prog::kSum>(sum, v[q]);
         }
         for (; p < it.npieces; ++p)
             sum = combine<Prog::kSum>(sum, __builtin_nontemporal_load(p0 + (int64_t)p * g.T + x));
@@ -759,10 +763,12 @@ struct MultiGraph {
     double* stats;     // [4 * (iters + 2)]
     float* buf0;
     float* buf1;
-    float* xout;       // [n] result
+    float* xout;       // [n] result (in internal ids for a relabeled graph)
     int32_t* done0;    // a zero word (no tolerance stop in this mode)
     int32_t item_base; // first item of this graph in the global item array
     int32_t n_items;
+    const int32_t* o2n;  // relabeled graph: caller id -> internal id, else NULL
+    float* user;         // the caller's result buffer (written from xout when o2n is set)
 };
 
 template <int WG>
@@ -808,6 +814,37 @@ __global__ __launch_bounds__(WG) void k_multi_finish(const MultiGraph* __restric
     gather_hub<ProgPR<float>, WG>(mg.geo, prog, f.f, acc);
     apply_range<ProgPR<float>, WG>(mg.geo, ctl, prog, ((int64_t)f.f.tile << mg.geo.t) + f.f.v0, f.f.vlen,
                                    f.f.sslot, acc);
+}
+
+// One workgroup per graph: x^0 = 1/n (gathered array x^0 / outdeg) and the
+// dangling mass entering iteration 0, summed in a fixed order.
+__global__ __launch_bounds__(256) void k_multi_init(const MultiGraph* __restrict__ graphs) {
+    __shared__ double red[4];
+    const MultiGraph& mg = graphs[blockIdx.x];
+    const int32_t n = mg.geo.n;
+    const float x = (float)(1.0 / n);
+    double sdang = 0.0;
+    for (int64_t v = threadIdx.x; v < n; v += 256) {
+        const int32_t dg = mg.geo.deg[v];
+        if (dg == 0) sdang += (double)x;
+        mg.buf0[v] = dg ? (float)((double)x / dg) : x;
+    }
+    sdang = wave_sum(sdang);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = sdang;
+    __syncthreads();
+    if (threadIdx.x == 0) mg.stats[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+// One workgroup per relabeled graph: the result into the caller's ids.
+__global__ __launch_bounds__(256) void k_multi_emit(const MultiGraph* __restrict__ graphs) {
+    const MultiGraph& mg = graphs[blockIdx.x];
+    if (!mg.o2n) return;
+    for (int64_t v = threadIdx.x; v < mg.geo.n; v += 256) mg.user[v] = mg.xout[mg.o2n[v]];
+}
+
+// The last iteration's residual of every graph, gathered for one copy to the host.
+__global__ void k_multi_residuals(const MultiGraph* __restrict__ graphs, int G, int k, double* __restrict__ out) {
+    for (int i = threadIdx.x; i < G; i += blockDim.x) out[i] = graphs[i].stats[4 * k + 1];
 }
 
 // One workgroup per graph: that graph's scalars in tile order.
@@ -1556,9 +1593,7 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
     if (!p->h_fin.empty())
         NXG_HIP(hipMemcpyAsync(p->fin.p, p->h_fin.data(), sizeof(Item) * p->h_fin.size(),
                                hipMemcpyHostToDevice, s));
-    // segments of kFinSeg vertices, so a heavy tile's FromHub is spread over
-    // many workgroups; scalar slots n_tiles, n_tiles + 1, ... in list order
-    constexpr int kFinSeg = 2048;
+    // segments of kFinSeg vertices; scalar slots n_tiles, n_tiles + 1, ... in list order
     for (const Item& it : p->h_fin) {
         const int64_t base = (int64_t)it.tile * L.T;
         const int64_t len = std::max<int64_t>(0, std::min<int64_t>(L.T, (int64_t)L.n - base));
@@ -1586,6 +1621,16 @@ struct Workspace {
     DevBuf buf[2], partial, tile_s, tile_flag, stats, done, act, apref, clist,
         ccount, part, bfsout;
     DevBuf mtele, mvals, mseeds, mgx, mxs;  // caller data in internal ids (relabeled builds)
+};
+
+// What a multi-graph handle keeps between runs: per-graph workspaces, the
+// descriptor and item arrays (device and host).
+struct MultiCache : Cached {
+    int iters = 0, piece = 0, per_iter = 0, n_fin = 0;
+    size_t lds = 0;
+    std::vector<Workspace> ws;
+    std::vector<MultiGraph> hdesc;
+    DevBuf ditems, dprefix, ddesc, dfin, dres;
 };
 
 // Index arrays of a relabeled build (both NULL otherwise).
@@ -1619,8 +1664,6 @@ void prepare_iter(size_t lds) {
     if (lds > attr_lds) {
         NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        NXG_HIP(hipFuncSetAttribute((const void*)k_finish<Prog, WG>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_lds = lds;
     }
 }
@@ -1637,8 +1680,8 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p
         NXG_CHECK_LAUNCH();
     }
     if (!p.h_fseg.empty()) {
-        hipLaunchKernelGGL((k_finish<Prog, WG>), dim3((int)p.h_fseg.size()), dim3(WG), lds, s, geo, ctl,
-                           prog, p.fseg.as<FinSeg>());
+        hipLaunchKernelGGL((k_finish<Prog, kFinWG>), dim3((int)p.h_fseg.size()), dim3(kFinWG),
+                           kFinSeg * sizeof(typename Prog::acc_t), s, geo, ctl, prog, p.fseg.as<FinSeg>());
         NXG_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL((k_reduce<Prog, 1024>), dim3(1), dim3(1024), 0, s, geo, ctl);
@@ -2365,92 +2408,108 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         for (nxg_dsss* g : mg->graphs) minC = std::min(minC, g->fwd.C);
         piece = default_piece(chunks, minC, (size_t)maxT * 8, cus);
     }
-    // per-graph plans, workspaces and descriptors
-    std::vector<Item> all_items;
-    std::vector<MultiFin> all_fin;
-    std::vector<int32_t> prefix(1, 0);
-    std::vector<MultiGraph> hdesc(G);
-    std::vector<Workspace> ws(G);
-    const int nbp = 64;
-    DevBuf parts;
-    parts.alloc(sizeof(double) * nbp * G, s);
-    for (int i = 0; i < G; ++i) {
-        nxg_dsss* g = mg->graphs[i];
-        const Layout& L = g->fwd;
-        Plan* p = get_plan(g, L, piece, false, s);
-        Workspace& w = ws[i];
-        alloc_common(w, L, *p, 8, iters, s, false);
-        w.buf[0].alloc(sizeof(float) * (L.n), s);
-        w.buf[1].alloc(sizeof(float) * (L.n), s);
-        hipLaunchKernelGGL(k_init_pr<float>, dim3(nbp), dim3(256), 0, s, L.n, L.outdeg.as<int32_t>(),
-                           (const float*)nullptr, (const float*)nullptr, 1, w.buf[0].as<float>(),
-                           parts.as<double>() + (size_t)nbp * i);
-        NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, parts.as<double>() + (size_t)nbp * i,
-                           nbp, w.stats.as<double>());
-        NXG_CHECK_LAUNCH();
-        MultiGraph& m = hdesc[i];
-        m.geo = make_geo(L, *p, w, 8);
-        lds = std::max(lds, iter_lds(m.geo, L, 8));
-        m.stats = w.stats.as<double>();
-        m.buf0 = w.buf[0].as<float>();
-        m.buf1 = w.buf[1].as<float>();
-        m.xout = (float*)d_values[i];
-        if (g->relabeled) {
-            w.mvals.alloc(sizeof(float) * L.n, s);
-            m.xout = w.mvals.as<float>();
+    // per-graph plans, workspaces and descriptors, kept by the handle for the
+    // next run with the same iteration count and piece size
+    MultiCache* c = dynamic_cast<MultiCache*>(mg->run_cache);
+    if (!c || c->iters != iters || c->piece != piece) {
+        delete mg->run_cache;
+        mg->run_cache = nullptr;
+        std::unique_ptr<MultiCache> nc(new MultiCache());
+        nc->iters = iters;
+        nc->piece = piece;
+        nc->ws.resize(G);
+        nc->hdesc.resize(G);
+        std::vector<Item> all_items;
+        std::vector<MultiFin> all_fin;
+        std::vector<int32_t> prefix(1, 0);
+        for (int i = 0; i < G; ++i) {
+            nxg_dsss* g = mg->graphs[i];
+            const Layout& L = g->fwd;
+            Plan* p = get_plan(g, L, piece, false, s);
+            Workspace& w = nc->ws[i];
+            alloc_common(w, L, *p, 8, iters, s, false);
+            w.buf[0].alloc(sizeof(float) * (L.n), s);
+            w.buf[1].alloc(sizeof(float) * (L.n), s);
+            MultiGraph& m = nc->hdesc[i];
+            m.geo = make_geo(L, *p, w, 8);
+            lds = std::max(lds, iter_lds(m.geo, L, 8));
+            m.stats = w.stats.as<double>();
+            m.buf0 = w.buf[0].as<float>();
+            m.buf1 = w.buf[1].as<float>();
+            m.o2n = nullptr;
+            if (g->relabeled) {
+                w.mvals.alloc(sizeof(float) * L.n, s);
+                m.xout = w.mvals.as<float>();
+                m.o2n = g->old2new.as<int32_t>();
+            }
+            m.done0 = w.done.as<int32_t>();
+            m.item_base = (int32_t)all_items.size();
+            m.n_items = (int32_t)p->h_items.size();
+            all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
+            for (const FinSeg& f : p->h_fseg) all_fin.push_back(MultiFin{i, f});
+            prefix.push_back((int32_t)all_items.size());
         }
-        m.done0 = w.done.as<int32_t>();
-        m.item_base = (int32_t)all_items.size();
-        m.n_items = (int32_t)p->h_items.size();
-        all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
-        for (const FinSeg& f : p->h_fseg) all_fin.push_back(MultiFin{i, f});
-        prefix.push_back((int32_t)all_items.size());
-    }
-    DevBuf ditems, dprefix, ddesc, dfin;
-    dfin.alloc(sizeof(MultiFin) * std::max<size_t>(all_fin.size(), 1), s);
-    if (!all_fin.empty())
-        NXG_HIP(hipMemcpyAsync(dfin.p, all_fin.data(), sizeof(MultiFin) * all_fin.size(),
+        nc->lds = lds;
+        nc->per_iter = prefix.back();
+        nc->n_fin = (int)all_fin.size();
+        nc->dfin.alloc(sizeof(MultiFin) * std::max<size_t>(all_fin.size(), 1), s);
+        if (!all_fin.empty())
+            NXG_HIP(hipMemcpyAsync(nc->dfin.p, all_fin.data(), sizeof(MultiFin) * all_fin.size(),
+                                   hipMemcpyHostToDevice, s));
+        nc->ditems.alloc(sizeof(Item) * all_items.size(), s);
+        nc->dprefix.alloc(sizeof(int32_t) * prefix.size(), s);
+        nc->ddesc.alloc(sizeof(MultiGraph) * G, s);
+        nc->dres.alloc(sizeof(double) * G, s);
+        NXG_HIP(hipMemcpyAsync(nc->ditems.p, all_items.data(), sizeof(Item) * all_items.size(),
                                hipMemcpyHostToDevice, s));
-    ditems.alloc(sizeof(Item) * all_items.size(), s);
-    dprefix.alloc(sizeof(int32_t) * prefix.size(), s);
-    ddesc.alloc(sizeof(MultiGraph) * G, s);
-    NXG_HIP(hipMemcpyAsync(ditems.p, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice, s));
-    NXG_HIP(hipMemcpyAsync(dprefix.p, prefix.data(), sizeof(int32_t) * prefix.size(), hipMemcpyHostToDevice, s));
-    NXG_HIP(hipMemcpyAsync(ddesc.p, hdesc.data(), sizeof(MultiGraph) * G, hipMemcpyHostToDevice, s));
+        NXG_HIP(hipMemcpyAsync(nc->dprefix.p, prefix.data(), sizeof(int32_t) * prefix.size(),
+                               hipMemcpyHostToDevice, s));
+        NXG_HIP(hipStreamSynchronize(s));  // the host vectors above go out of scope
+        c = nc.release();
+        mg->run_cache = c;
+    }
+    lds = c->lds;
+    // the caller's buffers of this run
+    for (int i = 0; i < G; ++i) {
+        MultiGraph& m = c->hdesc[i];
+        m.user = (float*)d_values[i];
+        if (!m.o2n) m.xout = m.user;
+    }
+    NXG_HIP(hipMemcpyAsync(c->ddesc.p, c->hdesc.data(), sizeof(MultiGraph) * G, hipMemcpyHostToDevice, s));
     static size_t attr = 0;
     if (lds > attr) {
         NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_finish<1024>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = lds;
     }
-    const int per_iter = prefix.back();
+    const MultiGraph* ddesc = c->ddesc.as<MultiGraph>();
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
     NXG_HIP(hipEventCreate(&e1));
     NXG_HIP(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_multi_init, dim3(G), dim3(256), 0, s, ddesc);
+    NXG_CHECK_LAUNCH();
     for (int k = 0; k < iters; ++k) {
-        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(per_iter), dim3(1024), lds, s,
-                           ddesc.as<MultiGraph>(), G, dprefix.as<int32_t>(), ditems.as<Item>(), k,
-                           iters, d.damping);
+        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, s, ddesc, G,
+                           c->dprefix.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
         NXG_CHECK_LAUNCH();
-        if (!all_fin.empty()) {
-            hipLaunchKernelGGL(k_multi_finish<1024>, dim3((int)all_fin.size()), dim3(1024), lds, s,
-                               ddesc.as<MultiGraph>(), dfin.as<MultiFin>(), k, iters, d.damping);
+        if (c->n_fin > 0) {
+            hipLaunchKernelGGL(k_multi_finish<kFinWG>, dim3(c->n_fin), dim3(kFinWG), kFinSeg * sizeof(double),
+                               s, ddesc, c->dfin.as<MultiFin>(), k, iters, d.damping);
             NXG_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, s, ddesc.as<MultiGraph>(), k);
+        hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, s, ddesc, k);
         NXG_CHECK_LAUNCH();
     }
-    for (int i = 0; i < G; ++i) {
-        const VMap vm = vmap_of(mg->graphs[i]);
-        if (vm)
-            permute_rows<float>(ws[i].mvals.as<float>(), vm.o2n, mg->graphs[i]->fwd.n, 1,
-                                (float*)d_values[i], s);
-    }
+    hipLaunchKernelGGL(k_multi_emit, dim3(G), dim3(256), 0, s, ddesc);
+    NXG_CHECK_LAUNCH();
     NXG_HIP(hipEventRecord(e1, s));
+    std::vector<double> res(G);
+    if (st) {
+        hipLaunchKernelGGL(k_multi_residuals, dim3(1), dim3(256), 0, s, ddesc, G, iters - 1, c->dres.as<double>());
+        NXG_CHECK_LAUNCH();
+        NXG_HIP(hipMemcpyAsync(res.data(), c->dres.p, sizeof(double) * G, hipMemcpyDeviceToHost, s));
+    }
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -2458,12 +2517,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     NXG_HIP(hipEventDestroy(e1));
     if (st) {
         double worst = 0.0;
-        std::vector<double> hs(4);
-        for (int i = 0; i < G; ++i) {
-            NXG_HIP(hipMemcpy(hs.data(), ws[i].stats.as<double>() + 4 * (iters - 1), sizeof(double) * 4,
-                              hipMemcpyDeviceToHost));
-            worst = std::max(worst, hs[1]);
-        }
+        for (double r : res) worst = std::max(worst, r);
         memset(st, 0, sizeof(*st));
         st->iterations = iters;
         st->residual = worst;

@@ -174,7 +174,9 @@ struct nxg_dsss {
 
 struct nxg_multi {
     std::vector<nxg_dsss*> graphs;
+    nxg::Cached* run_cache = nullptr;  // workspaces of the last run (released first)
     ~nxg_multi() {
+        delete run_cache;
         for (nxg_dsss* g : graphs) delete g;
     }
 };
