@@ -1013,8 +1013,10 @@ __global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, uint8_t* __rest
 // write are cleared here.
 __global__ __launch_bounds__(1024) void k_activity(const uint8_t* __restrict__ act, int P,
                                                    int32_t* __restrict__ apref,
-                                                   uint8_t* __restrict__ act_next) {
+                                                   uint8_t* __restrict__ act_next,
+                                                   int32_t* __restrict__ ccount, int n_tiles) {
     __shared__ int32_t part[1024];
+    for (int x = threadIdx.x; x < n_tiles; x += 1024) ccount[x] = 0;  // k_compact appends
     const int per = (P + 1023) / 1024;
     const int a = threadIdx.x * per, b = min(P, a + per);
     int32_t s = 0;
@@ -1039,35 +1041,47 @@ __global__ __launch_bounds__(1024) void k_activity(const uint8_t* __restrict__ a
 }
 
 // Frontier compaction: per tile, the chunks that touch at least one active
-// source interval, in stream order, stored from the tile's first chunk on.
-__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tchunk,
-                                                 const int32_t* __restrict__ crow,
+// source interval, stored from the tile's first chunk on. One thread per chunk;
+// the lanes of a wave that belong to one tile take their places with a single
+// atomic on the tile's count, so the order inside a tile's list varies from
+// run to run. BFS and WCC take integer minima, so their results do not depend
+// on it.
+__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tchunk, int n_tiles,
+                                                 int64_t n_chunks, const int32_t* __restrict__ crow,
                                                  const int32_t* __restrict__ crow_last,
                                                  const int32_t* __restrict__ apref,
                                                  int64_t* __restrict__ clist,
                                                  int32_t* __restrict__ ccount) {
-    __shared__ int32_t wsum[4];
-    __shared__ int32_t run;
-    const int tile = blockIdx.x;
-    const int64_t c0 = tchunk[tile], c1 = tchunk[tile + 1];
-    if (threadIdx.x == 0) run = 0;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6;
-    for (int64_t b = c0; b < c1; b += 256) {
-        int64_t c = b + threadIdx.x;
+    const int lane = lane_id();
+    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < n_chunks; c0 += (int64_t)gridDim.x * 256) {
+        const int64_t c = c0 + threadIdx.x;
         bool keep = false;
-        if (c < c1) keep = apref[crow_last[c] + 1] - apref[crow[c]] > 0;
-        uint64_t bal = __ballot(keep);
-        if (lane_id() == 0) wsum[wave] = __popcll(bal);
-        __syncthreads();
-        int32_t before = run;
-        for (int w = 0; w < wave; ++w) before += wsum[w];
-        if (keep) clist[c0 + before + __popcll(bal & ((1ull << lane_id()) - 1ull))] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        __syncthreads();
+        int tile = 0;
+        if (c < n_chunks) {
+            keep = apref[crow_last[c] + 1] - apref[crow[c]] > 0;
+            // the tile holding chunk c: last tau with tchunk[tau] <= c
+            int lo = 0, hi = n_tiles;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tchunk[mid] <= c)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            tile = lo;
+        }
+        uint64_t pending = __ballot(keep);
+        while (pending) {  // one round per distinct tile among the kept lanes
+            const int leader = __builtin_ctzll(pending);
+            const int t = __shfl(tile, leader);
+            const uint64_t mine = __ballot(keep && tile == t);
+            int32_t base = 0;
+            if (lane == leader) base = atomicAdd(&ccount[t], __popcll(mine));
+            base = __shfl(base, leader);
+            if (keep && tile == t) clist[tchunk[t] + base + __popcll(mine & ((1ull << lane) - 1ull))] = c;
+            pending &= ~mine;
+        }
     }
-    if (threadIdx.x == 0) ccount[tile] = run;
 }
 
 // BFS output (Alg. 4) plus the reached-edge count used for TEPS.
@@ -2159,11 +2173,14 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             uint8_t* act_cur = act0 + (size_t)(k & 1) * L.P;
             uint8_t* act_nxt = act0 + (size_t)((k + 1) & 1) * L.P;
             hipLaunchKernelGGL(k_activity, dim3(1), dim3(1024), 0, s, act_cur, L.P,
-                               w.apref.as<int32_t>(), act_nxt);
+                               w.apref.as<int32_t>(), act_nxt, w.ccount.as<int32_t>(), L.n_tiles);
             NXG_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_compact, dim3(L.n_tiles), dim3(256), 0, s, L.tile_chunk.as<int64_t>(),
-                               L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
-                               w.apref.as<int32_t>(), w.clist.as<int64_t>(), w.ccount.as<int32_t>());
+            if (L.n_chunks > 0) {
+                hipLaunchKernelGGL(k_compact, dim3(grid_for(L.n_chunks, 256, 4096)), dim3(256), 0, s,
+                                   L.tile_chunk.as<int64_t>(), L.n_tiles, L.n_chunks,
+                                   L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
+                                   w.apref.as<int32_t>(), w.clist.as<int64_t>(), w.ccount.as<int32_t>());
+            }
             NXG_CHECK_LAUNCH();
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k - kb, 0.0};
             const int32_t* cur = w.buf[k & 1].as<int32_t>();
