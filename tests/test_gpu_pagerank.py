@@ -91,3 +91,36 @@ def test_weighted_fp64(gpu_device):
     ref, _ = oracle.pagerank(n, src, dst, iters=15, w=w.astype(np.float64))
     x, _ = g.pagerank(15, dtype=torch.float64, weighted=True)
     assert rel_l1(x.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("order,relabel", [("dst", False), ("src", True)])
+def test_extreme_hub_ragged_n_many_pieces(gpu_device, order, relabel, monkeypatch):
+    # every vertex points at vertex 7 (one tile holds a fifth of the edges), plus
+    # R-MAT edges; n is not a multiple of any tile or interval; pieces of 2
+    # chunks force hundreds of hub slots and finishing segments
+    n = 100003
+    rs, rd = rmatgen.rmat_edges(16, 8, seed=41)
+    rs, rd = rs % n, rd % n
+    hub_s = np.arange(n, dtype=np.int64)
+    src = np.concatenate([rs, hub_s]).astype(np.int32)
+    dst = np.concatenate([rd, np.full(n, 7)]).astype(np.int32)
+    key = np.unique(src.astype(np.int64) * n + dst)
+    src, dst = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    ref, _ = oracle.pagerank(n, src, dst, iters=8)
+    monkeypatch.setenv("NXG_PIECE_CHUNKS", "2")
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=3000, tile=4096,
+                   chunk=256, order=order, relabel=relabel)
+    say("hub graph n=%d m=%d order=%s relabel=%s" % (n, len(src), order, relabel))
+    x, _ = g.pagerank(8, dtype=torch.float64)
+    # the hub sums ~1e5 terms in FP64 in another order than the oracle: the
+    # worst-case rounding of such a sum is k*u ~ 1e5 * 1.1e-16 ~ 1e-11 relative,
+    # and the hub carries most of the L1 mass, so the FP64 bar here is 1e-11
+    # (a lost or doubled piece would show as ~1e-3)
+    assert rel_l1(x.cpu().numpy(), ref) <= 1e-11
+    x32, _ = g.pagerank(8, dtype=torch.float32)
+    assert rel_l1(x32.cpu().numpy(), ref) <= 1e-5
+    gb = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=3000, tile=4096,
+                    chunk=256, value_bytes=4, order=order, relabel=relabel)
+    lev, st = gb.bfs(3)
+    rl, rounds, mx = oracle.bfs(n, src, dst, 3)
+    assert np.array_equal(lev.cpu().numpy(), rl) and st["max_level"] == mx
