@@ -21,6 +21,23 @@ constexpr uint32_t kMarker = 0x80000000u;
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// deg[id] += 1 for every valid lane of the wave, with one atomic per run of
+// equal ids in consecutive lanes (sorted inputs put a vertex's edges side by
+// side, so a hub's count no longer takes one contended atomic per edge). All
+// 64 lanes must call it.
+__device__ inline void add_degree_runs(int32_t* deg, uint32_t id, bool valid) {
+    const int lane = lane_id();
+    const uint32_t prev = (uint32_t)__shfl_up((int)id, 1);
+    const bool prev_valid = __shfl_up((int)valid, 1) != 0;
+    const bool head = valid && (lane == 0 || !prev_valid || prev != id);
+    const uint64_t bound = __ballot(head) | __ballot(!valid);
+    if (head) {
+        const uint64_t after = lane == 63 ? 0ull : bound >> (lane + 1);
+        const int len = after ? __builtin_ctzll(after) + 1 : 64 - lane;
+        atomicAdd(&deg[id], len);
+    }
+}
+
 // Lanes of the wavefront holding the same 8-bit digit as this lane.
 __device__ inline uint64_t match_digit(uint32_t digit, uint64_t valid) {
     uint64_t peers = valid;
@@ -223,13 +240,20 @@ __global__ __launch_bounds__(kRsBlock) void k_uniq_scatter(
 
 __global__ void k_outdeg(const uint64_t* __restrict__ keys, int64_t m, KeyGeom g,
                          int32_t* __restrict__ deg) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t k = keys[e];
-        uint32_t i = (uint32_t)((k >> (g.t + g.L)) % (uint64_t)g.P);
-        uint32_t sl = g.order == NXG_ORDER_SRC ? (uint32_t)(k >> g.t) & ((1u << g.L) - 1u)
-                                               : (uint32_t)k & ((1u << g.L) - 1u);
-        atomicAdd(&deg[i * (uint32_t)g.I + sl], 1);
+    // wave-uniform loop: every lane reaches the wave operations of add_degree_runs
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); e0 < m;
+         e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + lane_id();
+        const bool valid = e < m;
+        uint32_t id = 0;
+        if (valid) {
+            uint64_t k = keys[e];
+            uint32_t i = (uint32_t)((k >> (g.t + g.L)) % (uint64_t)g.P);
+            uint32_t sl = g.order == NXG_ORDER_SRC ? (uint32_t)(k >> g.t) & ((1u << g.L) - 1u)
+                                                   : (uint32_t)k & ((1u << g.L) - 1u);
+            id = i * (uint32_t)g.I + sl;
+        }
+        add_degree_runs(deg, id, valid);
     }
 }
 
@@ -527,15 +551,22 @@ int64_t dedup(DevBuf* kb, DevBuf* vb, int cur, int64_t m, hipStream_t s) {
 __global__ void k_input_degree(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                                int64_t m, int32_t n, int both, uint32_t* __restrict__ deg,
                                int32_t* __restrict__ err) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t s = src[e], d = dst[e];
-        if (s < 0 || s >= n || d < 0 || d >= n) {
-            atomicOr(err, 1);
-            continue;
+    // wave-uniform loop: every lane reaches the wave operations of add_degree_runs
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); e0 < m;
+         e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + lane_id();
+        bool valid = e < m;
+        int32_t sv = 0, dv = 0;
+        if (valid) {
+            sv = src[e];
+            dv = dst[e];
+            if (sv < 0 || sv >= n || dv < 0 || dv >= n) {
+                atomicOr(err, 1);
+                valid = false;
+            }
         }
-        atomicAdd(&deg[s], 1u);
-        if (both) atomicAdd(&deg[d], 1u);
+        add_degree_runs(reinterpret_cast<int32_t*>(deg), (uint32_t)sv, valid);
+        if (both) add_degree_runs(reinterpret_cast<int32_t*>(deg), (uint32_t)dv, valid);
     }
 }
 
