@@ -216,7 +216,8 @@ typedef struct nxg_run_desc {
     const int32_t* d_seeds; /* batched personalised PageRank: device [B] seed vertices;
                                column b teleports to seeds[b] (one-hot t). NULL = uniform */
     int32_t piece_chunks;   /* chunks per workgroup piece of a destination tile (0 = planner);
-                               larger tiles are split and combined in two phases */
+                               larger tiles are split, and a second launch sums the
+                               pieces' partials in piece order (two phases) */
 } nxg_run_desc;
 
 typedef struct nxg_run_stats {
@@ -274,10 +275,13 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
                            nxg_multi** out);
 
 /* Runs desc->max_iters synchronous PageRank iterations (FP32 values, uniform
- * teleport, x^0 = 1/n, no tolerance stop) on every graph together: each
- * iteration is ONE launch whose workgroups are the tile pieces of all graphs,
- * so small graphs fill the GPU together instead of one after another. d_values
- * is a host array of count device pointers, graph i's result [n_i] FP32.
+ * teleport, x^0 = 1/n, no tolerance stop) on every graph together: the edge
+ * work of an iteration is ONE launch whose workgroups are the tile pieces of all
+ * graphs, so small graphs fill the GPU together instead of one after another
+ * (then one launch finishes the split tiles of all graphs and one reduces every
+ * graph's scalars). d_values is a host array of count device pointers, graph
+ * i's result [n_i] FP32. The handle keeps the run's workspaces for the next run
+ * with the same iteration count; calls on one handle must not overlap.
  * NXG_RUN_PERSISTENT (one launch for all iterations, workgroups waiting on
  * per-graph iteration counters) returns NXG_EUNSUPPORTED: that variant did not
  * complete on MI355X and is switched off. Synchronises the stream. */

@@ -3,16 +3,17 @@
 // update of Alg. 6).
 //
 // A workgroup owns one piece of one destination tile: its accumulators live in
-// LDS, and its wavefronts stream the tile's edge words chunk by chunk. Inside a
-// chunk every lane loads four consecutive words (one 16-byte load), follows the
-// source-interval markers, gathers the source values, merges runs of equal
-// destination and adds (PageRank) or min-reduces (BFS, WCC) into LDS -- the
-// write-conflict-free destination ownership of Sec. III-D. A tile handled by one
+// LDS, and its wavefronts stream the tile's edge words chunk by chunk. They
+// follow the source-interval markers, gather the source values and add
+// (PageRank) or min-reduce (BFS, WCC) into LDS -- the write-conflict-free
+// destination ownership of Sec. III-D. In destination order a lane loads four
+// consecutive words and merges runs of equal destination first; in source order
+// the 64 lanes of a gather take 64 consecutive edges. A tile handled by one
 // workgroup applies the vertex update straight from LDS (single phase). A tile
-// split into k pieces writes k partial arrays (the hub of Sec. III-B2); the last
-// piece to finish sums them in piece order and applies the update (two phase).
-// The last tile to finish reduces the per-iteration scalars (dangling mass,
-// residual, activity) in tile order, so they are independent of scheduling.
+// split into k pieces writes k partial arrays (the hub of Sec. III-B2), which a
+// second launch sums in piece order and applies (two phase); a third launch
+// reduces the per-iteration scalars (dangling mass, residual, activity) in a
+// fixed order, so they are independent of scheduling.
 #include <algorithm>
 #include <memory>
 #include <cmath>
