@@ -333,7 +333,8 @@ class WeightedPageRank(torch.autograd.Function):
 
 
 class MultiDSSS:
-    """Many independent graphs iterated together in one persistent launch."""
+    """Many independent graphs iterated together: each iteration's edge work of all
+    graphs is one launch."""
 
     def __init__(self, handle, device, sizes):
         self._h = handle
@@ -375,8 +376,18 @@ class MultiDSSS:
         except Exception:
             pass
 
-    def pagerank(self, iters, damping=0.85, persistent=False):
-        outs = [torch.empty(n, dtype=torch.float32, device=self.device) for n in self.sizes]
+    def pagerank(self, iters, damping=0.85, persistent=False, out=None):
+        """x of every graph after iters iterations; out: optional list of FP32
+        tensors [n_i] to write into (else views of one new buffer)."""
+        if out is None:
+            flat = torch.empty(sum(self.sizes), dtype=torch.float32, device=self.device)
+            outs = list(flat.split(self.sizes))
+        else:
+            outs = list(out)
+            if len(outs) != len(self.sizes) or any(
+                    o.numel() != n or o.dtype != torch.float32 or not o.is_contiguous()
+                    for o, n in zip(outs, self.sizes)):
+                raise ValueError("out must hold one contiguous FP32 tensor [n_i] per graph")
         ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=1,
                          damping=float(damping), max_iters=int(iters), tol=0.0, d_teleport=None,

@@ -754,8 +754,8 @@ __global__ __launch_bounds__(WG) void k_reduce(Geo g, Ctl ctl) {
 
 // ---------------------------------------------------------------------------
 // Many graphs per launch: one launch per iteration covers the work items (tile
-// pieces) of every graph; workgroup w finds its graph by a search over the
-// per-graph item prefix. As for one graph, the split tiles of all graphs are
+// pieces) of every graph, heaviest first across all graphs; workgroup w reads
+// its item and the item's graph. As for one graph, the split tiles of all graphs are
 // finished by a second launch and each graph's scalars are reduced by a third
 // (one workgroup per graph), so no workgroup ever waits for another.
 // ---------------------------------------------------------------------------
@@ -766,33 +766,23 @@ struct MultiGraph {
     float* buf1;
     float* xout;       // [n] result (in internal ids for a relabeled graph)
     int32_t* done0;    // a zero word (no tolerance stop in this mode)
-    int32_t item_base; // first item of this graph in the global item array
-    int32_t n_items;
+    int32_t n_items;   // work items of this graph
     const int32_t* o2n;  // relabeled graph: caller id -> internal id, else NULL
     float* user;         // the caller's result buffer (written from xout when o2n is set)
 };
 
 template <int WG>
-__global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict__ graphs, int G,
-                                                   const int32_t* __restrict__ item_prefix,
+__global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict__ graphs,
+                                                   const int32_t* __restrict__ item_graph,
                                                    const Item* __restrict__ items, int k, int iters,
                                                    double damping) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int r = blockIdx.x;
-    int lo = 0, hi = G;  // graph: last index with item_prefix[gi] <= r
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (item_prefix[mid] <= r)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const MultiGraph& mg = graphs[lo];
+    const MultiGraph& mg = graphs[item_graph[r]];
     Ctl ctl{mg.stats, mg.done0, k, 0.0};
     ProgPR<float> prog{(k & 1) ? mg.buf1 : mg.buf0, (k & 1) ? mg.buf0 : mg.buf1, nullptr,
                        k == iters - 1 ? mg.xout : nullptr, damping};
-    iterate_item<ProgPR<float>, WG>(mg.geo, ctl, prog, items[mg.item_base + (r - item_prefix[lo])],
-                                    smem);
+    iterate_item<ProgPR<float>, WG>(mg.geo, ctl, prog, items[r], smem);
 }
 
 // A finishing segment of graph `graph`.
@@ -1645,7 +1635,7 @@ struct MultiCache : Cached {
     size_t lds = 0;
     std::vector<Workspace> ws;
     std::vector<MultiGraph> hdesc;
-    DevBuf ditems, dprefix, ddesc, dfin, dres;
+    DevBuf ditems, dgraph, ddesc, dfin, dres;
 };
 
 // Index arrays of a relabeled build (both NULL otherwise).
@@ -2422,9 +2412,12 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     if (lds > (size_t)lds_budget_bytes(device)) fail(NXG_EINVAL, "a tile does not fit in LDS");
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) {
-        int minC = 65536;
-        for (nxg_dsss* g : mg->graphs) minC = std::min(minC, g->fwd.C);
-        piece = default_piece(chunks, minC, (size_t)maxT * 8, cus);
+        // half a CU's share: the items of many graphs vary more in size, and
+        // smaller ones balance the end of each launch. The partial-size floor
+        // is taken at the largest chunk (the graphs whose tiles are split)
+        int maxC = 256;
+        for (nxg_dsss* g : mg->graphs) maxC = std::max(maxC, g->fwd.C);
+        piece = default_piece(chunks / 2, maxC, (size_t)maxT * 8, cus);
     }
     // per-graph plans, workspaces and descriptors, kept by the handle for the
     // next run with the same iteration count and piece size
@@ -2438,8 +2431,9 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         nc->ws.resize(G);
         nc->hdesc.resize(G);
         std::vector<Item> all_items;
+        std::vector<int32_t> item_graph;
+        std::vector<int64_t> item_words;
         std::vector<MultiFin> all_fin;
-        std::vector<int32_t> prefix(1, 0);
         for (int i = 0; i < G; ++i) {
             nxg_dsss* g = mg->graphs[i];
             const Layout& L = g->fwd;
@@ -2461,26 +2455,40 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
                 m.o2n = g->old2new.as<int32_t>();
             }
             m.done0 = w.done.as<int32_t>();
-            m.item_base = (int32_t)all_items.size();
             m.n_items = (int32_t)p->h_items.size();
-            all_items.insert(all_items.end(), p->h_items.begin(), p->h_items.end());
+            for (const Item& it : p->h_items) {
+                all_items.push_back(it);
+                item_graph.push_back(i);
+                item_words.push_back((it.c1 - it.c0) * (int64_t)L.C);
+            }
             for (const FinSeg& f : p->h_fseg) all_fin.push_back(MultiFin{i, f});
-            prefix.push_back((int32_t)all_items.size());
+        }
+        // heaviest items (in stream words) first over all graphs, so no heavy
+        // item of a late graph starts when the GPU is draining
+        std::vector<int32_t> ord(all_items.size());
+        for (size_t x = 0; x < ord.size(); ++x) ord[x] = (int32_t)x;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int32_t a, int32_t b) { return item_words[a] > item_words[b]; });
+        std::vector<Item> sorted_items(ord.size());
+        std::vector<int32_t> sorted_graph(ord.size());
+        for (size_t x = 0; x < ord.size(); ++x) {
+            sorted_items[x] = all_items[ord[x]];
+            sorted_graph[x] = item_graph[ord[x]];
         }
         nc->lds = lds;
-        nc->per_iter = prefix.back();
+        nc->per_iter = (int)sorted_items.size();
         nc->n_fin = (int)all_fin.size();
         nc->dfin.alloc(sizeof(MultiFin) * std::max<size_t>(all_fin.size(), 1), s);
         if (!all_fin.empty())
             NXG_HIP(hipMemcpyAsync(nc->dfin.p, all_fin.data(), sizeof(MultiFin) * all_fin.size(),
                                    hipMemcpyHostToDevice, s));
-        nc->ditems.alloc(sizeof(Item) * all_items.size(), s);
-        nc->dprefix.alloc(sizeof(int32_t) * prefix.size(), s);
+        nc->ditems.alloc(sizeof(Item) * std::max<size_t>(sorted_items.size(), 1), s);
+        nc->dgraph.alloc(sizeof(int32_t) * std::max<size_t>(sorted_graph.size(), 1), s);
         nc->ddesc.alloc(sizeof(MultiGraph) * G, s);
         nc->dres.alloc(sizeof(double) * G, s);
-        NXG_HIP(hipMemcpyAsync(nc->ditems.p, all_items.data(), sizeof(Item) * all_items.size(),
+        NXG_HIP(hipMemcpyAsync(nc->ditems.p, sorted_items.data(), sizeof(Item) * sorted_items.size(),
                                hipMemcpyHostToDevice, s));
-        NXG_HIP(hipMemcpyAsync(nc->dprefix.p, prefix.data(), sizeof(int32_t) * prefix.size(),
+        NXG_HIP(hipMemcpyAsync(nc->dgraph.p, sorted_graph.data(), sizeof(int32_t) * sorted_graph.size(),
                                hipMemcpyHostToDevice, s));
         NXG_HIP(hipStreamSynchronize(s));  // the host vectors above go out of scope
         c = nc.release();
@@ -2508,8 +2516,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     hipLaunchKernelGGL(k_multi_init, dim3(G), dim3(256), 0, s, ddesc);
     NXG_CHECK_LAUNCH();
     for (int k = 0; k < iters; ++k) {
-        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, s, ddesc, G,
-                           c->dprefix.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
+        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, s, ddesc,
+                           c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
         NXG_CHECK_LAUNCH();
         if (c->n_fin > 0) {
             hipLaunchKernelGGL(k_multi_finish<kFinWG>, dim3(c->n_fin), dim3(kFinWG), kFinSeg * sizeof(double),

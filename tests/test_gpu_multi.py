@@ -53,6 +53,14 @@ def test_multi_source_order_and_relabel(gpu_device, order, relabel):
     for i, (s, d, n) in enumerate(gs):
         ref, _ = oracle.pagerank(n, s, d, iters=25)
         assert rel_l1(xs[i].cpu().numpy(), ref) <= 1e-5, i
+    # caller-owned outputs, and the handle's workspaces reused by a second run
+    outs = [torch.full((n,), -1.0, dtype=torch.float32, device=gpu_device) for _, _, n in gs]
+    xo, _ = mg.pagerank(25, out=outs)
+    for i in range(len(gs)):
+        assert xo[i].data_ptr() == outs[i].data_ptr()
+        assert rel_l1(outs[i].cpu().numpy(), xs[i].cpu().numpy()) <= 1e-7, i
+    with pytest.raises(ValueError):
+        mg.pagerank(3, out=outs[:-1])
 
 
 def test_multi_persistent_flag_is_refused(gpu_device):
