@@ -9,9 +9,10 @@ K timed iterations are one replay of a captured hipGraph. Prints one JSON line.
 
 Other workloads (--mode): bfs, wcc (scale 22, ef 16, 32 intervals), ppr (64
 seeds, scale 22), multi (256 graphs, scales 10..18), adjoint (scale 20, fwd to
-1e-8 residual + backward); --mode all runs every one (one JSON line each).
+1e-8 residual + backward), degree (scale 22 over 2^23 sparse ids, with and
+without degreeing); --mode all runs every one (one JSON line each).
 
-  python bench.py [--steps K] [--warmup W] [--mode pagerank|bfs|wcc|ppr|multi|adjoint|all]
+  python bench.py [--steps K] [--warmup W] [--mode pagerank|bfs|wcc|ppr|multi|adjoint|degree|all]
 """
 import argparse
 import hashlib
@@ -314,6 +315,44 @@ def bench_multi(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_degree(args, dev):
+    """Degreeing: the scale-22 ef16 R-MAT graph scattered over 2^23 ids (half of
+    them in no edge), built and iterated with and without NXG_BUILD_DEGREE."""
+    import numpy as np
+    import torch
+    from paper_1510_06916_amd import DSSS
+    scale, ef, seed = 22, 16, 6
+    n = 1 << (scale + 1)
+    src, dst = rmat(scale, ef, seed, dev)
+    spread = torch.from_numpy(np.random.default_rng(seed + 100).permutation(n)[: 1 << scale]
+                              .astype(np.int32)).to(dev)
+    src, dst = spread[src.long()], spread[dst.long()]
+    res = {"metric": "PageRank FP32 ms per iteration, sparse ids, with and without degreeing",
+           "unit": "ms", "n_gpus": 1, "dtype": "f32", "higher_is_better": False,
+           "config": {"workload": "degree rmat-s22-ef16 over 2^23 ids", "n_ids": n, "m": int(src.numel()),
+                      "order": args.order, "relabel": int(args.relabel)}}
+    for deg in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = DSSS.build(src, dst, n, order=args.order, relabel=bool(args.relabel), degree=deg)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+        g.pagerank(20, capture=True, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.pagerank(20, capture=True, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 20
+        key = "degreed" if deg else "plain"
+        res["config"][key + "_build_s"] = tb
+        res["config"][key + "_ms_per_iter"] = ms
+        res["config"][key + "_vertices"] = g.info()["n_kept"]
+        del g
+    res["value"] = res["config"]["degreed_ms_per_iter"]
+    print(json.dumps(res), flush=True)
+
+
 def bench_adjoint(args, dev):
     import numpy as np
     import torch
@@ -366,7 +405,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="pagerank",
-                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "all"])
+                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "all"])
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--ef", type=int, default=48)
     ap.add_argument("--seed", type=int, default=3)
@@ -388,7 +427,8 @@ def main():
         sys.exit(2)
     import torch
     dev = torch.device("cuda:0")
-    modes = ["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint"] if args.mode == "all" else [args.mode]
+    modes = (["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree"] if args.mode == "all"
+             else [args.mode])
     for mode in modes:
         log("== mode %s" % mode)
         if mode == "pagerank":
@@ -399,6 +439,8 @@ def main():
             bench_ppr(args, dev)
         elif mode == "multi":
             bench_multi(args, dev)
+        elif mode == "degree":
+            bench_degree(args, dev)
         else:
             bench_adjoint(args, dev)
         torch.cuda.empty_cache()

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 3
+#define NXG_ABI_VERSION 4
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -93,7 +93,21 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                                      so both fields fit one word. Only
                                      NXG_RUN_SCATTER PageRank runs use it (the
                                      tile has no LDS bound); not combinable with
-                                     NXG_BUILD_RELABEL or NXG_BUILD_TRANSPOSE */
+                                     NXG_BUILD_RELABEL, NXG_BUILD_TRANSPOSE or
+                                     NXG_BUILD_DEGREE */
+#define NXG_BUILD_DEGREE 0x40u    /* degreeing (Sec. III-A preprocessing): ids that
+                                     appear in no edge are dropped and the others
+                                     numbered densely in increasing id order (by
+                                     decreasing out-degree with NXG_BUILD_RELABEL).
+                                     The graph then has n_kept vertices: PageRank's
+                                     uniform teleport and dangling share are
+                                     1/n_kept, and a teleport vector counts only on
+                                     kept ids. Runs still take and return vectors
+                                     over the caller's n ids; dropped ids read as 0
+                                     (PageRank, adjoint), INT32_MAX (BFS; a dropped
+                                     root reaches only itself) and their own id
+                                     (WCC). Batched seeds must be kept ids. Not for
+                                     nxg_multi_build. */
 
 /* Order of the edges inside one sub-shard. */
 #define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */
@@ -145,6 +159,7 @@ typedef struct nxg_dsss_info {
     int32_t has_perm, has_weights, has_transpose;
     int32_t order;       /* NXG_ORDER_* */
     int32_t relabeled;   /* built with NXG_BUILD_RELABEL */
+    int32_t n_kept;      /* vertices of the stored graph: n, or fewer with NXG_BUILD_DEGREE */
 } nxg_dsss_info;
 
 nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
@@ -165,10 +180,10 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
 nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets,
                            int32_t* d_src, int32_t* d_dst, int32_t* d_perm, void* stream);
 
-/* Internal vertex numbering of a NXG_BUILD_RELABEL build: d_new2old[k] (device,
- * [n], caller-owned) receives the caller id of internal vertex k. The ids that
- * nxg_dsss_export returns are internal ids. NXG_EINVAL if the handle was not
- * relabeled. Synchronises the stream. */
+/* Internal vertex numbering of a NXG_BUILD_RELABEL or NXG_BUILD_DEGREE build:
+ * d_new2old[k] (device, [n_kept], caller-owned) receives the caller id of
+ * internal vertex k. The ids that nxg_dsss_export returns are internal ids.
+ * NXG_EINVAL if the handle was built with neither flag. Synchronises the stream. */
 nxg_status nxg_dsss_vertex_map(const nxg_dsss* g, int32_t* d_new2old, void* stream);
 
 /* ------------------------------------------------------------------------- */

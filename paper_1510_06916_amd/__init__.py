@@ -105,9 +105,11 @@ class DSSS:
     @classmethod
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
               value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
-              order="dst", relabel=False, scatter=False, stream=None):
+              order="dst", relabel=False, scatter=False, degree=False, stream=None):
         """scatter=True builds the coarse-grained source-sorted layout
-        (NXG_BUILD_SCATTER) that only pagerank(..., scatter=True) runs."""
+        (NXG_BUILD_SCATTER) that only pagerank(..., scatter=True) runs.
+        degree=True drops the ids that appear in no edge (NXG_BUILD_DEGREE);
+        vectors stay indexed by the caller's n ids."""
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -126,7 +128,8 @@ class DSSS:
                  (_lib.NXG_BUILD_SYMMETRIZE if symmetrize else 0) |
                  (_lib.NXG_BUILD_DEDUP if dedup else 0) |
                  (_lib.NXG_BUILD_RELABEL if relabel else 0) |
-                 (_lib.NXG_BUILD_SCATTER if scatter else 0))
+                 (_lib.NXG_BUILD_SCATTER if scatter else 0) |
+                 (_lib.NXG_BUILD_DEGREE if degree else 0))
         d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,
@@ -166,8 +169,9 @@ class DSSS:
         return self.info()["m"]
 
     def vertex_map(self):
-        """Caller id of every internal vertex (relabeled builds): int32 [n]."""
-        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        """Caller id of every internal vertex (relabeled or degreed builds):
+        int32 [n_kept]."""
+        out = torch.empty(self.info()["n_kept"], dtype=torch.int32, device=self.device)
         _lib.check(_lib.lib().nxg_dsss_vertex_map(self._h, out.data_ptr(), _stream_handle()),
                    "nxg_dsss_vertex_map")
         return out

@@ -15,6 +15,7 @@ NXG_BUILD_SYMMETRIZE = 0x4
 NXG_BUILD_DEDUP = 0x8
 NXG_BUILD_RELABEL = 0x10
 NXG_BUILD_SCATTER = 0x20
+NXG_BUILD_DEGREE = 0x40
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
@@ -40,7 +41,8 @@ class DsssInfo(ctypes.Structure):
                 ("n_words", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("max_tile_edges", ctypes.c_int64), ("has_perm", ctypes.c_int32),
                 ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("relabeled", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("relabeled", ctypes.c_int32),
+                ("n_kept", ctypes.c_int32)]
 
 
 class RunDesc(ctypes.Structure):

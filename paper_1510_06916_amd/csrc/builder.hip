@@ -570,21 +570,39 @@ __global__ void k_input_degree(const int32_t* __restrict__ src, const int32_t* _
     }
 }
 
-// Sort keys of the new order: degree descending, then id ascending.
-__global__ void k_vertex_keys(const uint32_t* __restrict__ deg, int32_t n,
-                              uint64_t* __restrict__ keys) {
+// Sort keys of the new order: dropped ids last (bit 63), then degree descending
+// (when deg is given), then id ascending (bits 0..30).
+__global__ void k_vertex_keys(const uint32_t* __restrict__ deg, const uint32_t* __restrict__ any,
+                              int32_t n, uint64_t* __restrict__ keys) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        keys[v] = ((uint64_t)(0xFFFFFFFFu - deg[v]) << 32) | (uint64_t)v;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t dropped = (any && any[v] == 0) ? 1ull : 0ull;
+        const uint64_t high = deg ? (uint64_t)(0xFFFFFFFFu - deg[v]) : 0ull;
+        keys[v] = (dropped << 63) | (high << 31) | (uint64_t)v;
+    }
 }
 
-__global__ void k_vertex_maps(const uint64_t* __restrict__ sorted, int32_t n,
+// Vertices with at least one edge (block partial counts).
+__global__ __launch_bounds__(256) void k_count_kept(const uint32_t* __restrict__ any, int32_t n,
+                                                    unsigned long long* __restrict__ count) {
+    int c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        c += any[v] != 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane_id() == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+// new2old[k] = id at sorted position k (k < kept); old2new[id] = its position,
+// or -1 for the ids sorted past the kept ones.
+__global__ void k_vertex_maps(const uint64_t* __restrict__ sorted, int32_t n, int32_t kept,
                               int32_t* __restrict__ new2old, int32_t* __restrict__ old2new) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = (int32_t)(sorted[k] & 0xFFFFFFFFu);
-        new2old[k] = v;
-        old2new[v] = (int32_t)k;
+        const int32_t v = (int32_t)(sorted[k] & 0x7FFFFFFFu);
+        if (k < kept) new2old[k] = v;
+        old2new[v] = k < kept ? (int32_t)k : -1;
     }
 }
 
@@ -806,34 +824,65 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
     NXG_HIP(hipStreamSynchronize(s));
 }
 
-void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevBuf& old2new,
-                   DevBuf& src2, DevBuf& dst2) {
+int32_t relabel_input(const nxg_build_desc& d, hipStream_t s, bool by_degree, bool drop,
+                      DevBuf& new2old, DevBuf& old2new, DevBuf& src2, DevBuf& dst2) {
     const int32_t n = d.n;
     const int64_t m = d.m;
-    DevBuf deg, err, kb[2], vb[2];
+    DevBuf deg, any, err, cnt, kb[2], vb[2];
     deg.alloc(sizeof(uint32_t) * n, s);
     err.alloc(sizeof(int32_t), s);
     NXG_HIP(hipMemsetAsync(deg.p, 0, sizeof(uint32_t) * n, s));
     NXG_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    // ordering degree: out-degree (plus in-degree for a symmetrised build)
     if (m > 0) {
         hipLaunchKernelGGL(k_input_degree, dim3(grid_for(m)), dim3(256), 0, s, d.d_src, d.d_dst, m,
                            n, (d.flags & NXG_BUILD_SYMMETRIZE) ? 1 : 0, deg.as<uint32_t>(),
                            err.as<int32_t>());
         NXG_CHECK_LAUNCH();
     }
+    // with drop: any edge at all, in or out
+    const uint32_t* anyp = nullptr;
+    if (drop) {
+        if (d.flags & NXG_BUILD_SYMMETRIZE) {
+            anyp = deg.as<uint32_t>();
+        } else {
+            any.alloc(sizeof(uint32_t) * n, s);
+            NXG_HIP(hipMemsetAsync(any.p, 0, sizeof(uint32_t) * n, s));
+            if (m > 0) {
+                hipLaunchKernelGGL(k_input_degree, dim3(grid_for(m)), dim3(256), 0, s, d.d_src, d.d_dst,
+                                   m, n, 1, any.as<uint32_t>(), err.as<int32_t>());
+                NXG_CHECK_LAUNCH();
+            }
+            anyp = any.as<uint32_t>();
+        }
+    }
     int32_t herr = 0;
     NXG_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     NXG_HIP(hipStreamSynchronize(s));
     if (herr) fail(NXG_EINVAL, "edge id outside [0, n)");
+    int32_t kept = n;
+    if (drop) {
+        cnt.alloc(sizeof(unsigned long long), s);
+        NXG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_count_kept, dim3(grid_for(n)), dim3(256), 0, s, anyp, n,
+                           cnt.as<unsigned long long>());
+        NXG_CHECK_LAUNCH();
+        unsigned long long hk = 0;
+        NXG_HIP(hipMemcpyAsync(&hk, cnt.p, sizeof(hk), hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        kept = (int32_t)hk;
+        if (kept < 1) fail(NXG_EINVAL, "NXG_BUILD_DEGREE needs at least one edge");
+    }
     kb[0].alloc(sizeof(uint64_t) * n, s);
     kb[1].alloc(sizeof(uint64_t) * n, s);
-    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for(n)), dim3(256), 0, s, deg.as<uint32_t>(), n,
+    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for(n)), dim3(256), 0, s,
+                       by_degree ? deg.as<uint32_t>() : (const uint32_t*)nullptr, anyp, n,
                        kb[0].as<uint64_t>());
     NXG_CHECK_LAUNCH();
     const int cur = radix_sort(kb, vb, n, 64, s);
-    new2old.alloc(sizeof(int32_t) * n, s);
+    new2old.alloc(sizeof(int32_t) * kept, s);
     old2new.alloc(sizeof(int32_t) * n, s);
-    hipLaunchKernelGGL(k_vertex_maps, dim3(grid_for(n)), dim3(256), 0, s, kb[cur].as<uint64_t>(), n,
+    hipLaunchKernelGGL(k_vertex_maps, dim3(grid_for(n)), dim3(256), 0, s, kb[cur].as<uint64_t>(), n, kept,
                        new2old.as<int32_t>(), old2new.as<int32_t>());
     NXG_CHECK_LAUNCH();
     src2.alloc(sizeof(int32_t) * std::max<int64_t>(m, 1), s);
@@ -844,6 +893,7 @@ void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevB
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipStreamSynchronize(s));
+    return kept;
 }
 
 void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,

@@ -96,6 +96,9 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
         if (!out) fail(NXG_EINVAL, "out is NULL");
         *out = nullptr;
         if (count < 1 || !descs) fail(NXG_EINVAL, "count must be >= 1 and descs non-NULL");
+        for (int32_t i = 0; i < count; ++i)
+            if (descs[i].flags & (NXG_BUILD_DEGREE | NXG_BUILD_SCATTER))
+                fail(NXG_EUNSUPPORTED, "nxg_multi_build takes neither NXG_BUILD_DEGREE nor NXG_BUILD_SCATTER");
         nxg_multi* mg = new nxg_multi();
         try {
             for (int32_t i = 0; i < count; ++i)
@@ -136,10 +139,12 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
             fail(NXG_EINVAL, "too many edges");
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
-                                  NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER))
+                                  NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER |
+                                  NXG_BUILD_DEGREE))
             fail(NXG_EINVAL, "unknown build flag");
-        if ((d.flags & NXG_BUILD_SCATTER) && (d.flags & (NXG_BUILD_RELABEL | NXG_BUILD_TRANSPOSE)))
-            fail(NXG_EINVAL, "SCATTER cannot be combined with RELABEL or TRANSPOSE");
+        if ((d.flags & NXG_BUILD_SCATTER) &&
+            (d.flags & (NXG_BUILD_RELABEL | NXG_BUILD_TRANSPOSE | NXG_BUILD_DEGREE)))
+            fail(NXG_EINVAL, "SCATTER cannot be combined with RELABEL, TRANSPOSE or DEGREE");
         if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
             fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
         if (d.interval < 0 || d.interval > d.n) fail(NXG_EINVAL, "interval outside [0, n]");
@@ -150,11 +155,14 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
             g->flags = d.flags;
             nxg_build_desc dd = d;
             DevBuf src2, dst2;
-            if (d.flags & NXG_BUILD_RELABEL) {
-                relabel_input(d, s, g->new2old, g->old2new, src2, dst2);
+            g->n_caller = d.n;
+            if (d.flags & (NXG_BUILD_RELABEL | NXG_BUILD_DEGREE)) {
+                dd.n = relabel_input(d, s, (d.flags & NXG_BUILD_RELABEL) != 0,
+                                     (d.flags & NXG_BUILD_DEGREE) != 0, g->new2old, g->old2new, src2, dst2);
                 g->relabeled = true;
                 dd.d_src = src2.as<int32_t>();
                 dd.d_dst = dst2.as<int32_t>();
+                if (dd.interval > dd.n) dd.interval = dd.n;
             }
             build_layout(dd, false, s, g->fwd);
             if (d.flags & NXG_BUILD_TRANSPOSE) {
@@ -184,7 +192,8 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
         if (!g || !info) fail(NXG_EINVAL, "NULL argument");
         const Layout& L = g->fwd;
         memset(info, 0, sizeof(*info));
-        info->n = L.n;
+        info->n = g->n_caller;
+        info->n_kept = L.n;
         info->m = L.m;
         info->interval = L.I;
         info->P = L.P;
@@ -214,7 +223,7 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
 nxg_status nxg_dsss_vertex_map(const nxg_dsss* g, int32_t* d_new2old, void* stream) {
     return guarded([&]() {
         if (!g || !d_new2old) fail(NXG_EINVAL, "NULL argument");
-        if (!g->relabeled) fail(NXG_EINVAL, "the handle was built without NXG_BUILD_RELABEL");
+        if (!g->relabeled) fail(NXG_EINVAL, "the handle was built without NXG_BUILD_RELABEL or NXG_BUILD_DEGREE");
         hipStream_t s = (hipStream_t)stream;
         NXG_HIP(hipMemcpyAsync(d_new2old, g->new2old.p, sizeof(int32_t) * g->fwd.n,
                                hipMemcpyDeviceToDevice, s));

@@ -1184,16 +1184,19 @@ __global__ __launch_bounds__(256) void k_edge_grad(
 
 // Vertex data between caller ids and the internal ids of a relabeled build:
 // out[k*w + c] = f * in[idx[k]*w + c]. idx = new2old brings caller data in,
-// idx = old2new hands results back.
+// idx = old2new hands results back; an id dropped by degreeing (idx[k] < 0)
+// gets `fill`, or its own id k when own_id is set.
 template <typename T>
 __global__ __launch_bounds__(256) void k_permute_rows(const T* __restrict__ in,
                                                       const int32_t* __restrict__ idx, int64_t n,
-                                                      int w, T f, T* __restrict__ out) {
+                                                      int w, T f, T fill, int own_id,
+                                                      T* __restrict__ out) {
     for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n * w;
          x += (int64_t)gridDim.x * 256) {
         const int64_t k = x / w;
         const int64_t c = x - k * w;
-        out[x] = f * in[(int64_t)idx[k] * w + c];
+        const int32_t j = idx[k];
+        out[x] = j >= 0 ? f * in[(int64_t)j * w + c] : (own_id ? (T)k : fill);
     }
 }
 
@@ -1638,10 +1641,12 @@ struct MultiCache : Cached {
     DevBuf ditems, dgraph, ddesc, dfin, dres;
 };
 
-// Index arrays of a relabeled build (both NULL otherwise).
+// Index arrays of a relabeled or degreed build (both NULL otherwise); n is the
+// caller's id range (results are handed back over all of it).
 struct VMap {
     const int32_t* n2o = nullptr;
     const int32_t* o2n = nullptr;
+    int64_t n = 0;
     explicit operator bool() const { return n2o != nullptr; }
 };
 
@@ -1650,16 +1655,17 @@ VMap vmap_of(const nxg_dsss* g) {
     if (g->relabeled) {
         m.n2o = g->new2old.as<int32_t>();
         m.o2n = g->old2new.as<int32_t>();
+        m.n = g->n_caller;
     }
     return m;
 }
 
 template <typename T>
 void permute_rows(const T* in, const int32_t* idx, int64_t n, int w, T* out, hipStream_t s,
-                  T f = (T)1) {
+                  T f = (T)1, T fill = (T)0, int own_id = 0) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_permute_rows<T>, dim3(grid_for(n * w, 256, 8192)), dim3(256), 0, s, in, idx,
-                       n, w, f, out);
+                       n, w, f, fill, own_id, out);
     NXG_CHECK_LAUNCH();
 }
 
@@ -1794,7 +1800,7 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
             launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, p, lds, s);
         }
     }
-    if (vm) permute_rows<V>(vals, vm.o2n, L.n, 1, (V*)d.d_values, s);
+    if (vm) permute_rows<V>(vals, vm.o2n, vm.n, 1, (V*)d.d_values, s);
 }
 
 template <typename V>
@@ -2064,7 +2070,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         }
         NXG_CHECK_LAUNCH();
     }
-    if (vm) permute_rows<V>(vals, vm.o2n, L.n, 1, (V*)d.d_values, s);
+    if (vm) permute_rows<V>(vals, vm.o2n, vm.n, 1, (V*)d.d_values, s);
     NXG_HIP(hipEventRecord(e1, s));
     nxg_status rc = NXG_OK;
     if (st || d.tol > 0) {
@@ -2107,16 +2113,32 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     const bool bfs = d.program == NXG_BFS;
     if (!bfs && !(g->flags & NXG_BUILD_SYMMETRIZE))
         fail(NXG_EINVAL, "WCC needs a build with NXG_BUILD_SYMMETRIZE");
+    const VMap vm = vmap_of(g);
+    const int64_t n_out = vm ? vm.n : L.n;
     if (bfs) {
         if (!d.roots) fail(NXG_EINVAL, "BFS needs roots");
         if (d.batch != 1) fail(NXG_EUNSUPPORTED, "BFS runs one root per call");
-        if (d.roots[0] < 0 || d.roots[0] >= L.n) fail(NXG_EINVAL, "BFS root outside [0, n)");
+        if (d.roots[0] < 0 || d.roots[0] >= n_out) fail(NXG_EINVAL, "BFS root outside [0, n)");
     }
-    const VMap vm = vmap_of(g);
     int32_t root = bfs ? d.roots[0] : 0;
     if (bfs && vm) {
         NXG_HIP(hipMemcpyAsync(&root, vm.o2n + root, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
+        if (root < 0) {
+            // a root dropped by degreeing has no edges: it reaches only itself
+            int32_t* lev = (int32_t*)d.d_values;
+            hipLaunchKernelGGL(k_fill_val<int32_t>, dim3(grid_for(n_out)), dim3(256), 0, s, lev, n_out, kInf);
+            NXG_CHECK_LAUNCH();
+            const int32_t zero = 0;
+            NXG_HIP(hipMemcpyAsync(lev + d.roots[0], &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (st) {
+                memset(st, 0, sizeof(*st));
+                st->iterations = 1;
+                st->converged = 1;
+            }
+            return NXG_OK;
+        }
     }
     if (((size_t)L.T + kSpill) * 4 > (size_t)lds_budget_bytes(g->device))
         fail(NXG_EINVAL, "tile does not fit in LDS");
@@ -2198,7 +2220,8 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     // the values after round k live in buf[k & 1]; rounds past the fixed point copy
     NXG_HIP(hipEventRecord(e1, s));
     if (vm)
-        permute_rows<int32_t>(w.buf[k & 1].as<int32_t>(), vm.o2n, L.n, 1, (int32_t*)d.d_values, s);
+        permute_rows<int32_t>(w.buf[k & 1].as<int32_t>(), vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1,
+                              bfs ? kInf : 0, bfs ? 0 : 1);
     else
         hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s,
                            w.buf[k & 1].as<int32_t>(), (int32_t*)d.d_values, (int64_t)L.n);
@@ -2269,8 +2292,9 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         int32_t hseed[64];
         NXG_HIP(hipMemcpyAsync(hseed, seeds, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
+        const int64_t n_out = g->relabeled ? (int64_t)g->n_caller : (int64_t)L.n;
         for (int b = 0; b < B; ++b)
-            if (hseed[b] < 0 || hseed[b] >= L.n) fail(NXG_EINVAL, "seed vertex outside [0, n)");
+            if (hseed[b] < 0 || hseed[b] >= n_out) fail(NXG_EINVAL, "seed vertex outside [0, n)");
     }
     const VMap vm = vmap_of(g);
     float* vals = (float*)d.d_values;
@@ -2280,6 +2304,11 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             w.mseeds.alloc(sizeof(int32_t) * B, s);
             permute_rows<int32_t>(vm.o2n, seeds, B, 1, w.mseeds.as<int32_t>(), s);
             seeds = w.mseeds.as<int32_t>();
+            int32_t hs2[64];
+            NXG_HIP(hipMemcpyAsync(hs2, seeds, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            for (int b = 0; b < B; ++b)
+                if (hs2[b] < 0) fail(NXG_EINVAL, "seed vertex dropped by NXG_BUILD_DEGREE (it has no edges)");
         }
         w.mvals.alloc(sizeof(float) * (size_t)L.n * B, s);
         vals = w.mvals.as<float>();
@@ -2351,7 +2380,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                            d.damping, w.tile_s.as<double>());
         NXG_CHECK_LAUNCH();
     }
-    if (vm) permute_rows<float>(vals, vm.o2n, L.n, B, (float*)d.d_values, s);
+    if (vm) permute_rows<float>(vals, vm.o2n, vm.n, B, (float*)d.d_values, s);
     NXG_HIP(hipEventRecord(e1, s));
     std::vector<double> hs(nstat);
     NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
@@ -2646,8 +2675,8 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     }
     const double* lam = w.buf[k & 1].as<double>();
     if (vm) {
-        if (d.d_lambda) permute_rows<double>(lam, vm.o2n, R.n, 1, d.d_lambda, s);
-        if (d.d_gt) permute_rows<double>(lam, vm.o2n, R.n, 1, d.d_gt, s, 1.0 - d.damping);
+        if (d.d_lambda) permute_rows<double>(lam, vm.o2n, vm.n, 1, d.d_lambda, s);
+        if (d.d_gt) permute_rows<double>(lam, vm.o2n, vm.n, 1, d.d_gt, s, 1.0 - d.damping);
     } else {
         if (d.d_lambda)
             hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(R.n)), dim3(256), 0, s, lam, 1.0,

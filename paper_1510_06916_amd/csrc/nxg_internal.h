@@ -162,7 +162,8 @@ struct nxg_dsss {
     // NXG_BUILD_RELABEL: both layouts use internal ids; new2old[k] is the caller
     // id of internal vertex k, old2new the inverse
     bool relabeled = false;
-    nxg::DevBuf new2old, old2new;
+    nxg::DevBuf new2old, old2new;  // old2new[v] = -1 for a dropped id (NXG_BUILD_DEGREE)
+    int32_t n_caller = 0;          // the caller's id range; fwd.n = kept vertices
     // cached iteration plans, keyed by piece size
     std::vector<nxg::Plan*> plans;
     // captured runs (hipGraph + workspace), see NXG_RUN_CAPTURE, recorded on a
@@ -187,8 +188,11 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
 void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
                    int32_t* d_perm, hipStream_t s);
 // validates the ids, orders the vertices by decreasing degree and renames the edges
-void relabel_input(const nxg_build_desc& d, hipStream_t s, DevBuf& new2old, DevBuf& old2new,
-                   DevBuf& src2, DevBuf& dst2);
+// numbers the vertices internally (by decreasing out-degree when by_degree;
+// without the ids that appear in no edge when drop) and renames the edges;
+// returns the number of internal vertices
+int32_t relabel_input(const nxg_build_desc& d, hipStream_t s, bool by_degree, bool drop,
+                      DevBuf& new2old, DevBuf& old2new, DevBuf& src2, DevBuf& dst2);
 // validated build of a whole handle, with the optional relabeling and transpose
 // (capi.hip)
 nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s);
