@@ -10,9 +10,11 @@ K timed iterations are one replay of a captured hipGraph. Prints one JSON line.
 Other workloads (--mode): bfs, wcc (scale 22, ef 16, 32 intervals), ppr (64
 seeds, scale 22), multi (256 graphs, scales 10..18), adjoint (scale 20, fwd to
 1e-8 residual + backward), degree (scale 22 over 2^23 sparse ids, with and
-without degreeing); --mode all runs every one (one JSON line each).
+without degreeing), hoststream (the headline graph with its edge stream in
+host memory); --mode all runs every one (one JSON line each).
 
-  python bench.py [--steps K] [--warmup W] [--mode pagerank|bfs|wcc|ppr|multi|adjoint|degree|all]
+  python bench.py [--steps K] [--warmup W]
+                  [--mode pagerank|bfs|wcc|ppr|multi|adjoint|degree|hoststream|all]
 """
 import argparse
 import hashlib
@@ -353,6 +355,47 @@ def bench_degree(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_hoststream(args, dev):
+    """The headline graph with its edge stream in pinned host memory
+    (NXG_BUILD_HOST_STREAM): FP32 PageRank iterations streaming 6.3 GB of
+    sub-shards from the host each, against the host-to-device copy rate."""
+    import torch
+    from paper_1510_06916_amd import DSSS
+    n = 1 << args.scale
+    src, dst = rmat(args.scale, args.ef, args.seed, dev)
+    g = DSSS.build(src, dst, n, interval=16384, tile=16384, chunk=1024, order="src", relabel=True,
+                   host_stream=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    inf = g.info()
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    g.pagerank(1, out=out)
+    torch.cuda.synchronize()
+    iters = 3
+    t0 = time.perf_counter()
+    g.pagerank(iters, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / iters
+    stream_bytes = 4.0 * inf["n_words"]
+    # host-to-device rate of one 1 GiB pinned copy (best of 3)
+    a = torch.empty(1 << 28, dtype=torch.float32, pin_memory=True)
+    b = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    best = 1e9
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b.copy_(a, non_blocking=True)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t1)
+    h2d = (1 << 30) / best / 1e9
+    res = {"metric": "PageRank iteration with the edge stream in host memory", "value": ms, "unit": "ms",
+           "n_gpus": 1, "dtype": "f32", "higher_is_better": False,
+           "config": {"workload": "hoststream rmat-s%d-ef%d" % (args.scale, args.ef), "n": n, "m": inf["m"],
+                      "stream_gb": stream_bytes / 1e9, "stream_gbs": stream_bytes / (ms * 1e-3) / 1e9,
+                      "h2d_copy_gbs": h2d, "gteps": inf["m"] / (ms * 1e-3) / 1e9}}
+    print(json.dumps(res), flush=True)
+
+
 def bench_adjoint(args, dev):
     import numpy as np
     import torch
@@ -405,7 +448,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="pagerank",
-                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "all"])
+                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "hoststream",
+                             "all"])
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--ef", type=int, default=48)
     ap.add_argument("--seed", type=int, default=3)
@@ -427,8 +471,8 @@ def main():
         sys.exit(2)
     import torch
     dev = torch.device("cuda:0")
-    modes = (["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree"] if args.mode == "all"
-             else [args.mode])
+    modes = (["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "hoststream"]
+             if args.mode == "all" else [args.mode])
     for mode in modes:
         log("== mode %s" % mode)
         if mode == "pagerank":
@@ -441,6 +485,8 @@ def main():
             bench_multi(args, dev)
         elif mode == "degree":
             bench_degree(args, dev)
+        elif mode == "hoststream":
+            bench_hoststream(args, dev)
         else:
             bench_adjoint(args, dev)
         torch.cuda.empty_cache()

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 4
+#define NXG_ABI_VERSION 5
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -108,6 +108,20 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                                      root reaches only itself) and their own id
                                      (WCC). Batched seeds must be kept ids. Not for
                                      nxg_multi_build. */
+#define NXG_BUILD_HOST_STREAM 0x80u /* the SPU schedule with the sub-shards on a
+                                     slower tier (Sec. III-B1, Alg. 5): after the
+                                     build the edge stream (and weights) moves to
+                                     pinned host memory, and every iteration streams
+                                     it through two device staging buffers, copies
+                                     overlapped with the edge work, while the vertex
+                                     data stays in device memory. Such a handle runs
+                                     PageRank only (plain or weighted, F32 or F64,
+                                     batch 1, no capture); the staging size is set by
+                                     the environment variable NXG_STREAM_MB (default
+                                     256 per buffer). Not combinable with
+                                     NXG_BUILD_TRANSPOSE or NXG_BUILD_SCATTER, nor for
+                                     nxg_multi_build; nxg_dsss_export and
+                                     nxg_dsss_set_weights refuse such a handle. */
 
 /* Order of the edges inside one sub-shard. */
 #define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */

@@ -16,6 +16,7 @@ NXG_BUILD_DEDUP = 0x8
 NXG_BUILD_RELABEL = 0x10
 NXG_BUILD_SCATTER = 0x20
 NXG_BUILD_DEGREE = 0x40
+NXG_BUILD_HOST_STREAM = 0x80
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)

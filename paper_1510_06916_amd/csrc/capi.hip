@@ -97,8 +97,9 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
         *out = nullptr;
         if (count < 1 || !descs) fail(NXG_EINVAL, "count must be >= 1 and descs non-NULL");
         for (int32_t i = 0; i < count; ++i)
-            if (descs[i].flags & (NXG_BUILD_DEGREE | NXG_BUILD_SCATTER))
-                fail(NXG_EUNSUPPORTED, "nxg_multi_build takes neither NXG_BUILD_DEGREE nor NXG_BUILD_SCATTER");
+            if (descs[i].flags & (NXG_BUILD_DEGREE | NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM))
+                fail(NXG_EUNSUPPORTED, "nxg_multi_build takes none of NXG_BUILD_DEGREE, NXG_BUILD_SCATTER, "
+                                       "NXG_BUILD_HOST_STREAM");
         nxg_multi* mg = new nxg_multi();
         try {
             for (int32_t i = 0; i < count; ++i)
@@ -140,8 +141,10 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
                                   NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER |
-                                  NXG_BUILD_DEGREE))
+                                  NXG_BUILD_DEGREE | NXG_BUILD_HOST_STREAM))
             fail(NXG_EINVAL, "unknown build flag");
+        if ((d.flags & NXG_BUILD_HOST_STREAM) && (d.flags & (NXG_BUILD_TRANSPOSE | NXG_BUILD_SCATTER)))
+            fail(NXG_EINVAL, "HOST_STREAM cannot be combined with TRANSPOSE or SCATTER");
         if ((d.flags & NXG_BUILD_SCATTER) &&
             (d.flags & (NXG_BUILD_RELABEL | NXG_BUILD_TRANSPOSE | NXG_BUILD_DEGREE)))
             fail(NXG_EINVAL, "SCATTER cannot be combined with RELABEL, TRANSPOSE or DEGREE");
@@ -165,6 +168,22 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
                 if (dd.interval > dd.n) dd.interval = dd.n;
             }
             build_layout(dd, false, s, g->fwd);
+            if (d.flags & NXG_BUILD_HOST_STREAM) {
+                // the edge stream (and weights) move to pinned host memory
+                Layout& L = g->fwd;
+                L.h_words.alloc(sizeof(uint32_t) * (size_t)L.n_words);
+                NXG_HIP(hipMemcpyAsync(L.h_words.p, L.words.p, sizeof(uint32_t) * (size_t)L.n_words,
+                                       hipMemcpyDeviceToHost, s));
+                if (L.has_weight) {
+                    L.h_weight.alloc(sizeof(float) * (size_t)L.n_words);
+                    NXG_HIP(hipMemcpyAsync(L.h_weight.p, L.weight.p, sizeof(float) * (size_t)L.n_words,
+                                           hipMemcpyDeviceToHost, s));
+                }
+                NXG_HIP(hipStreamSynchronize(s));
+                L.words.reset();
+                L.weight.reset();
+                L.host_stream = true;
+            }
             if (d.flags & NXG_BUILD_TRANSPOSE) {
                 build_layout(dd, true, s, g->rev);
                 g->has_rev = true;
@@ -237,6 +256,7 @@ nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets
     return guarded([&]() {
         if (!g) fail(NXG_EINVAL, "handle is NULL");
         if (transposed && !g->has_rev) fail(NXG_EINVAL, "handle has no transposed graph");
+        if (!transposed && g->fwd.host_stream) fail(NXG_EINVAL, "the edge stream is in host memory (HOST_STREAM)");
         export_layout(transposed ? g->rev : g->fwd, d_offsets, d_src, d_dst, d_perm,
                       (hipStream_t)stream);
         return NXG_OK;

@@ -1550,12 +1550,15 @@ int num_cus(int device) {
 // Splits every tile into pieces of at most piece_chunks chunks; heavy tiles
 // first. With whole_tiles every piece carries the tile's full chunk range (the
 // pieces then split the tile's compacted active list at run time).
-Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s) {
+Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s,
+               bool tile_order = false) {
     for (Plan* p : g->plans)
-        if (p->layout == &L && p->piece_chunks == piece_chunks && p->whole_tiles == whole_tiles)
+        if (p->layout == &L && p->piece_chunks == piece_chunks && p->whole_tiles == whole_tiles &&
+            p->tile_order == tile_order)
             return p;
     Plan* p = new Plan();
     p->layout = &L;
+    p->tile_order = tile_order;
     p->piece_chunks = piece_chunks;
     p->whole_tiles = whole_tiles;
     std::vector<Item> items;
@@ -1585,11 +1588,13 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
             items.push_back(it);
         }
     }
-    std::stable_sort(items.begin(), items.end(), [np_whole = whole_tiles](const Item& a, const Item& b) {
-        int64_t wa = np_whole ? (a.c1 - a.c0) / a.npieces : a.c1 - a.c0;
-        int64_t wb = np_whole ? (b.c1 - b.c0) / b.npieces : b.c1 - b.c0;
-        return wa > wb;
-    });
+    if (!tile_order) {
+        std::stable_sort(items.begin(), items.end(), [np_whole = whole_tiles](const Item& a, const Item& b) {
+            int64_t wa = np_whole ? (a.c1 - a.c0) / a.npieces : a.c1 - a.c0;
+            int64_t wb = np_whole ? (b.c1 - b.c0) / b.npieces : b.c1 - b.c0;
+            return wa > wb;
+        });
+    }
     p->h_items = items;
     p->n_slots = slots;
     p->items.alloc(sizeof(Item) * std::max<size_t>(items.size(), 1), s);
@@ -1679,14 +1684,115 @@ void prepare_iter(size_t lds) {
     }
 }
 
+// A host-resident edge stream (NXG_BUILD_HOST_STREAM) is fed to the edge
+// kernel through two device staging buffers: the items run in stream order, in
+// batches of whole items whose chunks fit one buffer, and the copy of batch j+1
+// (on a copy stream) overlaps the edge work of batch j. The batch counter runs
+// on across iterations, so the copy of the next iteration's first batch also
+// overlaps this iteration's finishing launches.
+struct Streamer {
+    struct Batch {
+        int i0, i1;      // items [i0, i1)
+        int64_t c0, c1;  // their chunks [c0, c1)
+    };
+    const Layout* L = nullptr;
+    const Plan* p = nullptr;
+    std::vector<Batch> batches;
+    DevBuf wst[2], fst[2];
+    hipStream_t cs = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+    int64_t issued = 0, launched = 0;
+    ~Streamer() {
+        for (int b = 0; b < 2; ++b) {
+            if (copied[b]) (void)hipEventDestroy(copied[b]);
+            if (used[b]) (void)hipEventDestroy(used[b]);
+        }
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    void init(const Layout& lay, const Plan& plan, int64_t cap_chunks, hipStream_t s) {
+        L = &lay;
+        p = &plan;
+        const std::vector<Item>& it = plan.h_items;
+        for (int i = 0; i < (int)it.size(); ++i) {
+            if (it[i].c1 == it[i].c0) {  // an empty tile rides with its neighbours
+                if (batches.empty()) batches.push_back(Batch{i, i + 1, it[i].c0, it[i].c1});
+                else batches.back().i1 = i + 1;
+                continue;
+            }
+            if (batches.empty() || it[i].c1 - batches.back().c0 > cap_chunks)
+                batches.push_back(Batch{i, i + 1, it[i].c0, it[i].c1});
+            else {
+                batches.back().i1 = i + 1;
+                batches.back().c1 = it[i].c1;
+            }
+        }
+        int64_t most = 1;
+        for (const Batch& b : batches) most = std::max<int64_t>(most, b.c1 - b.c0);
+        for (int b = 0; b < 2; ++b) {
+            wst[b].alloc(sizeof(uint32_t) * (size_t)most * lay.C, s);
+            if (lay.has_weight) fst[b].alloc(sizeof(float) * (size_t)most * lay.C, s);
+            NXG_HIP(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
+            NXG_HIP(hipEventCreateWithFlags(&used[b], hipEventDisableTiming));
+        }
+        NXG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        NXG_HIP(hipStreamSynchronize(s));  // the staging buffers exist before cs uses them
+    }
+    // copy of global batch j into buffer j & 1, once the edge work of j - 2 is done
+    void issue(int64_t j) {
+        const int buf = (int)(j & 1);
+        const Batch& b = batches[j % (int64_t)batches.size()];
+        if (j >= 2) NXG_HIP(hipStreamWaitEvent(cs, used[buf], 0));
+        const size_t off = (size_t)b.c0 * L->C, cnt = (size_t)(b.c1 - b.c0) * L->C;
+        if (cnt) {
+            NXG_HIP(hipMemcpyAsync(wst[buf].p, L->h_words.as<uint32_t>() + off, sizeof(uint32_t) * cnt,
+                                   hipMemcpyHostToDevice, cs));
+            if (L->has_weight)
+                NXG_HIP(hipMemcpyAsync(fst[buf].p, L->h_weight.as<float>() + off, sizeof(float) * cnt,
+                                       hipMemcpyHostToDevice, cs));
+        }
+        NXG_HIP(hipEventRecord(copied[buf], cs));
+    }
+    // the edge kernel over every batch of one iteration
+    template <class Prog, int WG>
+    void launch(const Geo& geo, const Ctl& ctl, const Prog& prog, size_t lds, hipStream_t s) {
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            const int64_t j = launched;
+            while (issued <= j) issue(issued++);
+            const int buf = (int)(j & 1);
+            const Batch& b = batches[bi];
+            NXG_HIP(hipStreamWaitEvent(s, copied[buf], 0));
+            // the kernel indexes words by global chunk: the buffer holds chunks
+            // [c0, c1), so its base is shifted back by c0 chunks (only
+            // [c0, c1) is ever read through it)
+            Geo gb = geo;
+            gb.items = p->items.as<Item>() + b.i0;
+            gb.words = reinterpret_cast<const uint32_t*>(reinterpret_cast<uintptr_t>(wst[buf].p) -
+                                                         (uintptr_t)b.c0 * L->C * sizeof(uint32_t));
+            Prog pb = prog;
+            if constexpr (Prog::kWeights)
+                pb.w = reinterpret_cast<const float*>(reinterpret_cast<uintptr_t>(fst[buf].p) -
+                                                      (uintptr_t)b.c0 * L->C * sizeof(float));
+            if (b.i1 > b.i0) {
+                hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(b.i1 - b.i0), dim3(WG), lds, s, gb, ctl, pb);
+                NXG_CHECK_LAUNCH();
+            }
+            NXG_HIP(hipEventRecord(used[buf], s));
+            ++launched;
+            if (issued == launched) issue(issued++);  // the next batch into the other buffer
+        }
+    }
+};
+
 // One iteration: the items, the split tiles, the scalar reduction (no memsets,
 // so it can be recorded into a hipGraph).
 template <class Prog, int WG>
 void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p, size_t lds,
-                 hipStream_t s) {
+                 hipStream_t s, Streamer* str = nullptr) {
     prepare_iter<Prog, WG>(lds);
     const int n_items = (int)p.h_items.size();
-    if (n_items > 0) {
+    if (str) {
+        str->launch<Prog, WG>(geo, ctl, prog, lds, s);
+    } else if (n_items > 0) {
         hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
         NXG_CHECK_LAUNCH();
     }
@@ -1994,8 +2100,20 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     const int cus = num_cus(g->device);
     int piece = d.piece_chunks > 0 ? d.piece_chunks : env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * ab, cus);
-    if (d.flags & NXG_RUN_CAPTURE) return run_pagerank_captured<V>(g, d, s, st, piece);
-    Plan* p = get_plan(g, L, piece, false, s);
+    std::unique_ptr<Streamer> str;
+    if (L.host_stream) {
+        if (d.flags & NXG_RUN_CAPTURE) fail(NXG_EINVAL, "HOST_STREAM runs cannot be captured");
+        // staging buffer size; pieces never exceed one buffer
+        const int64_t mb = std::max(1, env_int("NXG_STREAM_MB", 256));
+        const int64_t cap = std::max<int64_t>(1, mb * (1 << 20) / ((int64_t)L.C * 4));
+        piece = (int)std::min<int64_t>(piece, cap);
+        str.reset(new Streamer());
+        Plan* sp = get_plan(g, L, piece, false, s, true);
+        str->init(L, *sp, cap, s);
+    } else if (d.flags & NXG_RUN_CAPTURE) {
+        return run_pagerank_captured<V>(g, d, s, st, piece);
+    }
+    Plan* p = get_plan(g, L, piece, false, s, L.host_stream);
     Workspace w;
     const int max_iters = d.max_iters;
     alloc_common(w, L, *p, ab, max_iters, s, false);
@@ -2043,10 +2161,10 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             V* xout = (k == max_iters - 1) ? vals : nullptr;
             if (weighted) {
                 ProgPRW<V> pr{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
-                launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, *p, lds, s);
+                launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, *p, lds, s, str.get());
             } else {
                 ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
-                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s);
+                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s, str.get());
             }
         }
         if (d.tol > 0 && k < max_iters) {
@@ -2720,6 +2838,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
 }
 
 void set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) {
+    if (g->fwd.host_stream) fail(NXG_EINVAL, "the weights of a HOST_STREAM handle are in host memory");
     for (Layout* L : {&g->fwd, &g->rev}) {
         if (L == &g->rev && !g->has_rev) continue;
         if (!L->has_weight || !L->has_perm)
@@ -2793,6 +2912,10 @@ int lds_budget_bytes(int device) {
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
     if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    if (g->fwd.host_stream &&
+        ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 || d.d_seeds ||
+         (d.flags & NXG_RUN_SCATTER)))
+        fail(NXG_EINVAL, "a HOST_STREAM handle runs single-column PageRank only");
     if ((d.flags & NXG_RUN_SCATTER) || (g->flags & NXG_BUILD_SCATTER)) {
         if (!(d.flags & NXG_RUN_SCATTER)) fail(NXG_EINVAL, "a NXG_BUILD_SCATTER layout runs only NXG_RUN_SCATTER PageRank");
         if (d.batch > 1 || d.d_seeds) fail(NXG_EUNSUPPORTED, "NXG_RUN_SCATTER runs one column");

@@ -97,6 +97,34 @@ struct DevBuf {
 // tile; chunk_row[c] is the source interval in effect at the chunk's first
 // word and chunk_row_last[c] the one in effect at its last edge.
 // ---------------------------------------------------------------------------
+// Pinned host memory (hipHostMalloc), freed with the owner.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf() { reset(); }
+    void alloc(size_t b) {
+        reset();
+        bytes = b ? b : 16;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            bytes = 0;
+            fail(NXG_ENOMEM, "pinned host allocation failed");
+        }
+    }
+    void reset() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
 struct Layout {
     int32_t n = 0, I = 0, P = 0, L = 0;
     int32_t T = 0, t = 0, n_tiles = 0, C = 0, order = 0;
@@ -113,6 +141,9 @@ struct Layout {
     std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
     std::vector<int64_t> h_tile_edges;  // edges per tile (host)
     bool has_perm = false, has_weight = false;
+    // NXG_BUILD_HOST_STREAM: words (and weights) live in pinned host memory
+    bool host_stream = false;
+    HostBuf h_words, h_weight;
 };
 
 // Item of work for the iteration kernels: one piece of one destination tile.
@@ -140,6 +171,7 @@ struct Layout;
 struct Plan {
     const Layout* layout = nullptr;
     bool whole_tiles = false;
+    bool tile_order = false;  // items in stream order (host-streamed runs), not heaviest first
     int32_t piece_chunks = 0;
     std::vector<Item> h_items;
     DevBuf items;

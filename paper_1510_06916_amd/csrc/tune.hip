@@ -103,7 +103,8 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
         fail(NXG_EUNSUPPORTED, "the autotuner times PageRank runs");
     if (dtype != NXG_F32 && dtype != NXG_F64) fail(NXG_EINVAL, "PageRank dtype must be F32 or F64");
     if (batch != 1) fail(NXG_EUNSUPPORTED, "the autotuner times single-column runs");
-    if (desc.flags & NXG_BUILD_SCATTER) fail(NXG_EUNSUPPORTED, "the autotuner times DSSS layouts, not NXG_BUILD_SCATTER");
+    if (desc.flags & (NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM))
+        fail(NXG_EUNSUPPORTED, "the autotuner times device-resident DSSS layouts (no SCATTER, no HOST_STREAM)");
     int device = 0;
     NXG_HIP(hipGetDevice(&device));
     const std::string key = tune_key(desc, program, dtype, batch, device);
