@@ -807,15 +807,20 @@ __global__ __launch_bounds__(WG) void k_multi_finish(const MultiGraph* __restric
                                    f.f.sslot, acc);
 }
 
-// One workgroup per graph: x^0 = 1/n (gathered array x^0 / outdeg) and the
-// dangling mass entering iteration 0, summed in a fixed order.
-__global__ __launch_bounds__(256) void k_multi_init(const MultiGraph* __restrict__ graphs) {
+// kMultiBlocks workgroups per graph for the start and the final mapping.
+constexpr int kMultiBlocks = 16;
+
+// x^0 = 1/n (gathered array x^0 / outdeg) and per-block dangling partial sums;
+// block b works on graph b / kMultiBlocks.
+__global__ __launch_bounds__(256) void k_multi_init(const MultiGraph* __restrict__ graphs,
+                                                    double* __restrict__ part) {
     __shared__ double red[4];
-    const MultiGraph& mg = graphs[blockIdx.x];
+    const MultiGraph& mg = graphs[blockIdx.x / kMultiBlocks];
+    const int j = blockIdx.x % kMultiBlocks;
     const int32_t n = mg.geo.n;
     const float x = (float)(1.0 / n);
     double sdang = 0.0;
-    for (int64_t v = threadIdx.x; v < n; v += 256) {
+    for (int64_t v = (int64_t)j * 256 + threadIdx.x; v < n; v += kMultiBlocks * 256) {
         const int32_t dg = mg.geo.deg[v];
         if (dg == 0) sdang += (double)x;
         mg.buf0[v] = dg ? (float)((double)x / dg) : x;
@@ -823,14 +828,27 @@ __global__ __launch_bounds__(256) void k_multi_init(const MultiGraph* __restrict
     sdang = wave_sum(sdang);
     if (lane_id() == 0) red[threadIdx.x >> 6] = sdang;
     __syncthreads();
-    if (threadIdx.x == 0) mg.stats[0] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// One workgroup per relabeled graph: the result into the caller's ids.
+// The dangling mass entering iteration 0 of every graph: its blocks' partial
+// sums in block order (one thread per graph).
+__global__ void k_multi_init_sum(const MultiGraph* __restrict__ graphs, int G, const double* __restrict__ part) {
+    for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        for (int j = 0; j < kMultiBlocks; ++j) sum += part[gi * kMultiBlocks + j];
+        graphs[gi].stats[0] = sum;
+    }
+}
+
+// The result of every relabeled graph into the caller's ids (kMultiBlocks
+// workgroups per graph).
 __global__ __launch_bounds__(256) void k_multi_emit(const MultiGraph* __restrict__ graphs) {
-    const MultiGraph& mg = graphs[blockIdx.x];
+    const MultiGraph& mg = graphs[blockIdx.x / kMultiBlocks];
     if (!mg.o2n) return;
-    for (int64_t v = threadIdx.x; v < mg.geo.n; v += 256) mg.user[v] = mg.xout[mg.o2n[v]];
+    const int j = blockIdx.x % kMultiBlocks;
+    for (int64_t v = (int64_t)j * 256 + threadIdx.x; v < mg.geo.n; v += kMultiBlocks * 256)
+        mg.user[v] = mg.xout[mg.o2n[v]];
 }
 
 // The last iteration's residual of every graph, gathered for one copy to the host.
@@ -1643,7 +1661,7 @@ struct MultiCache : Cached {
     size_t lds = 0;
     std::vector<Workspace> ws;
     std::vector<MultiGraph> hdesc;
-    DevBuf ditems, dgraph, ddesc, dfin, dres;
+    DevBuf ditems, dgraph, ddesc, dfin, dres, dpart;
 };
 
 // Index arrays of a relabeled or degreed build (both NULL otherwise); n is the
@@ -2633,6 +2651,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         nc->dgraph.alloc(sizeof(int32_t) * std::max<size_t>(sorted_graph.size(), 1), s);
         nc->ddesc.alloc(sizeof(MultiGraph) * G, s);
         nc->dres.alloc(sizeof(double) * G, s);
+        nc->dpart.alloc(sizeof(double) * G * kMultiBlocks, s);
         NXG_HIP(hipMemcpyAsync(nc->ditems.p, sorted_items.data(), sizeof(Item) * sorted_items.size(),
                                hipMemcpyHostToDevice, s));
         NXG_HIP(hipMemcpyAsync(nc->dgraph.p, sorted_graph.data(), sizeof(int32_t) * sorted_graph.size(),
@@ -2660,7 +2679,9 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     NXG_HIP(hipEventCreate(&e0));
     NXG_HIP(hipEventCreate(&e1));
     NXG_HIP(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_multi_init, dim3(G), dim3(256), 0, s, ddesc);
+    hipLaunchKernelGGL(k_multi_init, dim3(G * kMultiBlocks), dim3(256), 0, s, ddesc, c->dpart.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_multi_init_sum, dim3((G + 255) / 256), dim3(256), 0, s, ddesc, G, c->dpart.as<double>());
     NXG_CHECK_LAUNCH();
     for (int k = 0; k < iters; ++k) {
         hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, s, ddesc,
@@ -2674,7 +2695,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, s, ddesc, k);
         NXG_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_multi_emit, dim3(G), dim3(256), 0, s, ddesc);
+    hipLaunchKernelGGL(k_multi_emit, dim3(G * kMultiBlocks), dim3(256), 0, s, ddesc);
     NXG_CHECK_LAUNCH();
     NXG_HIP(hipEventRecord(e1, s));
     std::vector<double> res(G);
