@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 5
+#define NXG_ABI_VERSION 6
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -257,12 +257,20 @@ typedef struct nxg_run_stats {
     int32_t changed_rounds; /* BFS/WCC: rounds that changed at least one value */
     int64_t reached_edges;  /* BFS: sum of out-degrees of reached vertices */
     double device_ms;       /* time between the first and last launch, HIP events */
+    int64_t streamed_chunks;/* BFS/WCC: chunks streamed, summed over the rounds. Sec. II-B
+                               activity at the grain of 64-vertex blocks: a chunk is
+                               streamed in a round when its source id range holds a block
+                               changed in the previous round and, for BFS, its destination
+                               id range holds a block with an unreached vertex; 0 for
+                               other programs */
 } nxg_run_stats;
 
 /* Runs the program on the stored graph. With stats == NULL the call is fully
  * asynchronous (PageRank with tol <= 0 only); otherwise it synchronises the
  * stream and fills *stats. Returns NXG_ENOTCONV when tol > 0 was not reached
- * (values are still written). */
+ * (values are still written). BFS and WCC runs keep their workspace (and the
+ * per-chunk id ranges their activity test reads) in the handle from the first
+ * run on, so such runs on one handle must not overlap. */
 nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
 
 /* ------------------------------------------------------------------------- */

@@ -59,7 +59,7 @@ class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("max_level", ctypes.c_int32),
                 ("changed_rounds", ctypes.c_int32), ("reached_edges", ctypes.c_int64),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("streamed_chunks", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

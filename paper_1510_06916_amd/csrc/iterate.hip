@@ -42,6 +42,8 @@ constexpr int kSpill = 64;  // LDS accumulators past the tile: lane l's discard 
 // kFinWG threads (one vertex per thread) each, so a heavy tile's FromHub is
 // spread over many CUs and needs only kFinSeg accumulators of LDS.
 constexpr int kFinSeg = 256, kFinWG = 256;
+// workgroups of the two-step BFS output reduction
+constexpr int kFinalBlocks = 256;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -65,6 +67,9 @@ struct Geo {
     // compacted active chunk lists (BFS/WCC), nullable
     const int64_t* clist;
     const int32_t* ccount;
+    // with lists: a split tile listing at most this many chunks is done whole
+    // by its piece 0 in that round (no hub partials, no finishing segment work)
+    int64_t split_min;
 };
 
 // Per-iteration control block in device memory.
@@ -171,28 +176,29 @@ struct ProgBFS {
     static constexpr bool kSum = false, kWeights = false, kActivity = true;
     const int32_t* cur;
     int32_t* nxt;
-    const uint8_t* act;  // [P] source intervals updated in the previous round
-    uint8_t* act_nxt;    // [P] intervals updated in this round
-    int32_t P, I;
+    uint8_t* chg;  // [n >> bs] block flags: a vertex of the block changed in this round
+    uint8_t* opn;  // [n >> bs] block flags: a vertex of the block is still unreached
+    int32_t bs;    // log2 of the vertices per activity block
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t from_val(int32_t l, float) const { return l == kInf ? kInf : l + 1; }
     __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
-    // Inactive source intervals are skipped a chunk at a time (the compacted
-    // chunk list); edges of an inactive interval inside a kept chunk are
-    // processed anyway: their sources have not changed since they were last
-    // propagated, so they cannot lower a destination (Sec. II-B activity).
+    // Chunks none of whose sources changed in the previous round, or none of
+    // whose destinations is still unreached, are left out of the compacted
+    // chunk list; the edges of a kept chunk are all processed (an unchanged
+    // source offers what it offered before, which cannot lower a destination).
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
     struct Ld {
         int32_t c;
     };
     __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    // flag bit 0: the level changed; bit 1: the vertex is still unreached
     __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = l.c;
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) flag = 1;  // the caller raises the interval's activity flag
+        flag = (nv != o ? 1 : 0) | (nv == kInf ? 2 : 0);
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -204,28 +210,27 @@ struct ProgWCC {
     static constexpr bool kSum = false, kWeights = false, kActivity = true;
     const int32_t* cur;
     int32_t* nxt;
-    const uint8_t* act;
-    uint8_t* act_nxt;
-    int32_t P, I;
+    uint8_t* chg;  // [n >> bs] block flags: a vertex of the block changed in this round
+    uint8_t* opn;  // unused (a label may fall in any round)
+    int32_t bs;
     __device__ acc_t identity() const { return kInf; }
     __device__ acc_t from_val(int32_t l, float) const { return l; }
     __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
-    // Inactive source intervals are skipped a chunk at a time (the compacted
-    // chunk list); edges of an inactive interval inside a kept chunk are
-    // processed anyway: their sources have not changed since they were last
-    // propagated, so they cannot lower a destination (Sec. II-B activity).
+    // Chunks none of whose sources changed in the previous round are left out
+    // of the compacted chunk list (see ProgBFS).
     __device__ bool row_active(uint32_t) const { return true; }
     static __device__ bool converged(double, double, double) { return false; }
     struct Ld {
         int32_t c;
     };
     __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    // flag bit 0: the label changed
     __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
                           int& flag) const {
         int32_t o = l.c;
         int32_t nv = acc < o ? acc : o;
         nxt[v] = nv;
-        if (nv != o) flag = 1;  // the caller raises the interval's activity flag
+        flag = nv != o ? 1 : 0;
     }
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
@@ -329,7 +334,6 @@ __device__ void apply_range(const Geo& g, const Ctl& ctl, const Prog& prog, int6
     __shared__ double red[3][WG / 64];
     __shared__ int sflag;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint64_t lt = (1ull << lane) - 1ull;
     if (threadIdx.x == 0) sflag = 0;
     __syncthreads();
     const double scal = ctl.stats[ctl.k * 4 + 0];
@@ -338,6 +342,56 @@ __device__ void apply_range(const Geo& g, const Ctl& ctl, const Prog& prog, int6
     // kAR vertices per thread at a time: all their loads are issued (vertices
     // past the tile reload the first one) before the first update is computed
     constexpr int kAR = 4;
+    if constexpr (Prog::kActivity) {
+        // Block activity (Sec. II-B at a finer grain): the first lane of each
+        // block of 2^bs vertices stores the block's flags (changed; unreached).
+        // base is a multiple of the block size and a wave's lanes hold
+        // consecutive vertices, so a block lies inside one wave. A block not
+        // flagged as changed holds the same values in both buffers; if nothing
+        // reaches it in this round either it is skipped (no loads, no stores,
+        // flags unchanged). acc == NULL: nothing reaches the range at all.
+        // The range's flags from the previous round are first copied to LDS
+        // (at most kMaxBlk blocks: the range is at most a tile).
+        const int bl = 1 << prog.bs;  // <= 64
+        const int first = lane & ~(bl - 1);
+        const uint64_t bm = (bl == 64 ? ~0ull : (1ull << bl) - 1ull) << first;
+        constexpr int kMaxBlk = 1024;
+        __shared__ uint8_t was_s[kMaxBlk];
+        const int64_t b0 = base >> prog.bs;
+        const int nblk = (int)min((int64_t)kMaxBlk, (len + bl - 1) >> prog.bs);
+        for (int i = threadIdx.x; i < nblk; i += WG) was_s[i] = prog.chg[b0 + i];
+        __syncthreads();
+        for (int64_t x0 = threadIdx.x; x0 < len; x0 += kAR * WG) {
+            typename Prog::Ld ld[kAR];
+            bool need[kAR];
+#pragma unroll
+            for (int r = 0; r < kAR; ++r) {
+                const int64_t x = x0 + r * WG;
+                const bool in = x < len;
+                const int64_t xs = in ? x : x0;
+                const bool arrived = in && acc && acc[xs] != prog.identity();
+                const uint64_t am = __ballot(arrived);
+                const bool was = was_s[xs >> prog.bs] != 0;
+                need[r] = in && (was || (am & bm) != 0);
+                if (need[r]) ld[r] = prog.load(base + x);
+            }
+#pragma unroll
+            for (int r = 0; r < kAR; ++r) {
+                const int64_t x = x0 + r * WG;
+                if (x >= len) break;
+                if (!need[r]) continue;  // uniform over the block
+                int ch = 0;
+                prog.apply(base + x, ld[r], acc ? acc[x] : prog.identity(), 0, scal, g.n, sv, ch);
+                const uint64_t cm = __ballot(ch & 1), om = __ballot(ch & 2);
+                if (lane == first) {
+                    const int64_t b = (base + x) >> prog.bs;
+                    prog.chg[b] = (cm & bm) != 0;
+                    if (prog.opn) prog.opn[b] = (om & bm) != 0;
+                }
+                if (ch & 1) flag = 1;
+            }
+        }
+    } else {
     for (int64_t x0 = threadIdx.x; x0 < len; x0 += kAR * WG) {
         typename Prog::Ld ld[kAR];
         int32_t dgv[kAR];
@@ -351,24 +405,9 @@ __device__ void apply_range(const Geo& g, const Ctl& ctl, const Prog& prog, int6
         for (int r = 0; r < kAR; ++r) {
             const int64_t x = x0 + r * WG;
             if (x >= len) break;
-            if constexpr (Prog::kActivity) {
-                // interval activity (Sec. II-B): one flag store per interval and wave
-                // (a changed lane stores unless a lower changed lane of the wave has
-                // the same interval; a wave's vertices are consecutive)
-                int ch = 0;
-                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, ch);
-                const uint64_t cm = __ballot(ch != 0);
-                if (ch) {
-                    flag = 1;
-                    const int32_t iv = (int32_t)((base + x) / prog.I);
-                    const uint64_t lower = cm & lt;
-                    const int32_t piv = __shfl(iv, lower ? 63 - __clzll(lower) : lane);
-                    if (!lower || piv != iv) prog.act_nxt[iv] = 1;
-                }
-            } else {
-                prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, flag);
-            }
+            prog.apply(base + x, ld[r], acc[x], dgv[r], scal, g.n, sv, flag);
         }
+    }
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -378,13 +417,19 @@ __device__ void apply_range(const Geo& g, const Ctl& ctl, const Prog& prog, int6
     if (flag) sflag = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
+        if constexpr (Prog::kActivity) {
+            // no scalars; the round's changed flag (cleared before the round) is
+            // raised directly, so no reduction launch follows
+            if (sflag) ctl.stats[ctl.k * 4 + 3] = 1.0;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            double a = 0.0;
-            for (int w = 0; w < WG / 64; ++w) a += red[q][w];
-            g.tile_s[3 * slot + q] = a;
+            for (int q = 0; q < 3; ++q) {
+                double a = 0.0;
+                for (int w = 0; w < WG / 64; ++w) a += red[q][w];
+                g.tile_s[3 * slot + q] = a;
+            }
+            g.tile_flag[slot] = sflag;
         }
-        g.tile_flag[slot] = sflag;
     }
 }
 
@@ -470,6 +515,27 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         return;
     }
 
+    // chunk source: explicit range, or this piece's share of the tile's compacted list
+    int64_t c_lo = it.c0, c_hi = it.c1;
+    const int64_t* list = nullptr;
+    int npieces = it.npieces;
+    if (g.clist) {
+        const int64_t cnt = g.ccount[tile];
+        if (npieces > 1 && cnt <= g.split_min) {
+            if (it.piece > 0) return;  // piece 0 takes the whole (short) list
+            npieces = 1;
+        }
+        list = g.clist + it.c0;  // tile's first chunk = list origin
+        c_lo = cnt * it.piece / npieces;
+        c_hi = cnt * (it.piece + 1) / npieces;
+        if constexpr (Prog::kActivity) {
+            if (cnt == 0) {  // nothing reaches the tile: no accumulators to clear
+                apply_range<Prog, WG>(g, ctl, prog, base, len, tile, nullptr);
+                return;
+            }
+        }
+    }
+
     for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
     __syncthreads();
 
@@ -480,17 +546,6 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
     const uint32_t lmask = (1u << g.L) - 1u;
     const uint32_t tmask = (1u << g.t) - 1u;
     const int steps = g.C >> 8;
-
-    // chunk source: explicit range, or this piece's share of the tile's compacted list
-    int64_t c_lo = it.c0, c_hi = it.c1;
-    const int64_t* list = nullptr;
-    if (g.clist) {
-        const int64_t lbeg = it.c0;  // tile's first chunk = list origin
-        const int64_t cnt = g.ccount[tile];
-        list = g.clist + lbeg;
-        c_lo = cnt * it.piece / it.npieces;
-        c_hi = cnt * (it.piece + 1) / it.npieces;
-    }
 
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     if (g.order != NXG_ORDER_SRC) {
@@ -717,7 +772,7 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
 
     // a piece stores its partial in its hub slot; k_finish combines them (its
     // segments carry the tile's scalars, the tile's own slot holds zeros)
-    if (it.npieces > 1) {
+    if (npieces > 1) {
         acc_t* part = reinterpret_cast<acc_t*>(g.partial) + (int64_t)(it.slot + it.piece) * g.T;
         for (int64_t x = threadIdx.x; x < len; x += WG) part[x] = acc[x];
         if (it.piece == 0 && threadIdx.x == 0) {
@@ -741,6 +796,14 @@ __global__ __launch_bounds__(WG) void k_finish(Geo g, Ctl ctl, Prog prog, const 
     extern __shared__ __align__(16) unsigned char smem[];
     if (*ctl.done) return;  // converged: the pieces have carried the vectors over
     const FinSeg f = fin[blockIdx.x];
+    if (g.clist && g.ccount[f.tile] <= g.split_min) {
+        // the tile was done whole this round: the segment's scalar slot is empty
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < 3; ++q) g.tile_s[3 * f.sslot + q] = 0.0;
+            g.tile_flag[f.sslot] = 0;
+        }
+        return;
+    }
     typename Prog::acc_t* acc = reinterpret_cast<typename Prog::acc_t*>(smem);
     gather_hub<Prog, WG>(g, prog, f, acc);
     apply_range<Prog, WG>(g, ctl, prog, ((int64_t)f.tile << g.t) + f.v0, f.vlen, f.sslot, acc);
@@ -994,90 +1057,260 @@ __global__ void k_unscale(int32_t n, const int32_t* __restrict__ deg, const V* _
         out[v] = (divide && deg[v]) ? (V)((double)cur[v] * deg[v]) : cur[v];
 }
 
-__global__ void k_init_bfs(int32_t n, int32_t root, int32_t* __restrict__ lev,
-                           uint8_t* __restrict__ act, int P, int I) {
+// Levels into both buffers (a block not flagged as changed must agree in the
+// two). Block flags before the first round: only the root's block has
+// changed, and every block may hold an unreached vertex. The root comes in the
+// caller's ids (o2n maps it; -1: an id without edges, which reaches nothing).
+// Zeroes the streamed-chunk count.
+__global__ void k_init_bfs(int32_t n, int32_t root_caller, const int32_t* __restrict__ o2n,
+                           int32_t* __restrict__ lev, int32_t* __restrict__ lev1,
+                           uint8_t* __restrict__ chg, uint8_t* __restrict__ opn, int bs,
+                           unsigned long long* __restrict__ streamed) {
+    const int32_t root = o2n ? o2n[root_caller] : root_caller;
+    const int64_t nb = ((int64_t)n + (1 << bs) - 1) >> bs;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        lev[v] = v == root ? 0 : kInf;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P;
-         x += (int64_t)gridDim.x * blockDim.x)
-        act[x] = x == root / I ? 1 : 0;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        lev[v] = lev1[v] = v == root ? 0 : kInf;
+        if (v < nb) {
+            chg[v] = (root >= 0 && v == (root >> bs)) ? 1 : 0;
+            opn[v] = 1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *streamed = 0;
 }
 
 // Labels start as the vertex's caller id (its own id, or new2old[v] in a
 // relabeled build), so the fixed point is the minimum caller id of the component.
-__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, uint8_t* __restrict__ act, int P,
-                           const int32_t* __restrict__ ids) {
+// Every block counts as changed before the first round (labels go into both
+// buffers, as for BFS).
+__global__ void k_init_wcc(int32_t n, int32_t* __restrict__ lab, int32_t* __restrict__ lab1,
+                           uint8_t* __restrict__ chg, int bs, const int32_t* __restrict__ ids,
+                           unsigned long long* __restrict__ streamed) {
+    const int64_t nb = ((int64_t)n + (1 << bs) - 1) >> bs;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        lab[v] = ids ? ids[v] : (int32_t)v;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P;
-         x += (int64_t)gridDim.x * blockDim.x)
-        act[x] = 1;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        lab[v] = lab1[v] = ids ? ids[v] : (int32_t)v;
+        if (v < nb) chg[v] = 1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *streamed = 0;
 }
 
-// Interval activity (Sec. II-B): interval i is active in this round iff one of
-// its vertices changed in the previous round (flags written by the apply).
-// apref = prefix count of active intervals; the flags the coming round will
-// write are cleared here.
-__global__ __launch_bounds__(1024) void k_activity(const uint8_t* __restrict__ act, int P,
-                                                   int32_t* __restrict__ apref,
-                                                   uint8_t* __restrict__ act_next,
-                                                   int32_t* __restrict__ ccount, int n_tiles) {
-    __shared__ int32_t part[1024];
-    for (int x = threadIdx.x; x < n_tiles; x += 1024) ccount[x] = 0;  // k_compact appends
-    const int per = (P + 1023) / 1024;
-    const int a = threadIdx.x * per, b = min(P, a + per);
-    int32_t s = 0;
-    for (int i = a; i < b; ++i) {
-        s += act[i] != 0;
-        act_next[i] = 0;
+__global__ void k_set_root(int32_t* __restrict__ lev, int32_t root) {
+    if (threadIdx.x == 0) lev[root] = 0;
+}
+
+// The tile holding chunk c: the last tau with tchunk[tau] <= c.
+__device__ inline int tile_of_chunk(const int64_t* __restrict__ tchunk, int n_tiles, int64_t c) {
+    int lo = 0, hi = n_tiles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tchunk[mid] <= c)
+            lo = mid;
+        else
+            hi = mid;
     }
-    part[threadIdx.x] = s;
+    return lo;
+}
+
+// Per chunk, the smallest and largest source and destination (global ids) of
+// its edges, {slo, shi, dlo, dhi} (a chunk without edges gets
+// {INT32_MAX, -1, INT32_MAX, -1}), and its tile. One wave per chunk: lane l reads words
+// l, l + 64, ... and follows the interval markers as the iteration does.
+__global__ __launch_bounds__(256) void k_chunk_ranges(const uint32_t* __restrict__ words,
+                                                      const int32_t* __restrict__ crow,
+                                                      const int64_t* __restrict__ tchunk, int n_tiles,
+                                                      int64_t n_chunks, int C, int I, int L, int t,
+                                                      int sshift, int dshift, int4* __restrict__ out,
+                                                      int32_t* __restrict__ ctile) {
+    const int lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= n_chunks) return;  // uniform over the wave
+    const int tile = tile_of_chunk(tchunk, n_tiles, c);
+    const int64_t tb = (int64_t)tile << t;
+    const uint32_t lmask = (1u << L) - 1u, tmask = (1u << t) - 1u;
+    uint32_t row = (uint32_t)crow[c];
+    int32_t slo = INT32_MAX, shi = -1, dlo = INT32_MAX, dhi = -1;
+    for (int j = 0; j < C / 64; ++j) {
+        const uint32_t w = words[c * (int64_t)C + j * 64 + lane];
+        const bool mk = (w >> 31) != 0 && w != 0xFFFFFFFFu;  // a marker (not padding)
+        const uint64_t mm = __ballot(mk);
+        uint32_t r = row;
+        if (mm) {
+            const uint64_t upto = mm & (lt | (1ull << lane));
+            const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
+            r = upto ? got : row;
+            row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
+        }
+        if ((w >> 31) == 0) {
+            const int32_t sv = (int32_t)((int64_t)r * I + ((w >> sshift) & lmask));
+            const int32_t dv = (int32_t)(tb + ((w >> dshift) & tmask));
+            slo = min(slo, sv);
+            shi = max(shi, sv);
+            dlo = min(dlo, dv);
+            dhi = max(dhi, dv);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        slo = min(slo, __shfl_xor(slo, o));
+        shi = max(shi, __shfl_xor(shi, o));
+        dlo = min(dlo, __shfl_xor(dlo, o));
+        dhi = max(dhi, __shfl_xor(dhi, o));
+    }
+    if (lane == 0) {
+        out[c] = make_int4(slo, shi, dlo, dhi);
+        ctile[c] = tile;
+    }
+}
+
+// Block activity prefix counts, per segment of `seg` blocks (seg a multiple
+// of 1024; one workgroup per segment): for x in [0, nb], pre[x] = number of
+// flagged blocks in [x - x % seg, x), and tot[x / seg] = the segment's count
+// (a flag past nb reads as 0). Done for the changed flags (f0) and, when f1 is
+// not NULL, for the unreached flags. Workgroup 0 adds the previous round's
+// per-tile list lengths to *streamed (when not NULL), clears them for the
+// compaction to append to, and clears the round's changed flag.
+__device__ void count_and_clear(int32_t* __restrict__ ccount, int n_tiles,
+                                unsigned long long* __restrict__ streamed) {
+    __shared__ unsigned long long red[16];
+    unsigned long long sum = 0;
+    for (int x = threadIdx.x; x < n_tiles; x += blockDim.x) {
+        sum += (unsigned long long)ccount[x];
+        ccount[x] = 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    if (threadIdx.x == 0 && streamed) {
+        unsigned long long a = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += red[w];
+        *streamed += a;
     }
-    int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (int i = a; i < b; ++i) {
-        apref[i] = run;
-        run += act[i] != 0;
-    }
-    if (threadIdx.x == 1023) apref[P] = part[1023];
 }
 
-// Frontier compaction: per tile, the chunks that touch at least one active
-// source interval, stored from the tile's first chunk on. One thread per chunk;
-// the lanes of a wave that belong to one tile take their places with a single
-// atomic on the tile's count, so the order inside a tile's list varies from
-// run to run. BFS and WCC take integer minima, so their results do not depend
-// on it.
-__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tchunk, int n_tiles,
-                                                 int64_t n_chunks, const int32_t* __restrict__ crow,
-                                                 const int32_t* __restrict__ crow_last,
-                                                 const int32_t* __restrict__ apref,
+__global__ __launch_bounds__(1024) void k_blkscan(const uint8_t* __restrict__ f0,
+                                                  const uint8_t* __restrict__ f1, int64_t nb, int seg,
+                                                  int32_t* __restrict__ pre0, int32_t* __restrict__ pre1,
+                                                  int32_t* __restrict__ tot0, int32_t* __restrict__ tot1,
+                                                  int32_t* __restrict__ ccount, int n_tiles,
+                                                  unsigned long long* __restrict__ streamed,
+                                                  double* __restrict__ changed) {
+    __shared__ int32_t part[2][16];
+    if (blockIdx.x == 0) {
+        count_and_clear(ccount, n_tiles, streamed);
+        if (threadIdx.x == 0) *changed = 0.0;
+    }
+    const int per = seg / 1024;
+    const int64_t a = (int64_t)blockIdx.x * seg + (int64_t)threadIdx.x * per;
+    int32_t s0 = 0, s1 = 0;
+    for (int k = 0; k < per; ++k) {
+        const int64_t x = a + k;
+        if (x < nb) {
+            s0 += f0[x] != 0;
+            if (f1) s1 += f1[x] != 0;
+        }
+    }
+    // workgroup exclusive scan: inside each wave by shuffles, then over the
+    // 16 wave totals
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int32_t v0 = s0, v1 = s1;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t a0 = __shfl_up(v0, o), a1 = __shfl_up(v1, o);
+        if (lane >= o) {
+            v0 += a0;
+            v1 += a1;
+        }
+    }
+    if (lane == 63) {
+        part[0][wave] = v0;
+        part[1][wave] = v1;
+    }
+    __syncthreads();
+    int32_t r0 = v0 - s0, r1 = v1 - s1, all0 = 0, all1 = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) {
+            r0 += part[0][w];
+            r1 += part[1][w];
+        }
+        all0 += part[0][w];
+        all1 += part[1][w];
+    }
+    for (int k = 0; k < per; ++k) {
+        const int64_t x = a + k;
+        if (x > nb) break;
+        pre0[x] = r0;
+        if (f1) pre1[x] = r1;
+        if (x < nb) {
+            r0 += f0[x] != 0;
+            if (f1) r1 += f1[x] != 0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        tot0[blockIdx.x] = all0;
+        if (f1) tot1[blockIdx.x] = all1;
+    }
+}
+
+// Frontier compaction: per tile, the chunks that hold a source changed in the
+// previous round and (BFS, pre1 not NULL) a destination still unreached,
+// stored from the tile's first chunk on. A chunk's source and destination
+// ranges are tested against the block prefix counts (k_blkscan), so a kept
+// chunk may still hold only unchanged sources or reached destinations between
+// its extremes: a superset of the chunks that can lower a value. One thread
+// per chunk; the lanes of a wave that belong to one tile take their places
+// with a single atomic on the tile's count, so the order inside a tile's list
+// varies from run to run. BFS and WCC take integer minima, so their results
+// do not depend on it.
+__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tchunk,
+                                                 const int32_t* __restrict__ ctile,
+                                                 int64_t n_chunks, const int4* __restrict__ crng, int bs,
+                                                 int seg, int nseg, const int32_t* __restrict__ pre0,
+                                                 const int32_t* __restrict__ tot0,
+                                                 const int32_t* __restrict__ pre1,
+                                                 const int32_t* __restrict__ tot1,
                                                  int64_t* __restrict__ clist,
                                                  int32_t* __restrict__ ccount) {
+    // exclusive prefix of the segment counts (nseg <= 256)
+    __shared__ int32_t off[2][257];
+    {
+        const int x = threadIdx.x;
+        off[0][x + 1] = x < nseg ? tot0[x] : 0;
+        off[1][x + 1] = (pre1 && x < nseg) ? tot1[x] : 0;
+        if (x == 0) off[0][0] = off[1][0] = 0;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int32_t v0 = x >= o ? off[0][x + 1 - o] : 0;
+            const int32_t v1 = x >= o ? off[1][x + 1 - o] : 0;
+            __syncthreads();
+            off[0][x + 1] += v0;
+            off[1][x + 1] += v1;
+            __syncthreads();
+        }
+    }
+    // flagged blocks before block x (x in [0, nb]; seg is a power of two)
+    const int lseg = 31 - __clz(seg);
+    auto before = [&](int q, int64_t x) -> int32_t {
+        return off[q][x >> lseg] + (q ? pre1[x] : pre0[x]);
+    };
     const int lane = lane_id();
     for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < n_chunks; c0 += (int64_t)gridDim.x * 256) {
         const int64_t c = c0 + threadIdx.x;
         bool keep = false;
         int tile = 0;
+        int64_t origin = 0;
         if (c < n_chunks) {
-            keep = apref[crow_last[c] + 1] - apref[crow[c]] > 0;
-            // the tile holding chunk c: last tau with tchunk[tau] <= c
-            int lo = 0, hi = n_tiles;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (tchunk[mid] <= c)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            tile = lo;
+            // the loads of the two tests are independent (issued together), as
+            // is the list origin's
+            tile = ctile[c];
+            const int4 r = crng[c];
+            origin = tchunk[tile];
+            const int64_t s0 = (int64_t)r.x >> bs, s1 = ((int64_t)r.y >> bs) + 1;
+            const int64_t d0 = (int64_t)r.z >> bs, d1 = ((int64_t)r.w >> bs) + 1;
+            const bool any = r.y >= r.x;
+            const int64_t e0 = any ? s0 : 0, e1 = any ? s1 : 0;
+            const int64_t f0 = any ? d0 : 0, f1 = any ? d1 : 0;
+            keep = any && before(0, e1) - before(0, e0) > 0;
+            if (pre1) keep = keep && before(1, f1) - before(1, f0) > 0;
         }
         uint64_t pending = __ballot(keep);
         while (pending) {  // one round per distinct tile among the kept lanes
@@ -1087,17 +1320,24 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ tch
             int32_t base = 0;
             if (lane == leader) base = atomicAdd(&ccount[t], __popcll(mine));
             base = __shfl(base, leader);
-            if (keep && tile == t) clist[tchunk[t] + base + __popcll(mine & ((1ull << lane) - 1ull))] = c;
+            if (keep && tile == t) clist[origin + base + __popcll(mine & ((1ull << lane) - 1ull))] = c;
             pending &= ~mine;
         }
     }
 }
 
-// BFS output (Alg. 4) plus the reached-edge count used for TEPS.
+// Adds the last round's per-tile list lengths to *streamed (when not NULL).
+__global__ __launch_bounds__(1024) void k_count_streamed(int32_t* __restrict__ ccount, int n_tiles,
+                                                         unsigned long long* __restrict__ streamed) {
+    count_and_clear(ccount, n_tiles, streamed);
+}
+
+// BFS output (Alg. 4) plus the reached-edge count used for TEPS: per-block
+// partials (part[b] reached edges, part[kFinalBlocks + b] largest level) ...
 __global__ __launch_bounds__(256) void k_bfs_final(int32_t n, const int32_t* __restrict__ lev,
                                                    const int32_t* __restrict__ deg,
-                                                   int32_t* __restrict__ maxlev,
-                                                   unsigned long long* __restrict__ reached) {
+                                                   unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long red[2][4];
     int32_t mx = 0;
     unsigned long long r = 0;
     for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
@@ -1107,8 +1347,50 @@ __global__ __launch_bounds__(256) void k_bfs_final(int32_t n, const int32_t* __r
             r += (unsigned long long)deg[v];
         }
     }
-    atomicMax(maxlev, mx);
-    atomicAdd(reached, r);
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, __shfl_xor(mx, o));
+        r += __shfl_xor(r, o);
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x >> 6] = r;
+        red[1][threadIdx.x >> 6] = (unsigned long long)mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int w = 0; w < 4; ++w) {
+            a += red[0][w];
+            b = red[1][w] > b ? red[1][w] : b;
+        }
+        part[blockIdx.x] = a;
+        part[kFinalBlocks + blockIdx.x] = b;
+    }
+}
+
+// ... combined by one workgroup of kFinalBlocks threads into part[-2] (reached
+// edges) and part[-1] (largest level).
+__global__ __launch_bounds__(kFinalBlocks) void k_bfs_final_sum(unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long red[2][kFinalBlocks / 64];
+    unsigned long long a = part[threadIdx.x], b = part[kFinalBlocks + threadIdx.x];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        const unsigned long long y = __shfl_xor(b, o);
+        b = y > b ? y : b;
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0, m = 0;
+        for (int w = 0; w < kFinalBlocks / 64; ++w) {
+            s += red[0][w];
+            m = red[1][w] > m ? red[1][w] : m;
+        }
+        part[-2] = s;
+        part[-1] = m;
+    }
 }
 
 // lambda^0 = g, and per-block partial sums of g (S^0).
@@ -1649,7 +1931,7 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
 }
 
 struct Workspace {
-    DevBuf buf[2], partial, tile_s, tile_flag, stats, done, act, apref, clist,
+    DevBuf buf[2], partial, tile_s, tile_flag, stats, done, blk, bpre, btot, clist,
         ccount, part, bfsout;
     DevBuf mtele, mvals, mseeds, mgx, mxs;  // caller data in internal ids (relabeled builds)
 };
@@ -1819,8 +2101,10 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p
                            kFinSeg * sizeof(typename Prog::acc_t), s, geo, ctl, prog, p.fseg.as<FinSeg>());
         NXG_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL((k_reduce<Prog, 1024>), dim3(1), dim3(1024), 0, s, geo, ctl);
-    NXG_CHECK_LAUNCH();
+    if constexpr (!Prog::kActivity) {
+        hipLaunchKernelGGL((k_reduce<Prog, 1024>), dim3(1), dim3(1024), 0, s, geo, ctl);
+        NXG_CHECK_LAUNCH();
+    }
 }
 
 // ab = bytes of one LDS accumulator of the program.
@@ -1848,6 +2132,7 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     g.n_sslots = L.n_tiles + (int32_t)p.h_fseg.size();
     g.clist = nullptr;
     g.ccount = nullptr;
+    g.split_min = 0;
     return g;
 }
 
@@ -2244,101 +2529,144 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     return rc;
 }
 
+// The chunk ranges (and tiles) the compaction tests, made once per layout.
+void ensure_chunk_ranges(Layout& L, hipStream_t s) {
+    if (L.chunk_rng.p || L.n_chunks == 0) return;
+    DevBuf r, ct;
+    r.alloc(sizeof(int4) * (size_t)L.n_chunks, s);
+    ct.alloc(sizeof(int32_t) * (size_t)L.n_chunks, s);
+    const int sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
+    const int dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
+    hipLaunchKernelGGL(k_chunk_ranges, dim3((unsigned)((L.n_chunks + 3) / 4)), dim3(256), 0, s,
+                       L.words.as<uint32_t>(), L.chunk_row.as<int32_t>(), L.tile_chunk.as<int64_t>(),
+                       L.n_tiles, L.n_chunks, L.C, L.I, L.L, L.t, sshift, dshift, r.as<int4>(),
+                       ct.as<int32_t>());
+    NXG_CHECK_LAUNCH();
+    L.chunk_rng = std::move(r);
+    L.chunk_tile = std::move(ct);
+}
+
+// What a handle keeps between BFS (or WCC) runs: the workspace, sized for the
+// layout, so a run allocates nothing.
+struct MinprogCache : Cached {
+    bool bfs = false;
+    int piece = 0, block = 0, bs = 0, seg = 0, nseg = 0;
+    int64_t nb = 0;
+    Workspace w;
+};
+
 nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
-    const Layout& L = g->fwd;
     const bool bfs = d.program == NXG_BFS;
     if (!bfs && !(g->flags & NXG_BUILD_SYMMETRIZE))
         fail(NXG_EINVAL, "WCC needs a build with NXG_BUILD_SYMMETRIZE");
     const VMap vm = vmap_of(g);
-    const int64_t n_out = vm ? vm.n : L.n;
+    const int64_t n_out = vm ? vm.n : g->fwd.n;
     if (bfs) {
         if (!d.roots) fail(NXG_EINVAL, "BFS needs roots");
         if (d.batch != 1) fail(NXG_EUNSUPPORTED, "BFS runs one root per call");
         if (d.roots[0] < 0 || d.roots[0] >= n_out) fail(NXG_EINVAL, "BFS root outside [0, n)");
     }
-    int32_t root = bfs ? d.roots[0] : 0;
-    if (bfs && vm) {
-        NXG_HIP(hipMemcpyAsync(&root, vm.o2n + root, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        NXG_HIP(hipStreamSynchronize(s));
-        if (root < 0) {
-            // a root dropped by degreeing has no edges: it reaches only itself
-            int32_t* lev = (int32_t*)d.d_values;
-            hipLaunchKernelGGL(k_fill_val<int32_t>, dim3(grid_for(n_out)), dim3(256), 0, s, lev, n_out, kInf);
-            NXG_CHECK_LAUNCH();
-            const int32_t zero = 0;
-            NXG_HIP(hipMemcpyAsync(lev + d.roots[0], &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
-            NXG_HIP(hipStreamSynchronize(s));
-            if (st) {
-                memset(st, 0, sizeof(*st));
-                st->iterations = 1;
-                st->converged = 1;
-            }
-            return NXG_OK;
-        }
-    }
-    if (((size_t)L.T + kSpill) * 4 > (size_t)lds_budget_bytes(g->device))
+    if (((size_t)g->fwd.T + kSpill) * 4 > (size_t)lds_budget_bytes(g->device) || g->fwd.T > 65536)
         fail(NXG_EINVAL, "tile does not fit in LDS");
+    ensure_chunk_ranges(g->fwd, s);
+    const Layout& L = g->fwd;
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * 4, cus);
     Plan* p = get_plan(g, L, -piece, true, s);  // whole-tile ranges; pieces split the active list
-    Workspace w;
-    const int max_iters = d.max_iters;
     // the host reads the per-round stats a block of rounds at a time, so the
-    // device keeps one block of them (max_iters may be as large as n + 1)
+    // device keeps one block of them (max_iters may be as large as n + 1); the
+    // first block is longer (a power-law graph settles in about that many rounds)
     const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
-    alloc_common(w, L, *p, 4, block, s, true);
-    w.buf[0].alloc(sizeof(int32_t) * (L.n), s);
-    w.buf[1].alloc(sizeof(int32_t) * (L.n), s);
-    w.act.alloc(2 * (size_t)L.P, s);
-    w.apref.alloc(sizeof(int32_t) * (L.P + 1), s);
-    w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
-    w.ccount.alloc(sizeof(int32_t) * L.n_tiles, s);
-    uint8_t* act0 = w.act.as<uint8_t>();
-    if (bfs)
-        hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
-                           s, L.n, root, w.buf[0].as<int32_t>(), act0, L.P, L.I);
-    else
-        hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(std::max<int64_t>(L.n, L.P))), dim3(256), 0,
-                           s, L.n, w.buf[0].as<int32_t>(), act0, L.P, vm.n2o);
-    NXG_CHECK_LAUNCH();
-    Geo geo = make_geo(L, *p, w, 4);
-    geo.clist = w.clist.as<int64_t>();
-    geo.ccount = w.ccount.as<int32_t>();
-    const size_t lds = iter_lds(geo, L, 4);
-    const int n_items = (int)p->h_items.size();
+    const int first_block = std::max(block, env_int("NXG_SYNC_FIRST", 8));
+    MinprogCache* c = nullptr;
+    for (Cached* x : g->cached) {
+        MinprogCache* m = dynamic_cast<MinprogCache*>(x);
+        if (m && m->bfs == bfs && m->piece == piece && m->block == first_block) c = m;
+    }
+    if (!c) {
+        c = new MinprogCache();
+        g->cached.push_back(c);
+        c->bfs = bfs;
+        c->piece = piece;
+        c->block = first_block;
+        Workspace& w = c->w;
+        alloc_common(w, L, *p, 4, first_block, s, true);
+        w.buf[0].alloc(sizeof(int32_t) * (L.n), s);
+        w.buf[1].alloc(sizeof(int32_t) * (L.n), s);
+        // activity blocks of 2^bs vertices (at most a wave of the apply), their
+        // flags (changed, then unreached) and prefix counts per segment of `seg`
+        // blocks (at most 256 segments)
+        c->bs = std::min(6, L.t);
+        c->nb = ((int64_t)L.n + (1 << c->bs) - 1) >> c->bs;
+        c->seg = 4096;
+        while ((c->nb + c->seg) / c->seg > 256) c->seg *= 2;
+        c->nseg = (int)((c->nb + c->seg) / c->seg);  // segments over [0, nb]
+        w.blk.alloc(2 * (size_t)c->nb, s);
+        w.bpre.alloc(sizeof(int32_t) * 2 * (size_t)(c->nb + 1), s);
+        w.btot.alloc(sizeof(int32_t) * 2 * (size_t)c->nseg, s);
+        w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(L.n_chunks, 1), s);
+        w.ccount.alloc(sizeof(int32_t) * L.n_tiles, s);
+        // streamed-chunk count, reached edges, maximum level, then the BFS
+        // outputs' per-block partials
+        w.bfsout.alloc(sizeof(unsigned long long) * (3 + 2 * kFinalBlocks), s);
+    }
+    Workspace& w = c->w;
+    const int bs = c->bs, seg = c->seg, nseg = c->nseg;
+    const int64_t nb = c->nb;
+    uint8_t* chg = w.blk.as<uint8_t>();
+    uint8_t* opn = bfs ? chg + nb : nullptr;
+    int32_t* pre0 = w.bpre.as<int32_t>();
+    int32_t* pre1 = bfs ? pre0 + nb + 1 : nullptr;
+    int32_t* tot0 = w.btot.as<int32_t>();
+    int32_t* tot1 = bfs ? tot0 + nseg : nullptr;
+    unsigned long long* streamed = w.bfsout.as<unsigned long long>();
+    const int max_iters = d.max_iters;
     hipEvent_t e0, e1;
     NXG_HIP(hipEventCreate(&e0));
     NXG_HIP(hipEventCreate(&e1));
     NXG_HIP(hipEventRecord(e0, s));
+    // the root is mapped to its internal id on the device; a root dropped by
+    // degreeing (no edges) maps to -1 and reaches nothing but itself
+    if (bfs)
+        hipLaunchKernelGGL(k_init_bfs, dim3(grid_for(L.n)), dim3(256), 0, s, L.n, d.roots[0], vm.o2n,
+                           w.buf[0].as<int32_t>(), w.buf[1].as<int32_t>(), chg, opn, bs, streamed);
+    else
+        hipLaunchKernelGGL(k_init_wcc, dim3(grid_for(L.n)), dim3(256), 0, s, L.n,
+                           w.buf[0].as<int32_t>(), w.buf[1].as<int32_t>(), chg, bs, vm.n2o, streamed);
+    NXG_CHECK_LAUNCH();
+    Geo geo = make_geo(L, *p, w, 4);
+    geo.clist = w.clist.as<int64_t>();
+    geo.ccount = w.ccount.as<int32_t>();
+    geo.split_min = piece;
+    const size_t lds = iter_lds(geo, L, 4);
     int k = 0;
-    std::vector<double> hs(4 * (size_t)(block + 2));
+    std::vector<double> hs(4 * (size_t)(first_block + 2));
     bool fixed = false;
     int last_changed = 0;
     while (k < max_iters && !fixed) {
-        int kend = std::min(max_iters, k + block);
+        int kend = std::min(max_iters, k + (k == 0 ? first_block : block));
         int kb = k;
         for (; k < kend; ++k) {
-            uint8_t* act_cur = act0 + (size_t)(k & 1) * L.P;
-            uint8_t* act_nxt = act0 + (size_t)((k + 1) & 1) * L.P;
-            hipLaunchKernelGGL(k_activity, dim3(1), dim3(1024), 0, s, act_cur, L.P,
-                               w.apref.as<int32_t>(), act_nxt, w.ccount.as<int32_t>(), L.n_tiles);
+            hipLaunchKernelGGL(k_blkscan, dim3(nseg), dim3(1024), 0, s, chg, opn, nb, seg, pre0, pre1,
+                               tot0, tot1, w.ccount.as<int32_t>(), L.n_tiles, k > 0 ? streamed : nullptr,
+                               w.stats.as<double>() + 4 * (k - kb) + 3);
             NXG_CHECK_LAUNCH();
             if (L.n_chunks > 0) {
                 hipLaunchKernelGGL(k_compact, dim3(grid_for(L.n_chunks, 256, 4096)), dim3(256), 0, s,
-                                   L.tile_chunk.as<int64_t>(), L.n_tiles, L.n_chunks,
-                                   L.chunk_row.as<int32_t>(), L.chunk_row_last.as<int32_t>(),
-                                   w.apref.as<int32_t>(), w.clist.as<int64_t>(), w.ccount.as<int32_t>());
+                                   L.tile_chunk.as<int64_t>(), L.chunk_tile.as<int32_t>(), L.n_chunks,
+                                   L.chunk_rng.as<int4>(), bs, seg, nseg, pre0, tot0, pre1, tot1,
+                                   w.clist.as<int64_t>(), w.ccount.as<int32_t>());
             }
             NXG_CHECK_LAUNCH();
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k - kb, 0.0};
             const int32_t* cur = w.buf[k & 1].as<int32_t>();
             int32_t* nxt = w.buf[(k + 1) & 1].as<int32_t>();
             if (bfs) {
-                ProgBFS pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
+                ProgBFS pr{cur, nxt, chg, opn, bs};
                 launch_iter<ProgBFS, 1024>(geo, ctl, pr, *p, lds, s);
             } else {
-                ProgWCC pr{cur, nxt, act_cur, act_nxt, L.P, L.I};
+                ProgWCC pr{cur, nxt, chg, nullptr, bs};
                 launch_iter<ProgWCC, 1024>(geo, ctl, pr, *p, lds, s);
             }
         }
@@ -2355,24 +2683,33 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     }
     // the values after round k live in buf[k & 1]; rounds past the fixed point copy
     NXG_HIP(hipEventRecord(e1, s));
-    if (vm)
-        permute_rows<int32_t>(w.buf[k & 1].as<int32_t>(), vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1,
-                              bfs ? kInf : 0, bfs ? 0 : 1);
-    else
-        hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s,
-                           w.buf[k & 1].as<int32_t>(), (int32_t*)d.d_values, (int64_t)L.n);
+    const int32_t* fin = w.buf[k & 1].as<int32_t>();
+    if (vm) {
+        permute_rows<int32_t>(fin, vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1, bfs ? kInf : 0,
+                              bfs ? 0 : 1);
+        if (bfs)  // a dropped root keeps level 0
+            hipLaunchKernelGGL(k_set_root, dim3(1), dim3(64), 0, s, (int32_t*)d.d_values, d.roots[0]);
+    } else {
+        hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s, fin,
+                           (int32_t*)d.d_values, (int64_t)L.n);
+    }
     NXG_CHECK_LAUNCH();
-    int32_t mx = 0;
-    unsigned long long reached = 0;
+    // the last round's listed chunks join the count; then the BFS outputs
+    // (maximum level, reached edges) in two steps without atomics
+    hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, w.ccount.as<int32_t>(), L.n_tiles,
+                       k > 0 ? streamed : nullptr);
+    NXG_CHECK_LAUNCH();
+    unsigned long long out3[3] = {0, 0, 0};  // streamed, reached, max level
     if (bfs) {
-        w.bfsout.alloc(16, s);
-        NXG_HIP(hipMemsetAsync(w.bfsout.p, 0, 16, s));
-        hipLaunchKernelGGL(k_bfs_final, dim3(grid_for(L.n, 256, 1024)), dim3(256), 0, s, L.n,
-                           w.buf[k & 1].as<int32_t>(), L.outdeg.as<int32_t>(), w.bfsout.as<int32_t>(),
-                           (unsigned long long*)(w.bfsout.as<char>() + 8));
+        unsigned long long* part = streamed + 3;
+        hipLaunchKernelGGL(k_bfs_final, dim3(kFinalBlocks), dim3(256), 0, s, L.n, fin,
+                           L.outdeg.as<int32_t>(), part);
         NXG_CHECK_LAUNCH();
-        NXG_HIP(hipMemcpyAsync(&mx, w.bfsout.p, 4, hipMemcpyDeviceToHost, s));
-        NXG_HIP(hipMemcpyAsync(&reached, w.bfsout.as<char>() + 8, 8, hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_bfs_final_sum, dim3(1), dim3(kFinalBlocks), 0, s, part);
+        NXG_CHECK_LAUNCH();
+        NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(out3), hipMemcpyDeviceToHost, s));
+    } else {
+        NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     }
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
@@ -2384,9 +2721,10 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         st->iterations = std::min(k, last_changed + 1);
         st->converged = fixed ? 1 : 0;
         st->changed_rounds = last_changed;
-        st->max_level = mx;
-        st->reached_edges = (int64_t)reached;
+        st->max_level = (int32_t)out3[2];
+        st->reached_edges = (int64_t)out3[1];
         st->device_ms = ms;
+        st->streamed_chunks = (int64_t)out3[0];
     }
     return fixed ? NXG_OK : NXG_ENOTCONV;
 }

@@ -138,6 +138,9 @@ struct Layout {
     DevBuf perm;           // int32  [n_words] input index of the edge in that word, -1 otherwise
     DevBuf weight;         // float  [n_words] weight of the edge in that word, 0 otherwise
     DevBuf outdeg;         // int32  [n] out-degree in this (possibly reversed) graph
+    DevBuf chunk_rng;      // int4   [n_chunks] {min src, max src, min dst, max dst} of the
+                           // chunk's edges, made by the first BFS/WCC run
+    DevBuf chunk_tile;     // int32  [n_chunks] tile of each chunk (made with chunk_rng)
     std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
     std::vector<int64_t> h_tile_edges;  // edges per tile (host)
     bool has_perm = false, has_weight = false;

@@ -50,3 +50,44 @@ def test_bfs_path_graph(gpu_device):
     lev, st = g.bfs(0)
     assert np.array_equal(lev.cpu().numpy(), np.arange(n))
     assert st["changed_rounds"] == n - 1 and st["max_level"] == n - 1
+
+
+@pytest.mark.parametrize("n,tile,interval,order", [
+    (1000, 16, 128, "dst"), (1000, 32, 256, "src"), (1777, 8, 64, "dst"), (1777, 64, 512, "src")])
+def test_small_tiles_ragged_n(gpu_device, n, tile, interval, order):
+    # activity blocks are as small as the tile when the tile is under a wave;
+    # n is not a multiple of the block size
+    rng = np.random.default_rng(n + tile)
+    m = 6 * n
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=interval, tile=tile,
+                   order=order)
+    deg = np.bincount(src, minlength=n)
+    for r in rmatgen.distinct_vertices(n, 3, n, eligible=deg > 0).tolist():
+        say("bfs n=%d T=%d I=%d %s root=%d" % (n, tile, interval, order, r))
+        ref, rounds, mx = oracle.bfs(n, src, dst, r)
+        lev, st = g.bfs(r)
+        assert np.array_equal(lev.cpu().numpy(), ref)
+        assert st["changed_rounds"] == rounds and st["max_level"] == mx
+    gs = DSSS.build(to_dev(src[: m // 8], gpu_device), to_dev(dst[: m // 8], gpu_device), n,
+                    interval=interval, tile=tile, order=order, symmetrize=True)
+    say("wcc n=%d T=%d I=%d %s" % (n, tile, interval, order))
+    ref, rounds = oracle.wcc(n, src[: m // 8], dst[: m // 8])
+    lab, st = gs.wcc()
+    assert np.array_equal(lab.cpu().numpy(), ref)
+    assert st["changed_rounds"] == rounds
+
+
+@pytest.mark.parametrize("order", ["dst", "src"])
+def test_path_streams_only_the_frontier(gpu_device, order):
+    # a round streams the chunks that hold an edge out of the vertex reached in
+    # the previous round: at most two chunks per round on a path
+    n = 3000
+    src = np.arange(n - 1, dtype=np.int32)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(src + 1, gpu_device), n, interval=128, order=order)
+    lev, st = g.bfs(0)
+    assert np.array_equal(lev.cpu().numpy(), np.arange(n))
+    assert 0 < st["streamed_chunks"] <= 2 * st["iterations"]
+    info = g.info()
+    assert st["streamed_chunks"] < info["n_chunks"] * st["iterations"] // 4
