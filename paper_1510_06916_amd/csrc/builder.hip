@@ -367,11 +367,11 @@ __device__ inline int64_t last_group_at(const int64_t* gword, int64_t g0, int P,
     return lo;
 }
 
-__global__ void k_chunk_rows(const int64_t* __restrict__ tchunk,
-                             const int64_t* __restrict__ twords, int n_tiles,
+// Per chunk: the source interval in effect at its first word, and its tile.
+__global__ void k_chunk_rows(const int64_t* __restrict__ tchunk, int n_tiles,
                              const int64_t* __restrict__ gword, int P, int C,
                              int64_t n_chunks, int32_t* __restrict__ crow,
-                             int32_t* __restrict__ crow_last) {
+                             int32_t* __restrict__ ctile) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
          c += (int64_t)gridDim.x * blockDim.x) {
         // tile owning chunk c: last tau with tchunk[tau] <= c
@@ -385,13 +385,10 @@ __global__ void k_chunk_rows(const int64_t* __restrict__ tchunk,
         }
         const int64_t g0 = (int64_t)lo * P;
         const int64_t first = c * (int64_t)C;
-        // end of the tile's real words (markers + edges, before padding); trailing
-        // empty groups sit exactly there, so searching strictly below it only ever
-        // lands on non-empty groups
-        const int64_t real_end = tchunk[lo] * (int64_t)C + twords[lo];
+        // a chunk's first word precedes the tile's padding, where trailing empty
+        // groups sit, so the search lands on the non-empty group in effect
         crow[c] = (int32_t)(last_group_at(gword, g0, P, first) - g0);
-        int64_t last = min(first + C - 1, real_end - 1);
-        crow_last[c] = (int32_t)(last_group_at(gword, g0, P, last) - g0);
+        ctile[c] = lo;
     }
 }
 
@@ -812,13 +809,13 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
         NXG_CHECK_LAUNCH();
     }
     L.chunk_row.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
-    L.chunk_row_last.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
+    L.chunk_tile.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
     if (L.n_chunks > 0) {
         hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(L.n_chunks)), dim3(256), 0, s,
-                           L.tile_chunk.as<int64_t>(), twords.as<int64_t>(), L.n_tiles,
+                           L.tile_chunk.as<int64_t>(), L.n_tiles,
                            L.group_word.as<int64_t>(), L.P,
                            L.C, L.n_chunks, L.chunk_row.as<int32_t>(),
-                           L.chunk_row_last.as<int32_t>());
+                           L.chunk_tile.as<int32_t>());
         NXG_CHECK_LAUNCH();
     }
     NXG_HIP(hipStreamSynchronize(s));

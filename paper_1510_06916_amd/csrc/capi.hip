@@ -224,9 +224,9 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
         info->max_tile_edges = L.max_tile_edges;
         int64_t bytes = 0;
         for (const Layout* x : {&g->fwd, &g->rev}) {
-            for (const DevBuf* b : {&x->words, &x->chunk_row, &x->chunk_row_last, &x->tile_chunk,
+            for (const DevBuf* b : {&x->words, &x->chunk_row, &x->chunk_tile, &x->tile_chunk,
                                     &x->group_edge, &x->group_word, &x->perm, &x->weight, &x->outdeg,
-                                    &x->chunk_rng, &x->chunk_tile})
+                                    &x->chunk_rng})
                 bytes += (int64_t)b->bytes;
         }
         bytes += (int64_t)(g->new2old.bytes + g->old2new.bytes);

@@ -53,7 +53,6 @@ __device__ inline int lane_id() { return threadIdx.x & 63; }
 struct Geo {
     const uint32_t* words;
     const int32_t* chunk_row;
-    const int32_t* chunk_row_last;
     const Item* items;
     const int32_t* deg;
     int32_t n, I, P, L, T, t, n_tiles, C;
@@ -1099,35 +1098,20 @@ __global__ void k_set_root(int32_t* __restrict__ lev, int32_t root) {
     if (threadIdx.x == 0) lev[root] = 0;
 }
 
-// The tile holding chunk c: the last tau with tchunk[tau] <= c.
-__device__ inline int tile_of_chunk(const int64_t* __restrict__ tchunk, int n_tiles, int64_t c) {
-    int lo = 0, hi = n_tiles;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tchunk[mid] <= c)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // Per chunk, the smallest and largest source and destination (global ids) of
 // its edges, {slo, shi, dlo, dhi} (a chunk without edges gets
-// {INT32_MAX, -1, INT32_MAX, -1}), and its tile. One wave per chunk: lane l reads words
+// {INT32_MAX, -1, INT32_MAX, -1}). One wave per chunk: lane l reads words
 // l, l + 64, ... and follows the interval markers as the iteration does.
 __global__ __launch_bounds__(256) void k_chunk_ranges(const uint32_t* __restrict__ words,
                                                       const int32_t* __restrict__ crow,
-                                                      const int64_t* __restrict__ tchunk, int n_tiles,
+                                                      const int32_t* __restrict__ ctile,
                                                       int64_t n_chunks, int C, int I, int L, int t,
-                                                      int sshift, int dshift, int4* __restrict__ out,
-                                                      int32_t* __restrict__ ctile) {
+                                                      int sshift, int dshift, int4* __restrict__ out) {
     const int lane = lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= n_chunks) return;  // uniform over the wave
-    const int tile = tile_of_chunk(tchunk, n_tiles, c);
-    const int64_t tb = (int64_t)tile << t;
+    const int64_t tb = (int64_t)ctile[c] << t;
     const uint32_t lmask = (1u << L) - 1u, tmask = (1u << t) - 1u;
     uint32_t row = (uint32_t)crow[c];
     int32_t slo = INT32_MAX, shi = -1, dlo = INT32_MAX, dhi = -1;
@@ -1157,10 +1141,7 @@ __global__ __launch_bounds__(256) void k_chunk_ranges(const uint32_t* __restrict
         dlo = min(dlo, __shfl_xor(dlo, o));
         dhi = max(dhi, __shfl_xor(dhi, o));
     }
-    if (lane == 0) {
-        out[c] = make_int4(slo, shi, dlo, dhi);
-        ctile[c] = tile;
-    }
+    if (lane == 0) out[c] = make_int4(slo, shi, dlo, dhi);
 }
 
 // Block activity prefix counts, per segment of `seg` blocks (seg a multiple
@@ -1936,6 +1917,25 @@ struct Workspace {
     DevBuf mtele, mvals, mseeds, mgx, mxs;  // caller data in internal ids (relabeled builds)
 };
 
+// Two timing events, released on every exit path (an error throws).
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    Events() {
+        NXG_HIP(hipEventCreate(&a));
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+            fail(NXG_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    Events(const Events&) = delete;
+    Events& operator=(const Events&) = delete;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 // What a multi-graph handle keeps between runs: per-graph workspaces, the
 // descriptor and item arrays (device and host).
 struct MultiCache : Cached {
@@ -2112,7 +2112,6 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     Geo g;
     g.words = L.words.as<uint32_t>();
     g.chunk_row = L.chunk_row.as<int32_t>();
-    g.chunk_row_last = L.chunk_row_last.as<int32_t>();
     g.items = p.items.as<Item>();
     g.deg = L.outdeg.as<int32_t>();
     g.n = L.n;
@@ -2273,10 +2272,12 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         e = n.release();
         g->cached.push_back(e);
     }
-    hipEvent_t e0, e1;
+    std::unique_ptr<Events> ev;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st) {
-        NXG_HIP(hipEventCreate(&e0));
-        NXG_HIP(hipEventCreate(&e1));
+        ev.reset(new Events());
+        e0 = ev->a;
+        e1 = ev->b;
         NXG_HIP(hipEventRecord(e0, s));
     }
     NXG_HIP(hipGraphLaunch(e->exec, s));
@@ -2288,8 +2289,6 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         NXG_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
         NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-        NXG_HIP(hipEventDestroy(e0));
-        NXG_HIP(hipEventDestroy(e1));
         memset(st, 0, sizeof(*st));
         st->iterations = d.max_iters;
         st->residual = hs[4 * (d.max_iters - 1) + 1];
@@ -2329,9 +2328,8 @@ nxg_status run_scatter(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, w.part.as<double>(), nb, w.stats.as<double>());
     NXG_CHECK_LAUNCH();
     const int sgrid = grid_for(L.n_chunks * 64, 256, 16384);
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     int k = 0, done_h = 0;
     for (; k < max_iters; ++k) {
@@ -2377,8 +2375,6 @@ nxg_status run_scatter(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     const bool conv = d.tol > 0 && done_h;
     if (st) {
         memset(st, 0, sizeof(*st));
@@ -2448,9 +2444,8 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     Geo geo = make_geo(L, *p, w, ab);
     const size_t lds = iter_lds(geo, L, ab);
     const int n_items = (int)p->h_items.size();
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     int k = 0;
     int done_h = 0;
@@ -2519,8 +2514,6 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         }
         if (d.tol > 0 && conv_at < 0) rc = NXG_ENOTCONV;
     }
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     if (!st && d.tol <= 0) {
         // buffers are released through the allocator on the same stream, so
         // stream-ordered allocators see the frees after the kernels
@@ -2529,21 +2522,18 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     return rc;
 }
 
-// The chunk ranges (and tiles) the compaction tests, made once per layout.
+// The chunk ranges the compaction tests, made once per layout.
 void ensure_chunk_ranges(Layout& L, hipStream_t s) {
     if (L.chunk_rng.p || L.n_chunks == 0) return;
-    DevBuf r, ct;
+    DevBuf r;
     r.alloc(sizeof(int4) * (size_t)L.n_chunks, s);
-    ct.alloc(sizeof(int32_t) * (size_t)L.n_chunks, s);
     const int sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
     const int dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
     hipLaunchKernelGGL(k_chunk_ranges, dim3((unsigned)((L.n_chunks + 3) / 4)), dim3(256), 0, s,
-                       L.words.as<uint32_t>(), L.chunk_row.as<int32_t>(), L.tile_chunk.as<int64_t>(),
-                       L.n_tiles, L.n_chunks, L.C, L.I, L.L, L.t, sshift, dshift, r.as<int4>(),
-                       ct.as<int32_t>());
+                       L.words.as<uint32_t>(), L.chunk_row.as<int32_t>(), L.chunk_tile.as<int32_t>(),
+                       L.n_chunks, L.C, L.I, L.L, L.t, sshift, dshift, r.as<int4>());
     NXG_CHECK_LAUNCH();
     L.chunk_rng = std::move(r);
-    L.chunk_tile = std::move(ct);
 }
 
 // What a handle keeps between BFS (or WCC) runs: the workspace, sized for the
@@ -2622,9 +2612,8 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     int32_t* tot1 = bfs ? tot0 + nseg : nullptr;
     unsigned long long* streamed = w.bfsout.as<unsigned long long>();
     const int max_iters = d.max_iters;
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     // the root is mapped to its internal id on the device; a root dropped by
     // degreeing (no edges) maps to -1 and reaches nothing but itself
@@ -2714,8 +2703,6 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     if (st) {
         memset(st, 0, sizeof(*st));
         st->iterations = std::min(k, last_changed + 1);
@@ -2826,9 +2813,8 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                            ctl);
         NXG_CHECK_LAUNCH();
     };
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     const int block = d.tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
     int k = 0, done_h = 0;
@@ -2873,8 +2859,6 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if (conv_at >= 0) iters = conv_at + 1;
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     if (st) {
         memset(st, 0, sizeof(*st));
         st->iterations = iters;
@@ -3013,9 +2997,8 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         attr = lds;
     }
     const MultiGraph* ddesc = c->ddesc.as<MultiGraph>();
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     hipLaunchKernelGGL(k_multi_init, dim3(G * kMultiBlocks), dim3(256), 0, s, ddesc, c->dpart.as<double>());
     NXG_CHECK_LAUNCH();
@@ -3045,8 +3028,6 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     if (st) {
         double worst = 0.0;
         for (double r : res) worst = std::max(worst, r);
@@ -3102,9 +3083,8 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     geo.deg = F.outdeg.as<int32_t>();  // dangling set of the forward graph
     const size_t lds = iter_lds(geo, R, 8);
     const int n_items = (int)p->h_items.size();
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     const double tol = d.tol > 0 ? d.tol : 0.0;
     const int block = tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
@@ -3184,8 +3164,6 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     if (conv_at >= 0) iters = conv_at + 1;
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     if (st) {
         memset(st, 0, sizeof(*st));
         st->iterations = iters;
@@ -3242,9 +3220,8 @@ nxg_status copy_probe(int64_t bytes, int reps, hipStream_t s, double* gbps) {
     const int grid = cus * 16;
     hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, a.as<u32x4>(), b.as<u32x4>(), n);
     NXG_CHECK_LAUNCH();
-    hipEvent_t e0, e1;
-    NXG_HIP(hipEventCreate(&e0));
-    NXG_HIP(hipEventCreate(&e1));
+    Events ev;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
     for (int r = 0; r < reps; ++r)
         hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, a.as<u32x4>(), b.as<u32x4>(), n);
@@ -3253,8 +3230,6 @@ nxg_status copy_probe(int64_t bytes, int reps, hipStream_t s, double* gbps) {
     NXG_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    NXG_HIP(hipEventDestroy(e0));
-    NXG_HIP(hipEventDestroy(e1));
     *gbps = 2.0 * n * 16 * reps / (ms * 1e-3) / 1e9;
     return NXG_OK;
 }

@@ -95,7 +95,7 @@ struct DevBuf {
 // preceded by a marker word 0x80000000 | i. A tile's words are padded with
 // 0xFFFFFFFF to a multiple of the chunk size C, so every chunk belongs to one
 // tile; chunk_row[c] is the source interval in effect at the chunk's first
-// word and chunk_row_last[c] the one in effect at its last edge.
+// word and chunk_tile[c] the chunk's tile.
 // ---------------------------------------------------------------------------
 // Pinned host memory (hipHostMalloc), freed with the owner.
 struct HostBuf {
@@ -131,7 +131,7 @@ struct Layout {
     int64_t m = 0, n_chunks = 0, n_words = 0, max_tile_edges = 0;
     DevBuf words;          // uint32 [n_words]
     DevBuf chunk_row;      // int32  [n_chunks]
-    DevBuf chunk_row_last; // int32  [n_chunks]
+    DevBuf chunk_tile;     // int32  [n_chunks]
     DevBuf tile_chunk;     // int64  [n_tiles + 1] chunk index of each tile's first chunk
     DevBuf group_edge;     // int64  [n_tiles*P + 1] stream-order index of each group's first edge
     DevBuf group_word;     // int64  [n_tiles*P + 1] word position of each group's marker
@@ -140,7 +140,6 @@ struct Layout {
     DevBuf outdeg;         // int32  [n] out-degree in this (possibly reversed) graph
     DevBuf chunk_rng;      // int4   [n_chunks] {min src, max src, min dst, max dst} of the
                            // chunk's edges, made by the first BFS/WCC run
-    DevBuf chunk_tile;     // int32  [n_chunks] tile of each chunk (made with chunk_rng)
     std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
     std::vector<int64_t> h_tile_edges;  // edges per tile (host)
     bool has_perm = false, has_weight = false;

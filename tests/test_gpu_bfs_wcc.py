@@ -91,3 +91,20 @@ def test_path_streams_only_the_frontier(gpu_device, order):
     assert 0 < st["streamed_chunks"] <= 2 * st["iterations"]
     info = g.info()
     assert st["streamed_chunks"] < info["n_chunks"] * st["iterations"] // 4
+
+
+@pytest.mark.parametrize("order", ["dst", "src"])
+def test_edgeless_graphs(gpu_device, order):
+    # no chunks at all: every round streams nothing
+    import torch
+    e = torch.zeros(0, dtype=torch.int32, device=gpu_device)
+    g = DSSS.build(e, e, 10, interval=4, order=order)
+    lev, st = g.bfs(3)
+    ref = np.full(10, oracle.INF, dtype=np.int64)
+    ref[3] = 0
+    assert np.array_equal(lev.cpu().numpy(), ref)
+    assert st["changed_rounds"] == 0 and st["max_level"] == 0 and st["streamed_chunks"] == 0
+    gs = DSSS.build(e, e, 10, interval=4, order=order, symmetrize=True)
+    lab, st = gs.wcc()
+    assert np.array_equal(lab.cpu().numpy(), np.arange(10))
+    assert st["changed_rounds"] == 0
