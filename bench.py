@@ -53,8 +53,8 @@ def measured_traffic(cfg):
     sha = kernel_sha()
     for t in entries:
         if t.get("kernel_sha") == sha and all(
-                t["config"].get(k) == cfg.get(k)
-                for k in ("interval", "tile", "chunk", "piece_chunks", "order", "relabel")):
+                t["config"].get(k, False if k == "pairs" else None) == cfg.get(k, False if k == "pairs" else None)
+                for k in ("interval", "tile", "chunk", "piece_chunks", "order", "relabel", "pairs")):
             return t.get("bytes_per_iter")
     return None
 
@@ -94,7 +94,7 @@ def bench_pagerank(args, dev):
     if args.interval or args.tile or args.chunk:
         best = {"interval": args.interval, "tile": args.tile, "chunk": args.chunk,
                 "piece_chunks": args.piece, "order": ("dst", "src").index(args.order),
-                "relabel": int(args.relabel), "candidates": 0}
+                "relabel": int(args.relabel), "pairs": int(args.pairs), "candidates": 0}
     else:
         t0 = time.perf_counter()
         os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "tune_cache.txt"))
@@ -103,8 +103,9 @@ def bench_pagerank(args, dev):
         log("tuned in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
     t0 = time.perf_counter()
     order = ("dst", "src")[best["order"]]
+    pairs = bool(best.get("pairs", 0))
     g = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"],
-                   chunk=best["chunk"], order=order, relabel=bool(best["relabel"]))
+                   chunk=best["chunk"], order=order, relabel=bool(best["relabel"]), pairs=pairs)
     torch.cuda.synchronize()
     inf = g.info()
     log("built DSSS in %.2fs: %s" % (time.perf_counter() - t0, json.dumps(inf)))
@@ -165,7 +166,7 @@ def bench_pagerank(args, dev):
     log("copy probe: %.0f GB/s" % copy_gbs)
     traffic = measured_traffic({"interval": inf["interval"], "tile": inf["tile"], "chunk": inf["chunk"],
                                 "piece_chunks": piece, "order": order,
-                                "relabel": bool(best["relabel"])})
+                                "relabel": bool(best["relabel"]), "pairs": pairs})
     res = {
         "metric": "PageRank GTEPS per iteration (R-MAT scale %d, ef %d)" % (args.scale, args.ef),
         "value": m / (ms_step * 1e-3) / 1e9,
@@ -176,7 +177,8 @@ def bench_pagerank(args, dev):
         "config": {"workload": "pagerank-iteration rmat-s%d-ef%d" % (args.scale, args.ef),
                    "n": n, "m": m, "interval": inf["interval"], "P": inf["P"],
                    "tile": inf["tile"], "chunk": inf["chunk"], "piece_chunks": piece,
-                   "order": order, "relabel": bool(best["relabel"]), "damping": 0.85,
+                   "order": order, "relabel": bool(best["relabel"]), "pairs": pairs,
+                   "words": inf["n_words"], "damping": 0.85,
                    "tuned_candidates": best["candidates"],
                    "dst_sorted_natural_ids_ms_per_step": dsss_ms,
                    "coarse_scatter_ms_per_step": scatter_ms},
@@ -463,6 +465,7 @@ def main():
     ap.add_argument("--piece", type=int, default=0, help="chunks per work item (0: automatic)")
     ap.add_argument("--order", default="src", choices=["dst", "src"])
     ap.add_argument("--relabel", type=int, default=1, help="with explicit layout flags: 1 = relabel")
+    ap.add_argument("--pairs", type=int, default=0, help="with explicit layout flags: 1 = pair layout")
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true",

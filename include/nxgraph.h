@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 6
+#define NXG_ABI_VERSION 7
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -123,6 +123,24 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                                      nxg_multi_build; nxg_dsss_export and
                                      nxg_dsss_set_weights refuse such a handle. */
 
+#define NXG_BUILD_PAIRS 0x100u    /* source-order sub-shards (NXG_ORDER_SRC) with the
+                                     edges of one source into one destination tile
+                                     packed two to a word: a header word names the
+                                     source, then each pair word holds two
+                                     destinations (one gather serves both); an
+                                     unpaired edge keeps its plain word. Fewer words
+                                     to stream than one per edge when sources have
+                                     several edges per tile. Needs T <= 16384 and
+                                     ceil(log2 I) + log2 T <= 29. Plain PageRank
+                                     only (F32 or F64, batch 1, no weights, no
+                                     NXG_RUN_SCATTER); BFS, WCC, batched and
+                                     weighted runs, the adjoint and nxg_dsss_export
+                                     refuse such a handle. Not combinable with
+                                     NXG_BUILD_KEEP_PERM, NXG_BUILD_TRANSPOSE,
+                                     NXG_BUILD_SYMMETRIZE, NXG_BUILD_SCATTER or
+                                     NXG_BUILD_HOST_STREAM, nor with weights, nor
+                                     for nxg_multi_build. */
+
 /* Order of the edges inside one sub-shard. */
 #define NXG_ORDER_DST 0 /* destination, then source: the DSSS order of Sec. III-A */
 #define NXG_ORDER_SRC 1 /* source, then destination: the source-sorted sub-shard
@@ -174,6 +192,7 @@ typedef struct nxg_dsss_info {
     int32_t order;       /* NXG_ORDER_* */
     int32_t relabeled;   /* built with NXG_BUILD_RELABEL */
     int32_t n_kept;      /* vertices of the stored graph: n, or fewer with NXG_BUILD_DEGREE */
+    int32_t pairs;       /* built with NXG_BUILD_PAIRS */
 } nxg_dsss_info;
 
 nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info);
@@ -286,6 +305,7 @@ typedef struct nxg_tune_result {
     double ms_per_iter;    /* measured milliseconds per iteration */
     int32_t candidates;    /* candidates timed (0 when served from the cache) */
     int32_t relabel;       /* 1 if the best layout uses NXG_BUILD_RELABEL */
+    int32_t pairs;         /* 1 if the best layout uses NXG_BUILD_PAIRS */
 } nxg_tune_result;
 
 /* Times captured PageRank iterations (NXG_RUN_CAPTURE) of the graph in desc

@@ -74,7 +74,7 @@ def copy_probe(nbytes=1 << 30, reps=10):
 
 def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
     """Times candidate layouts for PageRank on this graph; returns a dict with
-    interval, tile, chunk, order (0 dst, 1 src), relabel, piece_chunks,
+    interval, tile, chunk, order (0 dst, 1 src), relabel, pairs, piece_chunks,
     ms_per_iter, candidates."""
     install_torch_allocator()
     src = _dev_i32(src, "src")
@@ -106,13 +106,15 @@ class DSSS:
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
               value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
               order="dst", relabel=False, scatter=False, degree=False, host_stream=False,
-              stream=None):
+              pairs=False, stream=None):
         """scatter=True builds the coarse-grained source-sorted layout
         (NXG_BUILD_SCATTER) that only pagerank(..., scatter=True) runs.
         degree=True drops the ids that appear in no edge (NXG_BUILD_DEGREE);
         vectors stay indexed by the caller's n ids. host_stream=True keeps the
         edge stream in pinned host memory and streams it every iteration
-        (NXG_BUILD_HOST_STREAM; PageRank only)."""
+        (NXG_BUILD_HOST_STREAM; PageRank only). pairs=True (with order="src")
+        packs two destinations of one source per word (NXG_BUILD_PAIRS; plain
+        PageRank only)."""
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -133,7 +135,8 @@ class DSSS:
                  (_lib.NXG_BUILD_RELABEL if relabel else 0) |
                  (_lib.NXG_BUILD_SCATTER if scatter else 0) |
                  (_lib.NXG_BUILD_DEGREE if degree else 0) |
-                 (_lib.NXG_BUILD_HOST_STREAM if host_stream else 0))
+                 (_lib.NXG_BUILD_HOST_STREAM if host_stream else 0) |
+                 (_lib.NXG_BUILD_PAIRS if pairs else 0))
         d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,

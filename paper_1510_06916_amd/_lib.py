@@ -17,6 +17,7 @@ NXG_BUILD_RELABEL = 0x10
 NXG_BUILD_SCATTER = 0x20
 NXG_BUILD_DEGREE = 0x40
 NXG_BUILD_HOST_STREAM = 0x80
+NXG_BUILD_PAIRS = 0x100
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
@@ -43,7 +44,7 @@ class DsssInfo(ctypes.Structure):
                 ("max_tile_edges", ctypes.c_int64), ("has_perm", ctypes.c_int32),
                 ("has_weights", ctypes.c_int32), ("has_transpose", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("relabeled", ctypes.c_int32),
-                ("n_kept", ctypes.c_int32)]
+                ("n_kept", ctypes.c_int32), ("pairs", ctypes.c_int32)]
 
 
 class RunDesc(ctypes.Structure):
@@ -76,7 +77,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("interval", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("piece_chunks", ctypes.c_int32),
                 ("ms_per_iter", ctypes.c_double), ("candidates", ctypes.c_int32),
-                ("relabel", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("pairs", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -17,6 +17,8 @@ constexpr int kRsBlock = 256;  // threads of the radix-sort kernels (4 wavefront
 constexpr int kRsItems = 8;    // keys per thread per step
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 constexpr uint32_t kMarker = 0x80000000u;
+constexpr uint32_t kHeader = 0x40000000u;  // pair layout: names the run's source
+constexpr uint32_t kPairW = 0x20000000u;   // pair layout: two destinations of that source
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
@@ -276,7 +278,17 @@ __global__ void k_group_bounds(const uint64_t* __restrict__ keys, int64_t m, int
 
 // One block per tile: word offsets of the tile's groups (relative to the
 // tile), the tile's word count and its edge count.
+// With pw (pair layout) a group's words are the marker plus what its edges
+// emit, pw[end] - pw[begin]; otherwise one word per edge plus the marker.
+__device__ inline int64_t group_words(const int64_t* __restrict__ gbeg,
+                                      const int64_t* __restrict__ pw, int64_t g) {
+    const int64_t c = gbeg[g + 1] - gbeg[g];
+    if (!c) return 0;
+    return 1 + (pw ? pw[gbeg[g + 1]] - pw[gbeg[g]] : c);
+}
+
 __global__ __launch_bounds__(1024) void k_tile_words(const int64_t* __restrict__ gbeg, int P,
+                                                     const int64_t* __restrict__ pw,
                                                      int64_t* __restrict__ gword,
                                                      int64_t* __restrict__ tile_words,
                                                      int64_t* __restrict__ tile_edges) {
@@ -286,10 +298,7 @@ __global__ __launch_bounds__(1024) void k_tile_words(const int64_t* __restrict__
     const int per = (P + 1023) / 1024;
     const int a = threadIdx.x * per, b = min(P, a + per);
     int64_t s = 0;
-    for (int i = a; i < b; ++i) {
-        int64_t c = gbeg[g0 + i + 1] - gbeg[g0 + i];
-        s += c ? c + 1 : 0;
-    }
+    for (int i = a; i < b; ++i) s += group_words(gbeg, pw, g0 + i);
     part[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -300,9 +309,8 @@ __global__ __launch_bounds__(1024) void k_tile_words(const int64_t* __restrict__
     }
     int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
     for (int i = a; i < b; ++i) {
-        int64_t c = gbeg[g0 + i + 1] - gbeg[g0 + i];
         gword[g0 + i] = run;
-        run += c ? c + 1 : 0;
+        run += group_words(gbeg, pw, g0 + i);
     }
     if (threadIdx.x == 1023) {
         tile_words[tau] = part[1023];
@@ -351,6 +359,125 @@ __global__ void k_markers(const int64_t* __restrict__ gbeg, const int64_t* __res
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G;
          g += (int64_t)gridDim.x * blockDim.x) {
         if (gbeg[g + 1] > gbeg[g]) words[gword[g]] = kMarker | (uint32_t)(g % P);
+    }
+}
+
+// ---- pair layout (NXG_BUILD_PAIRS, source order) ---------------------------
+// A run is the edges of one source into one tile: equal key >> t, consecutive
+// in the sorted keys. An edge at an even index pairs with the next edge when
+// that one is of the same run (one word: kPairW | dst | dst' << 14), and the
+// run's first pair is preceded by a header word (kHeader | source field). An
+// edge neither pairing nor paired keeps its plain word. Every flag is decided
+// from the edge's neighbours, so the words of an edge are known locally.
+struct PairFlags {
+    bool hdr, pair, plain;
+};
+__device__ inline PairFlags pair_flags(const uint64_t* __restrict__ keys, int64_t m, int t, int64_t e) {
+    const uint64_t r = keys[e] >> t;
+    const bool sn = e + 1 < m && (keys[e + 1] >> t) == r;
+    const bool sp = e > 0 && (keys[e - 1] >> t) == r;
+    const bool sp2 = e > 1 && (keys[e - 2] >> t) == r;
+    const bool even = (e & 1) == 0;
+    PairFlags f;
+    f.pair = even && sn;
+    f.plain = even ? !sn : !sp;
+    f.hdr = f.pair && (!sp || !sp2);
+    return f;
+}
+constexpr int kPB = 4096;  // sorted edges per block of the word-count scan
+
+// Words emitted by each block of kPB sorted edges.
+__global__ __launch_bounds__(256) void k_pair_count(const uint64_t* __restrict__ keys, int64_t m, int t,
+                                                    int64_t* __restrict__ bsum) {
+    __shared__ int64_t red[4];
+    int64_t s = 0;
+    for (int i = threadIdx.x; i < kPB; i += 256) {
+        const int64_t e = (int64_t)blockIdx.x * kPB + i;
+        if (e < m) {
+            const PairFlags f = pair_flags(keys, m, t, e);
+            s += (int)f.hdr + (int)f.pair + (int)f.plain;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// pw[e] = words emitted by sorted edges [0, e), for e in [0, m]; boff holds the
+// blocks' exclusive offsets (boff[nblocks] = total). Thread j of a block takes
+// 16 consecutive edges.
+__global__ __launch_bounds__(256) void k_pair_prefix(const uint64_t* __restrict__ keys, int64_t m, int t,
+                                                     const int64_t* __restrict__ boff,
+                                                     int64_t nblocks, int64_t* __restrict__ pw) {
+    __shared__ int64_t wsum[4];
+    const int64_t e0 = (int64_t)blockIdx.x * kPB + threadIdx.x * 16;
+    int c[16];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t e = e0 + k;
+        c[k] = 0;
+        if (e < m) {
+            const PairFlags f = pair_flags(keys, m, t, e);
+            c[k] = (int)f.hdr + (int)f.pair + (int)f.plain;
+        }
+        s += c[k];
+    }
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int64_t v = s;  // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t a = __shfl_up(v, o);
+        if (lane >= o) v += a;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    int64_t run = boff[blockIdx.x] + v - s;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t e = e0 + k;
+        if (e < m) pw[e] = run;
+        run += c[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) pw[m] = boff[nblocks];
+}
+
+// Writes the words of the pair layout (markers and padding come separately).
+__global__ void k_pair_words(const uint64_t* __restrict__ keys, int64_t m, int sh, int t,
+                             const int64_t* __restrict__ gbeg, const int64_t* __restrict__ gword,
+                             const int64_t* __restrict__ pw, uint32_t* __restrict__ words) {
+    const uint64_t low_mask = (1ull << sh) - 1ull;
+    const uint32_t tmask = (1u << t) - 1u;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[e];
+        const int64_t g = (int64_t)(k >> sh);
+        int64_t pos = gword[g] + 1 + (pw[e] - pw[gbeg[g]]);
+        const uint32_t low = (uint32_t)(k & low_mask);
+        const PairFlags f = pair_flags(keys, m, t, e);
+        if (f.hdr) words[pos++] = kHeader | (low >> t);
+        if (f.pair)
+            words[pos] = kPairW | (low & tmask) | (((uint32_t)keys[e + 1] & tmask) << 14);
+        else if (f.plain)
+            words[pos] = low;
+    }
+}
+
+// Pair layout: the source field named by the header in effect at each chunk's
+// first word, when that word is a pair (its run's header lies before the
+// chunk); 0 otherwise. The walk back only crosses pairs of the same run.
+__global__ void k_chunk_src(const uint32_t* __restrict__ words, int64_t n_chunks, int C,
+                            int32_t* __restrict__ csrc) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q = c * (int64_t)C;
+        int32_t v = 0;
+        if ((words[q] >> 29) == 1u) {
+            while (q > 0 && (words[q] >> 29) == 1u) --q;
+            if ((words[q] >> 30) == 1u) v = (int32_t)(words[q] & ~kHeader);
+        }
+        csrc[c] = v;
     }
 }
 
@@ -687,6 +814,14 @@ void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     }
     if (C < 256 || C > 65536 || (C & (C - 1))) fail(NXG_EINVAL, "chunk must be a power of two in [256, 65536]");
     L.C = (int32_t)C;
+    if (d.flags & NXG_BUILD_PAIRS) {
+        // two destination fields in a word under three flag bits, and plain
+        // words clear of the flag bits
+        if (L.order != NXG_ORDER_SRC) fail(NXG_EINVAL, "NXG_BUILD_PAIRS needs NXG_ORDER_SRC");
+        if (L.t > 14) fail(NXG_EINVAL, "NXG_BUILD_PAIRS needs a tile of at most 16384 vertices");
+        if (L.L + L.t > 29) fail(NXG_EINVAL, "NXG_BUILD_PAIRS needs L + t <= 29 (smaller interval)");
+        L.pairs = true;
+    }
 }
 
 void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& L) {
@@ -749,12 +884,32 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
     hipLaunchKernelGGL(k_group_bounds, dim3(grid_for(G + 1)), dim3(256), 0, s, keys, m, G, sh,
                        L.group_edge.as<int64_t>());
     NXG_CHECK_LAUNCH();
+    // pair layout: words emitted before each sorted edge
+    DevBuf pw;
+    if (L.pairs) {
+        const int64_t nbk = std::max<int64_t>(1, (m + kPB - 1) / kPB);
+        DevBuf boff;
+        boff.alloc(sizeof(int64_t) * (nbk + 1), s);
+        pw.alloc(sizeof(int64_t) * (m + 1), s);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_pair_count, dim3((unsigned)nbk), dim3(256), 0, s, keys, m, L.t,
+                               boff.as<int64_t>());
+            NXG_CHECK_LAUNCH();
+        } else {
+            NXG_HIP(hipMemsetAsync(boff.p, 0, sizeof(int64_t) * (nbk + 1), s));
+        }
+        hipLaunchKernelGGL(k_scan_i64_inplace_excl, dim3(1), dim3(1024), 0, s, boff.as<int64_t>(), nbk);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_pair_prefix, dim3((unsigned)nbk), dim3(256), 0, s, keys, m, L.t,
+                           boff.as<int64_t>(), nbk, pw.as<int64_t>());
+        NXG_CHECK_LAUNCH();
+    }
     DevBuf twords, tedges;
     twords.alloc(sizeof(int64_t) * L.n_tiles, s);
     tedges.alloc(sizeof(int64_t) * L.n_tiles, s);
     hipLaunchKernelGGL(k_tile_words, dim3(L.n_tiles), dim3(1024), 0, s,
-                       L.group_edge.as<int64_t>(), L.P, L.group_word.as<int64_t>(),
-                       twords.as<int64_t>(), tedges.as<int64_t>());
+                       L.group_edge.as<int64_t>(), L.P, L.pairs ? pw.as<int64_t>() : nullptr,
+                       L.group_word.as<int64_t>(), twords.as<int64_t>(), tedges.as<int64_t>());
     NXG_CHECK_LAUNCH();
     std::vector<int64_t> hw(L.n_tiles), he(L.n_tiles);
     NXG_HIP(hipMemcpyAsync(hw.data(), twords.p, sizeof(int64_t) * L.n_tiles, hipMemcpyDeviceToHost, s));
@@ -798,10 +953,15 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
         L.has_weight = true;
     }
     if (m > 0) {
-        hipLaunchKernelGGL(k_scatter_words, dim3(grid_for(m)), dim3(256), 0, s, keys, vals, m, sh,
-                           L.P, L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(),
-                           L.words.as<uint32_t>(), want_perm ? L.perm.as<int32_t>() : nullptr,
-                           d.d_weight, want_w ? L.weight.as<float>() : nullptr);
+        if (L.pairs)
+            hipLaunchKernelGGL(k_pair_words, dim3(grid_for(m)), dim3(256), 0, s, keys, m, sh, L.t,
+                               L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(), pw.as<int64_t>(),
+                               L.words.as<uint32_t>());
+        else
+            hipLaunchKernelGGL(k_scatter_words, dim3(grid_for(m)), dim3(256), 0, s, keys, vals, m, sh,
+                               L.P, L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(),
+                               L.words.as<uint32_t>(), want_perm ? L.perm.as<int32_t>() : nullptr,
+                               d.d_weight, want_w ? L.weight.as<float>() : nullptr);
         NXG_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_markers, dim3(grid_for(G)), dim3(256), 0, s,
                            L.group_edge.as<int64_t>(), L.group_word.as<int64_t>(), G, L.P,
@@ -817,6 +977,14 @@ void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout&
                            L.C, L.n_chunks, L.chunk_row.as<int32_t>(),
                            L.chunk_tile.as<int32_t>());
         NXG_CHECK_LAUNCH();
+    }
+    if (L.pairs) {
+        L.chunk_src.alloc(sizeof(int32_t) * std::max<int64_t>(L.n_chunks, 1), s);
+        if (L.n_chunks > 0) {
+            hipLaunchKernelGGL(k_chunk_src, dim3(grid_for(L.n_chunks)), dim3(256), 0, s,
+                               L.words.as<uint32_t>(), L.n_chunks, L.C, L.chunk_src.as<int32_t>());
+            NXG_CHECK_LAUNCH();
+        }
     }
     NXG_HIP(hipStreamSynchronize(s));
 }

@@ -97,9 +97,10 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
         *out = nullptr;
         if (count < 1 || !descs) fail(NXG_EINVAL, "count must be >= 1 and descs non-NULL");
         for (int32_t i = 0; i < count; ++i)
-            if (descs[i].flags & (NXG_BUILD_DEGREE | NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM))
+            if (descs[i].flags & (NXG_BUILD_DEGREE | NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM |
+                                  NXG_BUILD_PAIRS))
                 fail(NXG_EUNSUPPORTED, "nxg_multi_build takes none of NXG_BUILD_DEGREE, NXG_BUILD_SCATTER, "
-                                       "NXG_BUILD_HOST_STREAM");
+                                       "NXG_BUILD_HOST_STREAM, NXG_BUILD_PAIRS");
         nxg_multi* mg = new nxg_multi();
         try {
             for (int32_t i = 0; i < count; ++i)
@@ -141,8 +142,13 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
                                   NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER |
-                                  NXG_BUILD_DEGREE | NXG_BUILD_HOST_STREAM))
+                                  NXG_BUILD_DEGREE | NXG_BUILD_HOST_STREAM | NXG_BUILD_PAIRS))
             fail(NXG_EINVAL, "unknown build flag");
+        if ((d.flags & NXG_BUILD_PAIRS) &&
+            (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
+                                       NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM))))
+            fail(NXG_EINVAL, "PAIRS cannot be combined with weights, KEEP_PERM, TRANSPOSE, SYMMETRIZE, "
+                             "SCATTER or HOST_STREAM");
         if ((d.flags & NXG_BUILD_HOST_STREAM) && (d.flags & (NXG_BUILD_TRANSPOSE | NXG_BUILD_SCATTER)))
             fail(NXG_EINVAL, "HOST_STREAM cannot be combined with TRANSPOSE or SCATTER");
         if ((d.flags & NXG_BUILD_SCATTER) &&
@@ -226,7 +232,7 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
         for (const Layout* x : {&g->fwd, &g->rev}) {
             for (const DevBuf* b : {&x->words, &x->chunk_row, &x->chunk_tile, &x->tile_chunk,
                                     &x->group_edge, &x->group_word, &x->perm, &x->weight, &x->outdeg,
-                                    &x->chunk_rng})
+                                    &x->chunk_rng, &x->chunk_src})
                 bytes += (int64_t)b->bytes;
         }
         bytes += (int64_t)(g->new2old.bytes + g->old2new.bytes);
@@ -236,6 +242,7 @@ nxg_status nxg_dsss_info_get(const nxg_dsss* g, nxg_dsss_info* info) {
         info->has_weights = L.has_weight;
         info->has_transpose = g->has_rev;
         info->order = L.order;
+        info->pairs = L.pairs ? 1 : 0;
         return NXG_OK;
     });
 }
@@ -258,6 +265,7 @@ nxg_status nxg_dsss_export(const nxg_dsss* g, int transposed, int64_t* d_offsets
         if (!g) fail(NXG_EINVAL, "handle is NULL");
         if (transposed && !g->has_rev) fail(NXG_EINVAL, "handle has no transposed graph");
         if (!transposed && g->fwd.host_stream) fail(NXG_EINVAL, "the edge stream is in host memory (HOST_STREAM)");
+        if (!transposed && g->fwd.pairs) fail(NXG_EINVAL, "a PAIRS layout cannot be exported");
         export_layout(transposed ? g->rev : g->fwd, d_offsets, d_src, d_dst, d_perm,
                       (hipStream_t)stream);
         return NXG_OK;

@@ -16,6 +16,7 @@
 // fixed order, so they are independent of scheduling.
 #include <algorithm>
 #include <memory>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 
@@ -53,6 +54,7 @@ __device__ inline int lane_id() { return threadIdx.x & 63; }
 struct Geo {
     const uint32_t* words;
     const int32_t* chunk_row;
+    const int32_t* chunk_src;  // pair layout: header source at each chunk's first word
     const Item* items;
     const int32_t* deg;
     int32_t n, I, P, L, T, t, n_tiles, C;
@@ -127,6 +129,19 @@ struct ProgPR {
         if (xout) xout[v] = dg ? (V)((double)cur[v] * dg) : cur[v];
     }
 };
+
+// Plain PageRank over the pair layout (NXG_BUILD_PAIRS): the same program; the
+// iteration decodes header and pair words as well.
+template <typename V>
+struct ProgPRP : ProgPR<V> {
+    static constexpr bool kPairs = true;
+};
+
+// Whether a program's stream is the pair layout.
+template <class P, class = void>
+struct pairs_of : std::false_type {};
+template <class P>
+struct pairs_of<P, std::void_t<decltype(P::kPairs)>> : std::bool_constant<P::kPairs> {};
 
 // PageRank with the stored edge weights: gathers x_u and multiplies by w_e
 // (FP64 accumulation as above).
@@ -662,6 +677,10 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         using val_t = typename Prog::val_t;
         // 16 edges per lane and unit; 8 when weights or 8-byte values need the registers
         constexpr int kU = (Prog::kWeights || sizeof(val_t) > 4) ? 2 : 4, kQ = 4 * kU;
+        // pair layout: header words set the source of the pair words after them
+        // (carried across lanes and units like the interval markers), and a pair
+        // word adds its one gathered value to two destinations
+        constexpr bool kPairs = pairs_of<Prog>::value;
         const uint32_t* const wordsp = g.words;
         const int64_t Cw = g.C;
         const int32_t* const rowp = g.chunk_row;
@@ -676,13 +695,14 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         float fA[kQ], fB[kQ];
         bool vA = false, vB = false, nA = false, nB = false;  // valid, starts a chunk
         uint32_t rA = 0, rB = 0;                              // chunk's first interval
+        uint32_t sA = 0, sB = 0;  // pair layout: header source at the chunk's first word
         uint32_t iA = 0, iB = 0;  // sub-blocks of the unit that hold stream words (bit u)
         // Issues the loads of the next unit. Every load is unconditional (past the
         // end it reads a chunk this wave owns and the words become padding), so
         // the code has no branch around memory operations and the compiler keeps
         // exact counts of the loads in flight.
         auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0,
-                        uint32_t& inm) {
+                        uint32_t& s0, uint32_t& inm) {
             valid = lci < c_hi;
             const int64_t cl = valid ? lci : lprev;
             const int sl = valid ? ls : 0;
@@ -690,6 +710,7 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
             int64_t c_ = cl;
             if constexpr (Prog::kActivity) c_ = list ? list[cl] : cl;
             r0 = (uint32_t)rowp[c_];
+            if constexpr (kPairs) s0 = (uint32_t)g.chunk_src[c_];
             const int64_t base = c_ * Cw + (int64_t)sl * 256 + lane;
             inm = 0;
 #pragma unroll
@@ -718,15 +739,18 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
             }
         };
         if (lci < c_hi) {
-        next(wA, fA, vA, nA, rA, iA);
-        next(wB, fB, vB, nB, rB, iB);
-        uint32_t row = 0;
+        next(wA, fA, vA, nA, rA, sA, iA);
+        next(wB, fB, vB, nB, rB, sB, iB);
+        uint32_t row = 0, hsrc = 0;
         // one unit: decode, gathers, loads of the unit two ahead, LDS reductions
         auto unit = [&](uint32_t* w_, float* f_, bool& valid, bool& starts, uint32_t& r0,
-                        uint32_t& inm) {
-            if (starts) row = r0;
+                        uint32_t& s0, uint32_t& inm) {
+            if (starts) {
+                row = r0;
+                if constexpr (kPairs) hsrc = s0;
+            }
             const uint32_t in_now = inm;
-            uint32_t sidx[kQ], dl[kQ];
+            uint32_t sidx[kQ], dl[kQ], dl2[kPairs ? kQ : 1];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const uint32_t w = ((in_now >> (q >> 2)) & 1u) ? w_[q] : kNone;
@@ -738,9 +762,28 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                     r = upto ? got : row;
                     row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
                 }
-                const bool edge = (w >> 31) == 0 && prog.row_active(r);
-                sidx[q] = edge ? r * (uint32_t)g.I + ((w >> g.sshift) & lmask) : 0u;
-                dl[q] = edge ? ((w >> g.dshift) & tmask) : kNone;
+                if constexpr (kPairs) {
+                    // word kinds by the top three bits: 1xx marker or padding,
+                    // 01x header, 001 pair, 000 plain edge
+                    const uint32_t kind = w >> 29;
+                    const uint64_t hm = __ballot(kind == 2u || kind == 3u);
+                    uint32_t sv = hsrc;
+                    if (hm) {
+                        const uint64_t upto = hm & (lt | (1ull << lane));
+                        const uint32_t got = __shfl(w & 0x3FFFFFFFu, upto ? 63 - __clzll(upto) : lane);
+                        sv = upto ? got : hsrc;
+                        hsrc = (uint32_t)__builtin_amdgcn_readlane((int)(w & 0x3FFFFFFFu), 63 - __clzll(hm));
+                    }
+                    const bool on = prog.row_active(r);
+                    const bool pr = kind == 1u && on, pl = kind == 0u && on;
+                    sidx[q] = (pr || pl) ? r * (uint32_t)g.I + (pr ? sv : ((w >> g.sshift) & lmask)) : 0u;
+                    dl[q] = (pr || pl) ? (w & tmask) : kNone;
+                    dl2[q] = pr ? ((w >> 14) & tmask) : kNone;
+                } else {
+                    const bool edge = (w >> 31) == 0 && prog.row_active(r);
+                    sidx[q] = edge ? r * (uint32_t)g.I + ((w >> g.sshift) & lmask) : 0u;
+                    dl[q] = edge ? ((w >> g.dshift) & tmask) : kNone;
+                }
             }
             val_t raw[kQ];
             float wq[kQ];
@@ -749,7 +792,7 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                 wq[q] = f_[q];
                 raw[q] = curp[sidx[q]];  // non-edges read vertex 0: no divergent branch
             }
-            next(w_, f_, valid, starts, r0, inm);
+            next(w_, f_, valid, starts, r0, s0, inm);
             // branch-free reductions: markers and padding add the identity to
             // the lane's own discard slot (a conditional block here would let the
             // compiler sink a gather into it and wait on every load in flight)
@@ -758,12 +801,16 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                 const bool e = dl[q] != kNone;
                 const acc_t v = e ? prog.from_val(raw[q], wq[q]) : prog.identity();
                 lds_combine(&acc[e ? dl[q] : (uint32_t)g.T + lane], v, Prog::kSum);
+                if constexpr (kPairs) {
+                    const bool e2 = dl2[q] != kNone;
+                    if (__ballot(e2)) lds_combine(&acc[e2 ? dl2[q] : (uint32_t)g.T + lane], e2 ? v : prog.identity(), Prog::kSum);
+                }
             }
         };
         while (vA) {
-            unit(wA, fA, vA, nA, rA, iA);
+            unit(wA, fA, vA, nA, rA, sA, iA);
             if (!vB) break;
-            unit(wB, fB, vB, nB, rB, iB);
+            unit(wB, fB, vB, nB, rB, sB, iB);
         }
         }
     }
@@ -2107,11 +2154,22 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p
     }
 }
 
+// Plain PageRank on either stream layout (the pair layout decodes more word kinds).
+template <typename V>
+void launch_plain_pr(const Layout& L, const Geo& geo, const Ctl& ctl, const ProgPR<V>& pr, const Plan& p,
+                     size_t lds, hipStream_t s, Streamer* str = nullptr) {
+    if (L.pairs)
+        launch_iter<ProgPRP<V>, 1024>(geo, ctl, ProgPRP<V>{pr}, p, lds, s, str);
+    else
+        launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, p, lds, s, str);
+}
+
 // ab = bytes of one LDS accumulator of the program.
 Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
     Geo g;
     g.words = L.words.as<uint32_t>();
     g.chunk_row = L.chunk_row.as<int32_t>();
+    g.chunk_src = L.pairs ? L.chunk_src.as<int32_t>() : nullptr;
     g.items = p.items.as<Item>();
     g.deg = L.outdeg.as<int32_t>();
     g.n = L.n;
@@ -2205,7 +2263,7 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
             launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, p, lds, s);
         } else {
             ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
-            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, p, lds, s);
+            launch_plain_pr<V>(L, geo, ctl, pr, p, lds, s);
         }
     }
     if (vm) permute_rows<V>(vals, vm.o2n, vm.n, 1, (V*)d.d_values, s);
@@ -2252,6 +2310,8 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         const size_t lds = iter_lds(make_geo(L, *p, w, sizeof(double)), L, sizeof(double));
         if (weighted)
             prepare_iter<ProgPRW<V>, 1024>(lds);
+        else if (L.pairs)
+            prepare_iter<ProgPRP<V>, 1024>(lds);
         else
             prepare_iter<ProgPR<V>, 1024>(lds);
         NXG_HIP(hipStreamSynchronize(s));
@@ -2462,7 +2522,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
                 launch_iter<ProgPRW<V>, 1024>(geo, ctl, pr, *p, lds, s, str.get());
             } else {
                 ProgPR<V> pr{cur, nxt, tele, xout, d.damping};
-                launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s, str.get());
+                launch_plain_pr<V>(L, geo, ctl, pr, *p, lds, s, str.get());
             }
         }
         if (d.tol > 0 && k < max_iters) {
@@ -2482,7 +2542,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, vals, d.damping};
             NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
-            launch_iter<ProgPR<V>, 1024>(geo, ctl, pr, *p, lds, s);
+            launch_plain_pr<V>(L, geo, ctl, pr, *p, lds, s);
         }
         NXG_CHECK_LAUNCH();
     }
@@ -3250,6 +3310,8 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 || d.d_seeds ||
          (d.flags & NXG_RUN_SCATTER)))
         fail(NXG_EINVAL, "a HOST_STREAM handle runs single-column PageRank only");
+    if (g->fwd.pairs && (d.program != NXG_PAGERANK || d.batch > 1 || d.d_seeds || (d.flags & NXG_RUN_SCATTER)))
+        fail(NXG_EINVAL, "a PAIRS handle runs plain single-column PageRank only");
     if ((d.flags & NXG_RUN_SCATTER) || (g->flags & NXG_BUILD_SCATTER)) {
         if (!(d.flags & NXG_RUN_SCATTER)) fail(NXG_EINVAL, "a NXG_BUILD_SCATTER layout runs only NXG_RUN_SCATTER PageRank");
         if (d.batch > 1 || d.d_seeds) fail(NXG_EUNSUPPORTED, "NXG_RUN_SCATTER runs one column");

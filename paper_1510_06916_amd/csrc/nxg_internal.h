@@ -132,6 +132,8 @@ struct Layout {
     DevBuf words;          // uint32 [n_words]
     DevBuf chunk_row;      // int32  [n_chunks]
     DevBuf chunk_tile;     // int32  [n_chunks]
+    DevBuf chunk_src;      // int32  [n_chunks] pair layout: header source in effect at the
+                           // chunk's first word
     DevBuf tile_chunk;     // int64  [n_tiles + 1] chunk index of each tile's first chunk
     DevBuf group_edge;     // int64  [n_tiles*P + 1] stream-order index of each group's first edge
     DevBuf group_word;     // int64  [n_tiles*P + 1] word position of each group's marker
@@ -143,6 +145,11 @@ struct Layout {
     std::vector<int64_t> h_tile_chunk;  // host copy of tile_chunk
     std::vector<int64_t> h_tile_edges;  // edges per tile (host)
     bool has_perm = false, has_weight = false;
+    // NXG_BUILD_PAIRS (source order): besides plain edge words, a header word
+    // 0x40000000 | s names a source field, and each later pair word
+    // 0x20000000 | d | d' << 14 holds two destination fields of that source
+    // (the edges of one source into one tile, two at a time)
+    bool pairs = false;
     // NXG_BUILD_HOST_STREAM: words (and weights) live in pinned host memory
     bool host_stream = false;
     HostBuf h_words, h_weight;

@@ -49,7 +49,9 @@ def test_host_side_argument_errors(L):
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
     d = _lib.BuildDesc(n=10, m=5)  # null edge arrays
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
-    d = _lib.BuildDesc(n=10, m=0, flags=0x100)
+    d = _lib.BuildDesc(n=10, m=0, flags=0x1000)
+    assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
+    d = _lib.BuildDesc(n=10, m=0, flags=_lib.NXG_BUILD_PAIRS | _lib.NXG_BUILD_SYMMETRIZE)
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
     d = _lib.BuildDesc(n=10, m=0, flags=_lib.NXG_BUILD_SYMMETRIZE | _lib.NXG_BUILD_KEEP_PERM)
     assert L.nxg_dsss_build(ctypes.byref(d), None, ctypes.byref(out)) == _lib.NXG_EINVAL
