@@ -88,7 +88,7 @@ def rmat(scale, ef, seed, dev):
 # ---------------------------------------------------------------------------
 def bench_pagerank(args, dev):
     import torch
-    from paper_1510_06916_amd import DSSS, copy_probe, tune
+    from paper_1510_06916_amd import DSSS, copy_probe, read_probe, tune
     n = 1 << args.scale
     src, dst = rmat(args.scale, args.ef, args.seed, dev)
     if args.interval or args.tile or args.chunk:
@@ -163,7 +163,8 @@ def bench_pagerank(args, dev):
         del g3, out3
         torch.cuda.empty_cache()
     copy_gbs = copy_probe(1 << 30, 10)
-    log("copy probe: %.0f GB/s" % copy_gbs)
+    read_gbs = read_probe(1 << 31, 10)
+    log("copy probe: %.0f GB/s, read probe: %.0f GB/s" % (copy_gbs, read_gbs))
     traffic = measured_traffic({"interval": inf["interval"], "tile": inf["tile"], "chunk": inf["chunk"],
                                 "piece_chunks": piece, "order": order,
                                 "relabel": bool(best["relabel"]), "pairs": pairs})
@@ -185,7 +186,7 @@ def bench_pagerank(args, dev):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_iter": b_iter, "kernel_ms": kern_ms,
-                     "copy_probe_gbs": copy_gbs},
+                     "copy_probe_gbs": copy_gbs, "read_probe_gbs": read_gbs},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_pagerank(src, dst, n, args.cpu_stride)

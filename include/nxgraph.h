@@ -70,6 +70,12 @@ int nxg_abi_version(void);
  * Synchronises the stream. */
 nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbps);
 
+/* Attainable read bandwidth: times reps passes of four-deep 16-byte
+ * non-temporal loads over a `bytes`-byte buffer (nothing written back) and
+ * returns read GB/s, the ceiling of an iteration that mostly reads.
+ * NXG_EINVAL if bytes < 4096 or reps < 1. Synchronises the stream. */
+nxg_status nxg_read_probe(int64_t bytes, int32_t reps, void* stream, double* gbps);
+
 /* ------------------------------------------------------------------------- */
 /* DSSS construction (Sec. III-A: intervals and sub-shards from an edge list)  */
 /* ------------------------------------------------------------------------- */

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import NxgError  # noqa: F401
 
 __all__ = ["DSSS", "MultiDSSS", "NxgError", "WeightedPageRank", "abi_version",
-           "install_torch_allocator", "tune", "copy_probe"]
+           "install_torch_allocator", "tune", "copy_probe", "read_probe"]
 
 _alloc_refs = None
 
@@ -69,6 +69,15 @@ def copy_probe(nbytes=1 << 30, reps=10):
     g = ctypes.c_double(0.0)
     _lib.check(_lib.lib().nxg_copy_probe(int(nbytes), int(reps), _stream_handle(), ctypes.byref(g)),
                "nxg_copy_probe")
+    return g.value
+
+
+def read_probe(nbytes=1 << 30, reps=10):
+    """Attainable HBM read bandwidth (GB/s) of a plain read-only stream."""
+    install_torch_allocator()
+    g = ctypes.c_double(0.0)
+    _lib.check(_lib.lib().nxg_read_probe(int(nbytes), int(reps), _stream_handle(), ctypes.byref(g)),
+               "nxg_read_probe")
     return g.value
 
 

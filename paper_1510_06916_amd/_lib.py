@@ -108,6 +108,8 @@ SIGNATURES = {
     "nxg_multi_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "nxg_copy_probe": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_double)]),
+    "nxg_read_probe": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double)]),
     "nxg_tune": (ctypes.c_int, [ctypes.POINTER(BuildDesc), ctypes.c_int, ctypes.c_int, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.POINTER(TuneResult)]),
     "nxg_pagerank_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AdjointDesc),

@@ -286,6 +286,13 @@ nxg_status nxg_copy_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
     });
 }
 
+nxg_status nxg_read_probe(int64_t bytes, int32_t reps, void* stream, double* gbps) {
+    return guarded([&]() {
+        if (!gbps) fail(NXG_EINVAL, "gbps is NULL");
+        return read_probe(bytes, reps, (hipStream_t)stream, gbps);
+    });
+}
+
 nxg_status nxg_tune(const nxg_build_desc* desc, nxg_program program, nxg_dtype dtype,
                     int32_t batch, void* stream, nxg_tune_result* result) {
     return guarded([&]() {

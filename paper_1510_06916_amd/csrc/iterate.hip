@@ -3259,41 +3259,6 @@ nxg_status multi_run(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
 
 void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) { set_weights(g, d_w, s); }
 
-namespace {
-// Plain streaming copy: the reference point for attainable HBM bandwidth and
-// for scaling the FETCH_SIZE / WRITE_SIZE counters.
-__global__ __launch_bounds__(256) void k_copy_probe(const u32x4* __restrict__ a, u32x4* __restrict__ b,
-                                                    int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        b[i] = __builtin_nontemporal_load(a + i);
-}
-}  // namespace
-
-nxg_status copy_probe(int64_t bytes, int reps, hipStream_t s, double* gbps) {
-    if (bytes < 4096 || reps < 1) fail(NXG_EINVAL, "copy probe needs bytes >= 4096 and reps >= 1");
-    const int64_t n = bytes / 16;
-    DevBuf a, b;
-    a.alloc(n * 16, s);
-    b.alloc(n * 16, s);
-    NXG_HIP(hipMemsetAsync(a.p, 1, n * 16, s));
-    int cus = num_cus(0);
-    const int grid = cus * 16;
-    hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, a.as<u32x4>(), b.as<u32x4>(), n);
-    NXG_CHECK_LAUNCH();
-    Events ev;
-    hipEvent_t e0 = ev.a, e1 = ev.b;
-    NXG_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, a.as<u32x4>(), b.as<u32x4>(), n);
-    NXG_CHECK_LAUNCH();
-    NXG_HIP(hipEventRecord(e1, s));
-    NXG_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    *gbps = 2.0 * n * 16 * reps / (ms * 1e-3) / 1e9;
-    return NXG_OK;
-}
-
 int lds_budget_bytes(int device) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||

@@ -249,4 +249,5 @@ int lds_budget_bytes(int device);
 // Chunks per work item when a run does not choose (see iterate.hip).
 int default_piece(int64_t chunks, int C, size_t slot_bytes, int cus);
 nxg_status copy_probe(int64_t bytes, int reps, hipStream_t s, double* gbps);
+nxg_status read_probe(int64_t bytes, int reps, hipStream_t s, double* gbps);
 }  // namespace nxg
