@@ -316,7 +316,8 @@ typedef struct nxg_tune_result {
 
 /* Times captured PageRank iterations (NXG_RUN_CAPTURE) of the graph in desc
  * under candidate layouts (vertex numbering x edge order inside a sub-shard,
- * then source interval x destination tile, then chunk and piece size) and
+ * then source interval x destination tile, then chunk and piece size, then,
+ * for plain PageRank in source order, the pair encoding NXG_BUILD_PAIRS) and
  * returns the fastest. The paper picks the interval count from experience
  * (Sec. IV-B2); here it is measured. Results are cached per process and, when the
  * environment variable NXG_TUNE_CACHE names a file, appended to it and read

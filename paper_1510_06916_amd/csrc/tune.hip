@@ -51,8 +51,8 @@ bool load_cached(const std::string& key, nxg_tune_result* out) {
         if (key != line) continue;
         nxg_tune_result r;
         memset(&r, 0, sizeof r);
-        if (sscanf(bar + 1, "%d %d %d %d %d %lf %d", &r.interval, &r.tile, &r.chunk, &r.order,
-                   &r.piece_chunks, &r.ms_per_iter, &r.relabel) == 7) {
+        if (sscanf(bar + 1, "%d %d %d %d %d %lf %d %d", &r.interval, &r.tile, &r.chunk, &r.order,
+                   &r.piece_chunks, &r.ms_per_iter, &r.relabel, &r.pairs) >= 7) {
             *out = r;
             found = true;
         }
@@ -71,8 +71,8 @@ void store_cached(const std::string& key, const nxg_tune_result& r) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s|%d %d %d %d %d %.6f %d\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
-            r.piece_chunks, r.ms_per_iter, r.relabel);
+    fprintf(f, "%s|%d %d %d %d %d %.6f %d %d\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
+            r.piece_chunks, r.ms_per_iter, r.relabel, r.pairs);
     fclose(f);
 }
 
@@ -133,7 +133,8 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
                    : 256;
     }();
     // pieces: 0 = the run's default only; otherwise the default and {1/4, 1/2, 2} of it
-    auto try_layout = [&](int relabel, int order, int interval, int tile, int chunk, bool pieces) {
+    auto try_layout = [&](int relabel, int order, int interval, int tile, int chunk, bool pieces,
+                          int pairs = 0) {
         nxg_build_desc d = desc;
         d.interval = interval;
         d.tile = tile;
@@ -141,6 +142,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
         d.order = order;
         d.value_bytes = 8;
         d.flags = relabel ? (d.flags | NXG_BUILD_RELABEL) : (d.flags & ~(uint32_t)NXG_BUILD_RELABEL);
+        d.flags = pairs ? (d.flags | NXG_BUILD_PAIRS) : (d.flags & ~(uint32_t)NXG_BUILD_PAIRS);
         d.flags &= ~(uint32_t)NXG_BUILD_TRANSPOSE;  // only the forward graph is timed
         nxg_dsss* g = nullptr;
         try {
@@ -159,6 +161,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
                     best.chunk = g->fwd.C;
                     best.order = order;
                     best.relabel = relabel;
+                    best.pairs = pairs;
                     best.piece_chunks = cand[k];
                 }
             }
@@ -188,6 +191,12 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     // stage 3: chunk size and piece size for the best layout
     const nxg_tune_result stage2 = best;
     for (int C : {1024, 512, 2048}) try_layout(stage2.relabel, stage2.order, stage2.interval, stage2.tile, C, true);
+    // stage 4: encoding, for plain PageRank in source order: the pair layout
+    // (two destinations of one source per word) in the best geometry; a layout
+    // it does not fit (tile or interval too large) is skipped
+    const nxg_tune_result stage3 = best;
+    if (program == NXG_PAGERANK && stage3.order == NXG_ORDER_SRC && !desc.d_weight)
+        try_layout(stage3.relabel, stage3.order, stage3.interval, stage3.tile, stage3.chunk, false, 1);
     best.candidates = timed;
     store_cached(key, best);
     *out = best;

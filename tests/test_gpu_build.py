@@ -114,3 +114,13 @@ def test_empty_graph_and_single_vertex(gpu_device):
     assert abs(float(x[0]) - 1.0) < 1e-15
     lev, st = g1.bfs(0)
     assert lev.tolist() == [0]
+
+
+def test_bandwidth_probes(gpu_device):
+    from paper_1510_06916_amd import copy_probe, read_probe, NxgError
+    c = copy_probe(1 << 24, 2)
+    r = read_probe(1 << 24, 2)
+    say("copy probe %.0f GB/s, read probe %.0f GB/s (16 MiB)" % (c, r))
+    assert 10.0 < c < 20000.0 and 10.0 < r < 20000.0
+    with pytest.raises(NxgError, match="EINVAL"):
+        read_probe(1024, 1)
