@@ -247,16 +247,27 @@ def bench_bfs_wcc(args, dev, which):
 def bench_ppr(args, dev):
     import torch
     import rmatgen
-    from paper_1510_06916_amd import DSSS
+    from paper_1510_06916_amd import DSSS, tune
     scale, ef, seed, B, iters = 22, 16, 4, 64, 30
     n = 1 << scale
     src, dst = rmat(scale, ef, seed, dev)
     seeds = torch.from_numpy(rmatgen.distinct_vertices(seed + 100, B, n))
-    gb = DSSS.build(src, dst, n, tile=256, interval=16384, value_bytes=8 * B)
-    gb.ppr(seeds, 2)
+    # vector width (columns per pass), tile, interval, order and numbering from the tuner
+    t0 = time.perf_counter()
+    best = tune(src, dst, n, batch=B)
+    log("batched tune in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
+    W = best["width"]
+    gb = DSSS.build(src, dst, n, tile=best["tile"], interval=best["interval"], chunk=best["chunk"],
+                    order=("dst", "src")[best["order"]], relabel=bool(best["relabel"]),
+                    value_bytes=8 * W)
+
+    def run_all(k):
+        return [gb.ppr(seeds[i:i + W], k)[0] for i in range(0, B, W)]
+
+    run_all(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    xb, st = gb.ppr(seeds, iters)
+    run_all(iters)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     gp = DSSS.build(src, dst, n, order=args.order, relabel=bool(args.relabel))
@@ -275,6 +286,9 @@ def bench_ppr(args, dev):
     res = {"metric": "batched PPR edge-vector updates per second", "value": B * gb.m * iters / tb / 1e9,
            "unit": "G updates/s", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
            "config": {"workload": "ppr rmat-s22-ef16 B=64 30 iterations", "n": n, "m": gb.m,
+                      "width": W, "tile": best["tile"], "interval": best["interval"],
+                      "order": ("dst", "src")[best["order"]], "relabel": best["relabel"],
+                      "tuned_candidates": best["candidates"],
                       "plain_order": args.order, "plain_relabel": int(args.relabel),
                       "batched_ms": tb * 1e3, "plain_64_runs_ms": tp * 1e3,
                       "speedup_vs_plain": tp / tb}}

@@ -312,6 +312,9 @@ typedef struct nxg_tune_result {
     int32_t candidates;    /* candidates timed (0 when served from the cache) */
     int32_t relabel;       /* 1 if the best layout uses NXG_BUILD_RELABEL */
     int32_t pairs;         /* 1 if the best layout uses NXG_BUILD_PAIRS */
+    int32_t width;         /* batched runs: columns per pass (build with value_bytes =
+                              8 * width and run the batch in ceil(batch / width)
+                              passes); 1 for single-column tuning */
 } nxg_tune_result;
 
 /* Times captured PageRank iterations (NXG_RUN_CAPTURE) of the graph in desc
@@ -323,7 +326,12 @@ typedef struct nxg_tune_result {
  * environment variable NXG_TUNE_CACHE names a file, appended to it and read
  * back, keyed by device, n, m, program, dtype, batch, value_bytes and flags.
  * Builds and runs on `stream` and synchronises it; never use under capture.
- * PageRank (plain or weighted), F32 or F64, batch 1. */
+ * PageRank (plain or weighted), F32 or F64, batch 1; or batched personalised
+ * PageRank (plain, F32, batch > 1): then the candidates are the vector width
+ * (columns per pass: the batch up to 64, then 32 and 16) with the largest tile
+ * its accumulators fit in LDS and half of it, then the source interval, then
+ * edge order x vertex numbering, timed as uninterrupted 8-iteration batched
+ * runs over ceil(batch / width) passes. */
 nxg_status nxg_tune(const nxg_build_desc* desc, nxg_program program, nxg_dtype dtype,
                     int32_t batch, void* stream, nxg_tune_result* result);
 

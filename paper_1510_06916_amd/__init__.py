@@ -81,10 +81,12 @@ def read_probe(nbytes=1 << 30, reps=10):
     return g.value
 
 
-def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
+def tune(src, dst, n, dtype=torch.float32, weights=None, batch=1, stream=None):
     """Times candidate layouts for PageRank on this graph; returns a dict with
     interval, tile, chunk, order (0 dst, 1 src), relabel, pairs, piece_chunks,
-    ms_per_iter, candidates."""
+    ms_per_iter, candidates and width. batch > 1 tunes batched personalised
+    PageRank (FP32): width is then the columns per pass (build with
+    value_bytes=8*width) and ms_per_iter covers the whole batch."""
     install_torch_allocator()
     src = _dev_i32(src, "src")
     dst = _dev_i32(dst, "dst")
@@ -96,8 +98,8 @@ def tune(src, dst, n, dtype=torch.float32, weights=None, stream=None):
     r = _lib.TuneResult()
     prog = _lib.NXG_PAGERANK_WEIGHTED if w is not None else _lib.NXG_PAGERANK
     with torch.cuda.device(src.device):
-        _lib.check(_lib.lib().nxg_tune(ctypes.byref(d), prog, _DT[dtype], 1, _stream_handle(stream),
-                                       ctypes.byref(r)), "nxg_tune")
+        _lib.check(_lib.lib().nxg_tune(ctypes.byref(d), prog, _DT[dtype], int(batch),
+                                       _stream_handle(stream), ctypes.byref(r)), "nxg_tune")
     return {k: getattr(r, k) for k, _ in r._fields_}
 
 

@@ -77,7 +77,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("interval", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("piece_chunks", ctypes.c_int32),
                 ("ms_per_iter", ctypes.c_double), ("candidates", ctypes.c_int32),
-                ("relabel", ctypes.c_int32), ("pairs", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("pairs", ctypes.c_int32), ("width", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

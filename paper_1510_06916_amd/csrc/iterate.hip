@@ -2785,10 +2785,11 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         fail(NXG_EUNSUPPORTED, "batched runs support plain PageRank in FP32");
     if (d.d_teleport) fail(NXG_EUNSUPPORTED, "batched runs take seed vertices (d_seeds), not a dense teleport");
     if (d.flags & NXG_RUN_WARM_START) fail(NXG_EUNSUPPORTED, "batched runs start from the teleport vector");
-    const size_t lds = (size_t)L.T * B * 8;
+    // the tile's [T, B] FP64 sums; at least the kernels' scalar reduction area
+    // (48 x 64 doubles), so a narrow batch runs on a small tile too
+    const size_t lds = std::max((size_t)L.T * B * 8, (size_t)(3 * 16) * 64 * 8);
     if (lds > (size_t)lds_budget_bytes(g->device))
         fail(NXG_EINVAL, "tile * batch * 8 bytes exceeds LDS; build with value_bytes = 8 * batch");
-    if ((size_t)(3 * 16) * 64 * 8 > lds) fail(NXG_EINVAL, "tile too small for the batched reduction");
     const int cus = num_cus(g->device);
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * B * 8, cus);

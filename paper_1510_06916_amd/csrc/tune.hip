@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "nxg_internal.h"
 
@@ -51,8 +52,9 @@ bool load_cached(const std::string& key, nxg_tune_result* out) {
         if (key != line) continue;
         nxg_tune_result r;
         memset(&r, 0, sizeof r);
-        if (sscanf(bar + 1, "%d %d %d %d %d %lf %d %d", &r.interval, &r.tile, &r.chunk, &r.order,
-                   &r.piece_chunks, &r.ms_per_iter, &r.relabel, &r.pairs) >= 7) {
+        r.width = 1;
+        if (sscanf(bar + 1, "%d %d %d %d %d %lf %d %d %d", &r.interval, &r.tile, &r.chunk, &r.order,
+                   &r.piece_chunks, &r.ms_per_iter, &r.relabel, &r.pairs, &r.width) >= 7) {
             *out = r;
             found = true;
         }
@@ -71,8 +73,8 @@ void store_cached(const std::string& key, const nxg_tune_result& r) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s|%d %d %d %d %d %.6f %d %d\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
-            r.piece_chunks, r.ms_per_iter, r.relabel, r.pairs);
+    fprintf(f, "%s|%d %d %d %d %d %.6f %d %d %d\n", key.c_str(), r.interval, r.tile, r.chunk, r.order,
+            r.piece_chunks, r.ms_per_iter, r.relabel, r.pairs, r.width);
     fclose(f);
 }
 
@@ -95,6 +97,92 @@ double time_run(nxg_dsss* g, const nxg_run_desc& base, void* values, int piece, 
     return best;
 }
 
+// Milliseconds per iteration of `batch` personalised columns run `width` at a
+// time: an 8-iteration batched run of `width` uniform columns (the timing does
+// not depend on the seeds) after a 2-iteration warm-up, times the passes.
+double time_batched(nxg_dsss* g, int batch, int width, void* values, hipStream_t s) {
+    nxg_run_desc d;
+    memset(&d, 0, sizeof d);
+    d.program = NXG_PAGERANK;
+    d.dtype = NXG_F32;
+    d.batch = width;
+    d.damping = 0.85;
+    d.d_values = values;
+    d.max_iters = 2;
+    nxg_run_stats st;
+    run_program(g, d, s, &st);
+    d.max_iters = 8;
+    run_program(g, d, s, &st);
+    const int passes = (batch + width - 1) / width;
+    return (double)st.device_ms / d.max_iters * passes;
+}
+
+// Batched personalised PageRank: the vector width (columns per pass, each pass
+// a batched run over the same graph) with the tile it allows in LDS, then the
+// source interval, edge order and vertex numbering.
+void tune_batched(const nxg_build_desc& desc, int batch, hipStream_t s, nxg_tune_result& best,
+                  int device) {
+    const int budget = lds_budget_bytes(device);
+    DevBuf values;
+    values.alloc(sizeof(float) * (size_t)desc.n * std::min(batch, 64), s);
+    int timed = 0;
+    best.ms_per_iter = 1e300;
+    auto try_layout = [&](int width, int tile, int interval, int order, int relabel) {
+        nxg_build_desc d = desc;
+        d.interval = std::min(interval, desc.n);
+        d.tile = tile;
+        d.chunk = 0;
+        d.order = order;
+        d.value_bytes = 8 * width;
+        d.flags = (relabel ? (d.flags | NXG_BUILD_RELABEL) : (d.flags & ~(uint32_t)NXG_BUILD_RELABEL)) &
+                  ~(uint32_t)(NXG_BUILD_TRANSPOSE | NXG_BUILD_PAIRS);
+        nxg_dsss* g = nullptr;
+        try {
+            g = build_handle(d, s);
+            const double ms = time_batched(g, batch, width, values.p, s);
+            ++timed;
+            if (ms < best.ms_per_iter * (timed == 1 ? 1.0 : 0.98)) {
+                best.ms_per_iter = ms;
+                best.interval = g->fwd.I;
+                best.tile = g->fwd.T;
+                best.chunk = g->fwd.C;
+                best.order = order;
+                best.relabel = relabel;
+                best.width = width;
+                best.pairs = 0;
+                best.piece_chunks = 0;
+            }
+        } catch (const Error& e) {
+            if (e.status != NXG_EINVAL) {
+                delete g;
+                throw;
+            }
+        }
+        delete g;
+    };
+    // widths: the whole batch (up to 64 columns), then 32 and 16 when smaller
+    std::vector<int> widths{std::min(batch, 64)};
+    for (int w : {32, 16})
+        if (w < widths[0]) widths.push_back(w);
+    auto tile_for = [&](int w) {
+        int t = 1;
+        while ((int64_t)t * 2 * w * 8 <= budget) t *= 2;
+        return t;
+    };
+    // stage 1: width x tile (largest and half) at I = 16K, destination order, natural ids
+    for (int w : widths)
+        for (int tt : {tile_for(w), tile_for(w) / 2}) try_layout(w, tt, 16384, NXG_ORDER_DST, 0);
+    const nxg_tune_result s1 = best;
+    // stage 2: source interval
+    for (int I : {4096, 65536}) try_layout(s1.width, s1.tile, I, s1.order, s1.relabel);
+    const nxg_tune_result s2 = best;
+    // stage 3: edge order x vertex numbering
+    for (int relabel : {0, 1})
+        for (int order : {NXG_ORDER_DST, NXG_ORDER_SRC})
+            if (relabel != s2.relabel || order != s2.order) try_layout(s2.width, s2.tile, s2.interval, order, relabel);
+    best.candidates = timed;
+}
+
 }  // namespace
 
 nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, hipStream_t s,
@@ -102,7 +190,9 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     if (program != NXG_PAGERANK && program != NXG_PAGERANK_WEIGHTED)
         fail(NXG_EUNSUPPORTED, "the autotuner times PageRank runs");
     if (dtype != NXG_F32 && dtype != NXG_F64) fail(NXG_EINVAL, "PageRank dtype must be F32 or F64");
-    if (batch != 1) fail(NXG_EUNSUPPORTED, "the autotuner times single-column runs");
+    if (batch < 1) fail(NXG_EINVAL, "batch must be >= 1");
+    if (batch > 1 && (program != NXG_PAGERANK || dtype != NXG_F32))
+        fail(NXG_EUNSUPPORTED, "batched runs are plain PageRank in FP32");
     if (desc.flags & (NXG_BUILD_SCATTER | NXG_BUILD_HOST_STREAM))
         fail(NXG_EUNSUPPORTED, "the autotuner times device-resident DSSS layouts (no SCATTER, no HOST_STREAM)");
     int device = 0;
@@ -110,6 +200,15 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     const std::string key = tune_key(desc, program, dtype, batch, device);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (load_cached(key, out)) return NXG_OK;
+    if (batch > 1) {
+        nxg_tune_result rb;
+        memset(&rb, 0, sizeof rb);
+        tune_batched(desc, batch, s, rb, device);
+        if (rb.candidates == 0) fail(NXG_EINVAL, "no batched layout fits this graph");
+        store_cached(key, rb);
+        *out = rb;
+        return NXG_OK;
+    }
     const size_t vsize = dtype == NXG_F64 ? 8 : 4;
     DevBuf values;
     values.alloc(vsize * (size_t)desc.n, s);
@@ -198,6 +297,7 @@ nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, h
     if (program == NXG_PAGERANK && stage3.order == NXG_ORDER_SRC && !desc.d_weight)
         try_layout(stage3.relabel, stage3.order, stage3.interval, stage3.tile, stage3.chunk, false, 1);
     best.candidates = timed;
+    best.width = 1;
     store_cached(key, best);
     *out = best;
     return NXG_OK;
