@@ -243,7 +243,10 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
 #define NXG_RUN_CAPTURE 0x4u    /* PageRank, tol <= 0: record the launches of the run into a
                                    hipGraph kept by the handle (with its workspace) and replay
                                    it when a later run has the same program, dtype, iteration
-                                   count, damping, flags, buffers and piece size */
+                                   count, damping, flags, buffers and piece size. Batched
+                                   runs too (same batch, seed and output buffers; the seeds
+                                   are checked on the host at every call and read by the
+                                   graph at every replay) */
 #define NXG_RUN_SCATTER 0x8u    /* PageRank (plain or weighted, F32 or F64, batch 1) on a
                                    NXG_BUILD_SCATTER layout, coarse-grained: every edge adds
                                    its source's share to its destination with a device-scope

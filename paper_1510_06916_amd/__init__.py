@@ -249,17 +249,25 @@ class DSSS:
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 
-    def ppr(self, seeds, iters, damping=0.85, tol=0.0, out=None):
+    def ppr(self, seeds, iters, damping=0.85, tol=0.0, out=None, capture=False):
         """Batched personalised PageRank: column b teleports to seeds[b]; returns
         x [n, B] FP32 (B = len(seeds) <= 64). The graph must be built with
-        value_bytes >= 8 * B."""
+        value_bytes >= 8 * B. capture=True records the run into a hipGraph kept
+        by the handle and replays it when a later call passes the same seed
+        tensor (a device int32 tensor, whose contents may change) and out."""
+        # a contiguous device int32 tensor is used in place (its pointer is kept)
         seeds = torch.as_tensor(seeds, dtype=torch.int32).to(self.device).contiguous()
         B = seeds.numel()
         x = out if out is not None else torch.empty((self.n, B), dtype=torch.float32,
                                                     device=self.device)
+        flags = 0
+        if capture:
+            flags |= _lib.NXG_RUN_CAPTURE
+            self._keep = getattr(self, "_keep", [])
+            self._keep += [x, seeds]  # captured graphs hold these pointers
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=B,
                          damping=float(damping), max_iters=int(iters), tol=float(tol),
-                         d_teleport=None, roots=None, d_values=x.data_ptr(), flags=0,
+                         d_teleport=None, roots=None, d_values=x.data_ptr(), flags=flags,
                          d_seeds=seeds.data_ptr())
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
@@ -398,9 +406,12 @@ class MultiDSSS:
         except Exception:
             pass
 
-    def pagerank(self, iters, damping=0.85, persistent=False, out=None):
+    def pagerank(self, iters, damping=0.85, persistent=False, out=None, capture=False):
         """x of every graph after iters iterations; out: optional list of FP32
-        tensors [n_i] to write into (else views of one new buffer)."""
+        tensors [n_i] to write into (else views of one new buffer).
+        capture=True records the run's launches into a hipGraph kept by the
+        handle and replays it on later runs with the same iteration count and
+        damping (the outputs may differ from run to run)."""
         if out is None:
             flat = torch.empty(sum(self.sizes), dtype=torch.float32, device=self.device)
             outs = list(flat.split(self.sizes))
@@ -414,7 +425,8 @@ class MultiDSSS:
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=1,
                          damping=float(damping), max_iters=int(iters), tol=0.0, d_teleport=None,
                          roots=None, d_values=None,
-                         flags=_lib.NXG_RUN_PERSISTENT if persistent else 0, d_seeds=None)
+                         flags=(_lib.NXG_RUN_PERSISTENT if persistent else 0) |
+                         (_lib.NXG_RUN_CAPTURE if capture else 0), d_seeds=None)
         st = _lib.RunStats()
         with torch.cuda.device(self.device):
             _lib.check(_lib.lib().nxg_multi_run(self._h, ctypes.byref(d), ptrs, _stream_handle(),

@@ -1991,6 +1991,18 @@ struct MultiCache : Cached {
     std::vector<Workspace> ws;
     std::vector<MultiGraph> hdesc;
     DevBuf ditems, dgraph, ddesc, dfin, dres, dpart;
+    // NXG_RUN_CAPTURE: the run's launches recorded once (they read the graph
+    // descriptors, so each run's output buffers reach them through ddesc)
+    double cap_damping = 0.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~MultiCache() override { drop_graph(); }
 };
 
 // Index arrays of a relabeled or degreed build (both NULL otherwise); n is the
@@ -2224,6 +2236,24 @@ struct CapturedPR : Cached {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~CapturedPR() override {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// A batched personalised PageRank run recorded into a hipGraph (NXG_RUN_CAPTURE)
+// with its workspace; replayed when a later run has the same width, iteration
+// count, piece size, damping, seed and output buffers. Each call still checks
+// the seeds (and maps them to internal ids) before the replay.
+struct CapturedBatched : Cached {
+    int B = 0, iters = 0, piece = 0;
+    double damping = 0.0;
+    const void* values = nullptr;
+    const void* seeds = nullptr;
+    Workspace w;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~CapturedBatched() override {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -2794,20 +2824,48 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     int piece = env_int("NXG_PIECE_CHUNKS", 0);
     if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * B * 8, cus);
     Plan* p = get_plan(g, L, piece, false, s);
-    Workspace w;
     const int max_iters = d.max_iters;
-    // partial slots hold T*B doubles each
-    const int64_t hub = (int64_t)std::max(p->n_slots, 1) * L.T * B;
-    w.partial.alloc(sizeof(double) * hub, s);
-    w.tile_s.alloc(sizeof(double) * 3 * B * (size_t)L.n_tiles, s);
-    w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+    const bool capture = (d.flags & NXG_RUN_CAPTURE) != 0;
+    if (capture && d.tol > 0) fail(NXG_EINVAL, "NXG_RUN_CAPTURE needs a fixed iteration count (tol <= 0)");
+    if (capture && max_iters < 1) fail(NXG_EINVAL, "NXG_RUN_CAPTURE needs max_iters >= 1");
+    // a captured run keeps its workspace (and graph) in the handle
+    CapturedBatched* cap = nullptr;
+    bool fresh = true;
+    if (capture) {
+        for (Cached* x : g->cached) {
+            CapturedBatched* c = dynamic_cast<CapturedBatched*>(x);
+            if (c && c->B == B && c->iters == max_iters && c->piece == piece && c->damping == d.damping &&
+                c->values == d.d_values && c->seeds == d.d_seeds)
+                cap = c;
+        }
+        fresh = cap == nullptr;
+        if (fresh) {
+            cap = new CapturedBatched();
+            g->cached.push_back(cap);
+            cap->B = B;
+            cap->iters = max_iters;
+            cap->piece = piece;
+            cap->damping = d.damping;
+            cap->values = d.d_values;
+            cap->seeds = d.d_seeds;
+        }
+    }
+    Workspace wl;
+    Workspace& w = cap ? cap->w : wl;
     const size_t nstat = (size_t)(max_iters + 2) * 3 * B;
-    w.stats.alloc(sizeof(double) * nstat, s);
-    NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * nstat, s));
-    w.done.alloc(sizeof(int32_t), s);
-    NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
-    w.buf[0].alloc(sizeof(float) * (size_t)L.n * B, s);
-    w.buf[1].alloc(sizeof(float) * (size_t)L.n * B, s);
+    if (fresh) {
+        // partial slots hold T*B doubles each
+        const int64_t hub = (int64_t)std::max(p->n_slots, 1) * L.T * B;
+        w.partial.alloc(sizeof(double) * hub, s);
+        w.tile_s.alloc(sizeof(double) * 3 * B * (size_t)L.n_tiles, s);
+        w.tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+        w.stats.alloc(sizeof(double) * nstat, s);
+        NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * nstat, s));
+        w.done.alloc(sizeof(int32_t), s);
+        NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
+        w.buf[0].alloc(sizeof(float) * (size_t)L.n * B, s);
+        w.buf[1].alloc(sizeof(float) * (size_t)L.n * B, s);
+    }
     const int32_t* seeds = d.d_seeds;
     if (seeds) {
         // seeds index the vertex arrays (and the id map of a relabeled build)
@@ -2823,7 +2881,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if (vm) {
         // seeds to internal ids; the result rows come back through old2new
         if (seeds) {
-            w.mseeds.alloc(sizeof(int32_t) * B, s);
+            if (fresh) w.mseeds.alloc(sizeof(int32_t) * B, s);
             permute_rows<int32_t>(vm.o2n, seeds, B, 1, w.mseeds.as<int32_t>(), s);
             seeds = w.mseeds.as<int32_t>();
             int32_t hs2[64];
@@ -2832,15 +2890,17 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             for (int b = 0; b < B; ++b)
                 if (hs2[b] < 0) fail(NXG_EINVAL, "seed vertex dropped by NXG_BUILD_DEGREE (it has no edges)");
         }
-        w.mvals.alloc(sizeof(float) * (size_t)L.n * B, s);
+        if (fresh) w.mvals.alloc(sizeof(float) * (size_t)L.n * B, s);
         vals = w.mvals.as<float>();
     }
-    hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, s,
-                       L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
-    NXG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, s, L.n, B, L.outdeg.as<int32_t>(),
-                       seeds, w.stats.as<double>());
-    NXG_CHECK_LAUNCH();
+    auto start = [&](hipStream_t cs) {
+        hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, cs,
+                           L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, cs, L.n, B, L.outdeg.as<int32_t>(),
+                           seeds, w.stats.as<double>());
+        NXG_CHECK_LAUNCH();
+    };
     Geo geo = make_geo(L, *p, w, 8);
     const int n_items = (int)p->h_items.size();
     const int n_fin = (int)p->h_fin.size();
@@ -2855,27 +2915,74 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     // the scalar reduction: blocks of `per` tiles, then one block over the block sums
     const int rblocks = std::min(L.n_tiles, 256);
     const int rper = (L.n_tiles + rblocks - 1) / rblocks;
-    w.part.alloc(sizeof(double) * 3 * B * (size_t)rblocks, s);
-    auto one_iteration = [&](const BCtl& ctl, const float* cur, float* nxt, float* xout) {
+    if (fresh) w.part.alloc(sizeof(double) * 3 * B * (size_t)rblocks, s);
+    auto one_iteration = [&](const BCtl& ctl, const float* cur, float* nxt, float* xout, hipStream_t cs) {
         if (n_items > 0) {
-            hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, s, geo, ctl, cur,
+            hipLaunchKernelGGL(k_iterate_batched<1024>, dim3(n_items), dim3(1024), lds, cs, geo, ctl, cur,
                                nxt, xout, seeds, B, d.damping, w.tile_s.as<double>());
             NXG_CHECK_LAUNCH();
         }
         if (n_fin > 0) {
-            hipLaunchKernelGGL(k_finish_batched<1024>, dim3(n_fin), dim3(1024), lds, s, geo, ctl, cur, nxt,
+            hipLaunchKernelGGL(k_finish_batched<1024>, dim3(n_fin), dim3(1024), lds, cs, geo, ctl, cur, nxt,
                                xout, seeds, B, d.damping, w.tile_s.as<double>(), p->fin.as<Item>());
             NXG_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(k_reduce_batched1, dim3(rblocks), dim3(256), 0, s, w.tile_s.as<double>(),
+        hipLaunchKernelGGL(k_reduce_batched1, dim3(rblocks), dim3(256), 0, cs, w.tile_s.as<double>(),
                            L.n_tiles, B, rper, ctl.done, w.part.as<double>());
         NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_reduce_batched2, dim3(1), dim3(256), 0, s, w.part.as<double>(), rblocks, B,
+        hipLaunchKernelGGL(k_reduce_batched2, dim3(1), dim3(256), 0, cs, w.part.as<double>(), rblocks, B,
                            ctl);
         NXG_CHECK_LAUNCH();
     };
     Events ev;
     hipEvent_t e0 = ev.a, e1 = ev.b;
+    if (capture) {
+        // record start, the fixed iterations and the id map once (no memset in
+        // the graph: the workspace's counters were cleared at allocation and a
+        // fixed-count run never sets the stop flag), then replay
+        if (fresh) {
+            NXG_HIP(hipStreamSynchronize(s));
+            if (!g->capture_stream)
+                NXG_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+            hipStream_t cs = g->capture_stream;
+            NXG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                start(cs);
+                for (int k = 0; k < max_iters; ++k) {
+                    BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, 0.0};
+                    one_iteration(ctl, w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(),
+                                  k == max_iters - 1 ? vals : nullptr, cs);
+                }
+                if (vm) permute_rows<float>(vals, vm.o2n, vm.n, B, (float*)d.d_values, cs);
+            } catch (...) {
+                hipGraph_t dead = nullptr;
+                (void)hipStreamEndCapture(cs, &dead);
+                if (dead) (void)hipGraphDestroy(dead);
+                throw;
+            }
+            NXG_HIP(hipStreamEndCapture(cs, &cap->graph));
+            NXG_HIP(hipGraphInstantiate(&cap->exec, cap->graph, nullptr, nullptr, 0));
+        }
+        NXG_HIP(hipEventRecord(e0, s));
+        NXG_HIP(hipGraphLaunch(cap->exec, s));
+        NXG_HIP(hipEventRecord(e1, s));
+        double resid = 0.0;
+        if (st) {
+            std::vector<double> hs(nstat);
+            NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            for (int b = 0; b < B; ++b)
+                resid = std::max(resid, hs[(size_t)(max_iters - 1) * 3 * B + B + b]);
+            float ms = 0.f;
+            NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            memset(st, 0, sizeof(*st));
+            st->iterations = max_iters;
+            st->residual = resid;
+            st->device_ms = ms;
+        }
+        return NXG_OK;
+    }
+    start(s);
     NXG_HIP(hipEventRecord(e0, s));
     const int block = d.tol > 0 ? std::max(1, env_int("NXG_SYNC_BLOCK", 8)) : max_iters;
     int k = 0, done_h = 0;
@@ -2884,7 +2991,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         for (; k < kend; ++k) {
             BCtl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             float* xout = (k == max_iters - 1) ? vals : nullptr;
-            one_iteration(ctl, w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout);
+            one_iteration(ctl, w.buf[k & 1].as<float>(), w.buf[(k + 1) & 1].as<float>(), xout, s);
         }
         if (d.tol > 0 && k < max_iters) {
             NXG_HIP(hipMemcpyAsync(&done_h, w.done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -3058,27 +3165,63 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
         attr = lds;
     }
     const MultiGraph* ddesc = c->ddesc.as<MultiGraph>();
+    auto enqueue = [&](hipStream_t cs) {
+        hipLaunchKernelGGL(k_multi_init, dim3(G * kMultiBlocks), dim3(256), 0, cs, ddesc, c->dpart.as<double>());
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_multi_init_sum, dim3((G + 255) / 256), dim3(256), 0, cs, ddesc, G,
+                           c->dpart.as<double>());
+        NXG_CHECK_LAUNCH();
+        for (int k = 0; k < iters; ++k) {
+            hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, cs, ddesc,
+                               c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
+            NXG_CHECK_LAUNCH();
+            if (c->n_fin > 0) {
+                hipLaunchKernelGGL(k_multi_finish<kFinWG>, dim3(c->n_fin), dim3(kFinWG),
+                                   kFinSeg * sizeof(double), cs, ddesc, c->dfin.as<MultiFin>(), k, iters,
+                                   d.damping);
+                NXG_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, cs, ddesc, k);
+            NXG_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_multi_emit, dim3(G * kMultiBlocks), dim3(256), 0, cs, ddesc);
+        NXG_CHECK_LAUNCH();
+    };
+    if ((d.flags & NXG_RUN_CAPTURE) && (!c->exec || c->cap_damping != d.damping)) {
+        // record once on a private stream (the run has no memset: every
+        // workspace value it reads is written earlier in the same run)
+        c->drop_graph();
+        NXG_HIP(hipStreamSynchronize(s));
+        hipStream_t cs = nullptr;
+        NXG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            try {
+                enqueue(cs);
+            } catch (...) {
+                hipGraph_t dead = nullptr;
+                (void)hipStreamEndCapture(cs, &dead);
+                if (dead) (void)hipGraphDestroy(dead);
+                (void)hipStreamDestroy(cs);
+                throw;
+            }
+            err = hipStreamEndCapture(cs, &c->graph);
+        }
+        if (err == hipSuccess) err = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+        if (err != hipSuccess) {
+            c->drop_graph();
+            fail(NXG_EDEVICE, std::string("multi-graph capture: ") + hipGetErrorString(err));
+        }
+        c->cap_damping = d.damping;
+    }
     Events ev;
     hipEvent_t e0 = ev.a, e1 = ev.b;
     NXG_HIP(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_multi_init, dim3(G * kMultiBlocks), dim3(256), 0, s, ddesc, c->dpart.as<double>());
-    NXG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_multi_init_sum, dim3((G + 255) / 256), dim3(256), 0, s, ddesc, G, c->dpart.as<double>());
-    NXG_CHECK_LAUNCH();
-    for (int k = 0; k < iters; ++k) {
-        hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, s, ddesc,
-                           c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
-        NXG_CHECK_LAUNCH();
-        if (c->n_fin > 0) {
-            hipLaunchKernelGGL(k_multi_finish<kFinWG>, dim3(c->n_fin), dim3(kFinWG), kFinSeg * sizeof(double),
-                               s, ddesc, c->dfin.as<MultiFin>(), k, iters, d.damping);
-            NXG_CHECK_LAUNCH();
-        }
-        hipLaunchKernelGGL(k_multi_reduce, dim3(G), dim3(1024), 0, s, ddesc, k);
-        NXG_CHECK_LAUNCH();
-    }
-    hipLaunchKernelGGL(k_multi_emit, dim3(G * kMultiBlocks), dim3(256), 0, s, ddesc);
-    NXG_CHECK_LAUNCH();
+    if (d.flags & NXG_RUN_CAPTURE)
+        NXG_HIP(hipGraphLaunch(c->exec, s));
+    else
+        enqueue(s);
     NXG_HIP(hipEventRecord(e1, s));
     std::vector<double> res(G);
     if (st) {

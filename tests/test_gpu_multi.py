@@ -63,6 +63,30 @@ def test_multi_source_order_and_relabel(gpu_device, order, relabel):
         mg.pagerank(3, out=outs[:-1])
 
 
+@pytest.mark.parametrize("relabel", [False, True])
+def test_multi_capture_replays(gpu_device, relabel):
+    # the recorded run replays into new output buffers each time, matches the
+    # eager run, and is recorded again when the damping changes
+    gs = _graphs(10, gpu_device)
+    mg = MultiDSSS.build([(to_dev(s, gpu_device), to_dev(d, gpu_device), n) for s, d, n in gs],
+                         order="src", relabel=relabel)
+    xe, _ = mg.pagerank(20)
+    xe = [x.clone() for x in xe]
+    for rep in range(3):
+        damping = 0.85 if rep < 2 else 0.7
+        say("multi capture relabel=%d replay %d damping %.2f" % (relabel, rep, damping))
+        outs = [torch.full((n,), -1.0, dtype=torch.float32, device=gpu_device) for _, _, n in gs]
+        xc, st = mg.pagerank(20, damping=damping, out=outs, capture=True)
+        torch.cuda.synchronize()
+        assert st["iterations"] == 20
+        for i, (s, d, n) in enumerate(gs):
+            if damping == 0.85:
+                assert rel_l1(xc[i].cpu().numpy(), xe[i].cpu().numpy()) <= 1e-6, i
+            elif i % 3 == 0:
+                ref, _ = oracle.pagerank(n, s, d, iters=20, d=0.7)
+                assert rel_l1(xc[i].cpu().numpy(), ref) <= 1e-5, i
+
+
 def test_multi_persistent_flag_is_refused(gpu_device):
     gs = _graphs(2, gpu_device)
     mg = MultiDSSS.build([(to_dev(s, gpu_device), to_dev(d, gpu_device), n) for s, d, n in gs])

@@ -47,3 +47,25 @@ def test_batched_tolerance_stop(gpu_device):
     t[seeds[3]] = 1.0
     ref, res = oracle.pagerank(n, src, dst, iters=500, t=t, tol=1e-9)
     assert rel_l1(x[:, 3].cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_batched_capture_replays(gpu_device, relabel):
+    # a captured batched run replays against eager runs, also after the seed
+    # buffer's contents change (the graph reads the seeds at every replay)
+    scale, B, iters = 12, 32, 9
+    n = 1 << scale
+    src, dst = rmatgen.rmat_edges(scale, 8, seed=scale + 40)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=1024, tile=512,
+                   value_bytes=8 * B, relabel=relabel)
+    seeds = to_dev(rmatgen.distinct_vertices(61, B, n), gpu_device)
+    out = torch.empty((n, B), dtype=torch.float32, device=gpu_device)
+    for rep in range(3):
+        if rep == 2:
+            seeds.copy_(to_dev(rmatgen.distinct_vertices(62, B, n), gpu_device))
+        say("ppr capture relabel=%d replay %d" % (relabel, rep))
+        g.ppr(seeds, iters, out=out, capture=True)
+        xe, _ = g.ppr(seeds.clone(), iters)
+        torch.cuda.synchronize()
+        for b in range(B):
+            assert rel_l1(out[:, b].cpu().numpy(), xe[:, b].cpu().numpy()) <= 1e-6
