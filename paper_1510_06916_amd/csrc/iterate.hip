@@ -2723,6 +2723,40 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     std::vector<double> hs(4 * (size_t)(first_block + 2));
     bool fixed = false;
     int last_changed = 0;
+    // the values after round kk live in buf[kk & 1] (rounds past the fixed point
+    // copy): map them out, add the last round's listed chunks to the count, and
+    // form the BFS outputs (maximum level, reached edges) in two steps without
+    // atomics; the counts come back with the next synchronisation
+    unsigned long long out3[3] = {0, 0, 0};  // streamed, reached, max level
+    auto finish_work = [&](int kk) {
+        NXG_HIP(hipEventRecord(e1, s));
+        const int32_t* fin = w.buf[kk & 1].as<int32_t>();
+        if (vm) {
+            permute_rows<int32_t>(fin, vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1, bfs ? kInf : 0,
+                                  bfs ? 0 : 1);
+            if (bfs)  // a dropped root keeps level 0
+                hipLaunchKernelGGL(k_set_root, dim3(1), dim3(64), 0, s, (int32_t*)d.d_values, d.roots[0]);
+        } else {
+            hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s, fin,
+                               (int32_t*)d.d_values, (int64_t)L.n);
+        }
+        NXG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, w.ccount.as<int32_t>(), L.n_tiles,
+                           kk > 0 ? streamed : nullptr);
+        NXG_CHECK_LAUNCH();
+        if (bfs) {
+            unsigned long long* part = streamed + 3;
+            hipLaunchKernelGGL(k_bfs_final, dim3(kFinalBlocks), dim3(256), 0, s, L.n, fin,
+                               L.outdeg.as<int32_t>(), part);
+            NXG_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_bfs_final_sum, dim3(1), dim3(kFinalBlocks), 0, s, part);
+            NXG_CHECK_LAUNCH();
+            NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(out3), hipMemcpyDeviceToHost, s));
+        } else {
+            NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        }
+    };
+    bool finished = false;
     while (k < max_iters && !fixed) {
         int kend = std::min(max_iters, k + (k == 0 ? first_block : block));
         int kb = k;
@@ -2749,6 +2783,12 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                 launch_iter<ProgWCC, 1024>(geo, ctl, pr, *p, lds, s);
             }
         }
+        // after the first block the final work goes out before the host reads the
+        // changed flags (a power-law graph is settled by then), so a run that
+        // settles there needs one synchronisation; otherwise it is redone at the end
+        // (counting the streamed chunks twice is avoided: the count clears the lists)
+        const bool speculate = kb == 0;
+        if (speculate) finish_work(k);
         NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.as<double>(), sizeof(double) * 4 * (k - kb),
                                hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
@@ -2759,37 +2799,9 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             }
             last_changed = i + 1;
         }
+        finished = speculate && fixed;
     }
-    // the values after round k live in buf[k & 1]; rounds past the fixed point copy
-    NXG_HIP(hipEventRecord(e1, s));
-    const int32_t* fin = w.buf[k & 1].as<int32_t>();
-    if (vm) {
-        permute_rows<int32_t>(fin, vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1, bfs ? kInf : 0,
-                              bfs ? 0 : 1);
-        if (bfs)  // a dropped root keeps level 0
-            hipLaunchKernelGGL(k_set_root, dim3(1), dim3(64), 0, s, (int32_t*)d.d_values, d.roots[0]);
-    } else {
-        hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(L.n)), dim3(256), 0, s, fin,
-                           (int32_t*)d.d_values, (int64_t)L.n);
-    }
-    NXG_CHECK_LAUNCH();
-    // the last round's listed chunks join the count; then the BFS outputs
-    // (maximum level, reached edges) in two steps without atomics
-    hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, w.ccount.as<int32_t>(), L.n_tiles,
-                       k > 0 ? streamed : nullptr);
-    NXG_CHECK_LAUNCH();
-    unsigned long long out3[3] = {0, 0, 0};  // streamed, reached, max level
-    if (bfs) {
-        unsigned long long* part = streamed + 3;
-        hipLaunchKernelGGL(k_bfs_final, dim3(kFinalBlocks), dim3(256), 0, s, L.n, fin,
-                           L.outdeg.as<int32_t>(), part);
-        NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_bfs_final_sum, dim3(1), dim3(kFinalBlocks), 0, s, part);
-        NXG_CHECK_LAUNCH();
-        NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(out3), hipMemcpyDeviceToHost, s));
-    } else {
-        NXG_HIP(hipMemcpyAsync(out3, streamed, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    }
+    if (!finished) finish_work(k);
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
