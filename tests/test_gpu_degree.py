@@ -133,6 +133,23 @@ def test_adjoint(gpu_device):
     assert rel_l1(tt.grad.cpu().numpy(), gt_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("relabel", [False, True])
+def test_pagerank_pair_layout(gpu_device, relabel):
+    # degreeing then the pair layout: PageRank over the compacted graph, in the
+    # caller's ids
+    src, dst = _sparse_graph(63)
+    kept, o2n, s2, d2 = _compact(src, dst)
+    nk = len(kept)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), N, interval=512, tile=1024,
+                   chunk=256, degree=True, relabel=relabel, order="src", pairs=True)
+    assert g.info()["pairs"] == 1 and g.info()["n_kept"] == nk
+    ref_c, _ = oracle.pagerank(nk, s2, d2, iters=9)
+    ref = np.zeros(N)
+    ref[kept] = ref_c
+    x, _ = g.pagerank(9, dtype=torch.float64)
+    assert rel_l1(x.cpu().numpy(), ref) <= 1e-12
+
+
 def test_multi_refuses_degree(gpu_device):
     from paper_1510_06916_amd import _lib
     import ctypes
