@@ -19,6 +19,7 @@ host memory); --mode all runs every one (one JSON line each).
 import argparse
 import hashlib
 import json
+import tempfile
 import os
 import sys
 import time
@@ -97,7 +98,7 @@ def bench_pagerank(args, dev):
                 "relabel": int(args.relabel), "pairs": int(args.pairs), "candidates": 0}
     else:
         t0 = time.perf_counter()
-        os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "tune_cache.txt"))
+        os.environ.setdefault("NXG_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "nxg_tune_cache.txt"))
         os.makedirs(os.path.dirname(os.environ["NXG_TUNE_CACHE"]), exist_ok=True)
         best = tune(src, dst, n)
         log("tuned in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
@@ -496,7 +497,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the DSSS iteration runs on a single MI355X "
-              "(DESIGN.md describes how it would shard; nothing multi-GPU is built)",
+              "(nothing multi-GPU is built)",
               file=sys.stderr)
         sys.exit(2)
     import torch
