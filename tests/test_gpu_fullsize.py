@@ -28,7 +28,8 @@ def test_cfg3_pagerank_fp32_tuned_layout(gpu_device, cfg3):
     r = tune(src_d, dst_d, n)
     say("cfg3 tuned layout: %s" % r)
     g = DSSS.build(src_d, dst_d, n, interval=r["interval"], tile=r["tile"], chunk=r["chunk"],
-                   order=("dst", "src")[r["order"]], relabel=bool(r["relabel"]))
+                   order=("dst", "src")[r["order"]], relabel=bool(r["relabel"]),
+                   pairs=bool(r.get("pairs", 0)))
     pc = r["piece_chunks"]
     # one iteration from the uniform start, every vertex
     x1, _ = g.pagerank(1, dtype=torch.float32, piece_chunks=pc)
@@ -52,6 +53,32 @@ def test_cfg3_pagerank_fp32_tuned_layout(gpu_device, cfg3):
     out = torch.empty(n, dtype=torch.float32, device=gpu_device)
     xc, _ = g.pagerank(20, dtype=torch.float32, capture=True, out=out, piece_chunks=pc)
     assert rel_l1(xc.cpu().numpy(), x20h) <= 1e-6
+
+
+def test_cfg3_graph_bfs_level_properties(gpu_device, cfg3):
+    # BFS on the 1.56G-edge graph (many activity segments): levels that hold at
+    # any size -- the root at 0, no edge from a reached vertex skips a level, and
+    # every other reached vertex has an in-edge from the level before it
+    src_d, dst_d, _, _, n = cfg3
+    g = DSSS.build(src_d, dst_d, n, value_bytes=4, order="src", relabel=True)
+    s, d = src_d.long(), dst_d.long()
+    root = int(torch.argmax(torch.bincount(s, minlength=n)))
+    say("cfg3 bfs from %d" % root)
+    lev, st = g.bfs(root)
+    inf = 2**31 - 1
+    lv = lev.long()
+    ls, ld = lv[s], lv[d]
+    fin = ls != inf
+    assert int(lv[root]) == 0
+    assert bool((ld[fin] <= ls[fin] + 1).all())
+    has_parent = torch.zeros(n, dtype=torch.bool, device=gpu_device)
+    has_parent[d[fin & (ld == ls + 1)]] = True
+    reached = lv != inf
+    reached[root] = False
+    assert bool(has_parent[reached].all())
+    assert st["max_level"] == int(lv[lv != inf].max()) and st["changed_rounds"] == st["max_level"]
+    say("cfg3 bfs: %d levels, %d reached, %.2f stream passes" % (
+        st["max_level"], int(reached.sum()) + 1, st["streamed_chunks"] / g.info()["n_chunks"]))
 
 
 @pytest.fixture(scope="module")
