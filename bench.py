@@ -430,14 +430,20 @@ def bench_adjoint(args, dev):
     import numpy as np
     import torch
     import rmatgen
-    from paper_1510_06916_amd import DSSS, WeightedPageRank
+    from paper_1510_06916_amd import DSSS, WeightedPageRank, tune
     scale, ef, seed = 20, 16, 5
     n = 1 << scale
     src, dst = rmat(scale, ef, seed, dev)
     w = rmatgen.row_normalized_weights(src.cpu().numpy(), n, seed=seed + 100)
     gvec = torch.from_numpy(rmatgen.normal_f32(seed + 200, n).astype(np.float64)).to(dev)
+    # the layout the tuner picks for the weighted FP64 forward; the transposed
+    # graph of the backward takes the same geometry
+    t0 = time.perf_counter()
+    best = tune(src, dst, n, dtype=torch.float64, weights=torch.from_numpy(w))
+    log("weighted tune in %.1fs: %s" % (time.perf_counter() - t0, json.dumps(best)))
     g = DSSS.build(src, dst, n, weights=torch.from_numpy(w), transpose=True, keep_perm=True,
-                   order=args.order, relabel=bool(args.relabel))
+                   interval=best["interval"], tile=best["tile"], chunk=best["chunk"],
+                   order=("dst", "src")[best["order"]], relabel=bool(best["relabel"]))
     wt = torch.from_numpy(w).to(dev)
 
     def fwd():
@@ -466,7 +472,9 @@ def bench_adjoint(args, dev):
     res = {"metric": "weighted PageRank forward (1e-8) + adjoint backward time",
            "value": tfb * 1e3, "unit": "ms", "n_gpus": 1, "dtype": "f64", "higher_is_better": False,
            "config": {"workload": "adjoint rmat-s20-ef16 weighted", "n": n, "m": g.m,
-                      "order": args.order, "relabel": int(args.relabel), "timing": "median of 3",
+                      "order": ("dst", "src")[best["order"]], "relabel": best["relabel"],
+                      "tile": best["tile"], "interval": best["interval"], "chunk": best["chunk"],
+                      "tuned_candidates": best["candidates"], "timing": "median of 3",
                       "forward_iterations": st["iterations"], "forward_alone_ms": tf * 1e3,
                       "fwd_bwd_over_fwd": tfb / tf}}
     print(json.dumps(res), flush=True)
