@@ -162,7 +162,10 @@ typedef struct nxg_build_desc {
     int32_t interval;       /* I, interval size; P = ceil(n / I). 0 = planner's choice */
     int32_t tile;           /* destination tile size T, a power of two (tiles are the
                                vertex ranges [k*T, (k+1)*T), any T relative to I);
-                               0 = planner's choice */
+                               0 = planner's choice: the largest whose accumulators
+                               fit in LDS, halved (not below 256) until there are at
+                               least as many tiles as compute units (nxg_multi_build
+                               keeps the largest: its graphs share launches) */
     int32_t chunk;          /* edge-stream words per work chunk, power of two in
                                [256, 65536]; 0 = planner's choice */
     int32_t value_bytes;    /* bytes of one destination accumulator the tile must hold

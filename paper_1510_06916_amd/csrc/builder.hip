@@ -742,7 +742,7 @@ __global__ void k_relabel_edges(const int32_t* __restrict__ src, const int32_t* 
 
 }  // namespace
 
-void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
+void plan_geometry(const nxg_build_desc& d, int device, bool spread, Layout& L) {
     const int64_t n = d.n;
     // default: 8-byte accumulators, enough for every program (PageRank sums in
     // FP64; BFS/WCC need only 4)
@@ -790,7 +790,16 @@ void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     if (L.L > 30) fail(NXG_EINVAL, "interval too large");
     int64_t T = d.tile;
     if (T < 0 || (T & (T - 1))) fail(NXG_EINVAL, "tile must be 0 or a power of two");
-    if (T == 0) T = tmax;
+    if (T == 0) {
+        T = tmax;
+        // the planner's tile: the largest that fits, halved (down to 256) until
+        // there are at least as many tiles as compute units, so a graph of a few
+        // million vertices still occupies the whole chip (not for graphs that
+        // share launches: those fill the chip together)
+        int cus = 0;
+        if (spread && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
+            while (T > 256 && (n + T - 1) / T < cus) T >>= 1;
+    }
     if (T * vb > budget) fail(NXG_EINVAL, "tile * value_bytes exceeds the LDS of one workgroup");
     // destination tiles are global ranges [tau*T, (tau+1)*T); a tile may hold
     // several intervals (T > I) or part of one (T < I)
@@ -824,10 +833,10 @@ void plan_geometry(const nxg_build_desc& d, int device, Layout& L) {
     }
 }
 
-void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& L) {
+void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& L, bool spread) {
     int device = 0;
     NXG_HIP(hipGetDevice(&device));
-    plan_geometry(d, device, L);
+    plan_geometry(d, device, spread, L);
     const bool sym = (d.flags & NXG_BUILD_SYMMETRIZE) != 0;
     const bool dedup_req = sym || (d.flags & NXG_BUILD_DEDUP);
     const bool want_perm = (d.flags & NXG_BUILD_KEEP_PERM) != 0;

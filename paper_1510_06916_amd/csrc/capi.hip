@@ -104,7 +104,7 @@ nxg_status nxg_multi_build(int32_t count, const nxg_build_desc* descs, void* str
         nxg_multi* mg = new nxg_multi();
         try {
             for (int32_t i = 0; i < count; ++i)
-                mg->graphs.push_back(build_handle(descs[i], (hipStream_t)stream));
+                mg->graphs.push_back(build_handle(descs[i], (hipStream_t)stream, false));
         } catch (...) {
             delete mg;
             throw;
@@ -132,7 +132,7 @@ nxg_status nxg_multi_destroy(nxg_multi* mg) {
 }  // extern "C"
 
 namespace nxg {
-nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
+nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
     {
         if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
         if (d.m < 0) fail(NXG_EINVAL, "m must be >= 0");
@@ -173,7 +173,7 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
                 dd.d_dst = dst2.as<int32_t>();
                 if (dd.interval > dd.n) dd.interval = dd.n;
             }
-            build_layout(dd, false, s, g->fwd);
+            build_layout(dd, false, s, g->fwd, spread);
             if (d.flags & NXG_BUILD_HOST_STREAM) {
                 // the edge stream (and weights) move to pinned host memory
                 Layout& L = g->fwd;
@@ -191,7 +191,7 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s) {
                 L.host_stream = true;
             }
             if (d.flags & NXG_BUILD_TRANSPOSE) {
-                build_layout(dd, true, s, g->rev);
+                build_layout(dd, true, s, g->rev, spread);
                 g->has_rev = true;
             }
         } catch (...) {

@@ -225,7 +225,9 @@ struct nxg_multi {
 
 namespace nxg {
 // builder entry (builder.hip)
-void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& out);
+// spread: with no tile given, keep at least one tile per compute unit (a graph
+// that runs alone); false for the graphs of a multi-graph handle
+void build_layout(const nxg_build_desc& d, bool reversed, hipStream_t s, Layout& out, bool spread = true);
 void export_layout(const Layout& L, int64_t* d_offsets, int32_t* d_src, int32_t* d_dst,
                    int32_t* d_perm, hipStream_t s);
 // validates the ids, orders the vertices by decreasing degree and renames the edges
@@ -236,7 +238,7 @@ int32_t relabel_input(const nxg_build_desc& d, hipStream_t s, bool by_degree, bo
                       DevBuf& new2old, DevBuf& old2new, DevBuf& src2, DevBuf& dst2);
 // validated build of a whole handle, with the optional relabeling and transpose
 // (capi.hip)
-nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s);
+nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread = true);
 // runtime entry (iterate.hip)
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
