@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 7
+#define NXG_ABI_VERSION 8
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -303,6 +303,38 @@ typedef struct nxg_run_stats {
  * per-chunk id ranges their activity test reads) in the handle from the first
  * run on, so such runs on one handle must not overlap. */
 nxg_status nxg_run(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
+
+/* ------------------------------------------------------------------------- */
+/* Runs without device allocation                                             */
+/* ------------------------------------------------------------------------- */
+
+/* For callers that cannot allocate device memory during a run (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation).
+ * Same as nxg_run for single-column PageRank (NXG_PAGERANK or
+ * NXG_PAGERANK_WEIGHTED, F32 or F64, batch 1, no seeds; flags 0 or
+ * NXG_RUN_WARM_START), but the run's whole workspace -- value vectors, hub
+ * partials, per-tile scalars, statistics, and on a relabeled build the
+ * vectors in internal ids -- lives in one library-owned device array of
+ * nxg_noalloc_scratch_bytes() bytes (64 MiB), and the call makes no device
+ * allocation and no allocator callback. The caller still owns d_values and
+ * d_teleport. Each device the library runs this on keeps its own array until
+ * the process ends; its address on a device is looked up at the first call on
+ * that device (which also creates the call's two timing events). Every call on
+ * one device shares that device's array and leaves its contents there: calls
+ * that overlap on one device race, so callers must serialise them (one stream,
+ * or their own ordering). The handle must live on the current device
+ * (NXG_EINVAL otherwise) and must have the iteration plan for the run's piece
+ * size: nxg_dsss_build prepares the planner's (piece_chunks = 0); another
+ * piece size needs one earlier nxg_run with it, else NXG_EINVAL. A run whose
+ * workspace exceeds the array (about 2 * n * sizeof(value) plus hub partials,
+ * statistics of 32 bytes per iteration and, relabeled, up to 2 more vectors)
+ * is refused with NXG_EINVAL before anything is enqueued. SCATTER and
+ * HOST_STREAM handles, NXG_RUN_CAPTURE and batched runs are refused.
+ * Synchronises the stream at the end, like nxg_run. */
+nxg_status nxg_run_noalloc(nxg_dsss* g, const nxg_run_desc* desc, void* stream, nxg_run_stats* stats);
+
+/* Size in bytes of the per-device array nxg_run_noalloc works in. */
+size_t nxg_noalloc_scratch_bytes(void);
 
 /* ------------------------------------------------------------------------- */
 /* Autotuning                                                                 */

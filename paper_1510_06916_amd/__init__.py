@@ -249,6 +249,35 @@ class DSSS:
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 
+    def pagerank_noalloc(self, iters, out, damping=0.85, tol=0.0, teleport=None, x0=None,
+                         weighted=False):
+        """PageRank through nxg_run_noalloc: the library allocates nothing during
+        the call (its workspace is a per-device scratch array). out (FP32 or FP64,
+        [n], on this device) receives x and fixes the dtype; teleport, if given,
+        must already be a contiguous tensor of that dtype on this device."""
+        if out.dtype not in _DT or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous FP32/FP64 tensor on the graph's device")
+        flags = 0
+        if x0 is not None:
+            out.copy_(x0)
+            flags |= _lib.NXG_RUN_WARM_START
+        if teleport is not None and (teleport.dtype != out.dtype or not teleport.is_contiguous()
+                                     or teleport.device != self.device):
+            raise ValueError("teleport must be a contiguous tensor of out's dtype on the device")
+        d = _lib.RunDesc(program=_lib.NXG_PAGERANK_WEIGHTED if weighted else _lib.NXG_PAGERANK,
+                         dtype=_DT[out.dtype], batch=1, damping=float(damping),
+                         max_iters=int(iters), tol=float(tol),
+                         d_teleport=teleport.data_ptr() if teleport is not None else None,
+                         roots=None, d_values=out.data_ptr(), flags=flags)
+        st = _lib.RunStats()
+        with torch.cuda.device(self.device):
+            rc = _lib.check(_lib.lib().nxg_run_noalloc(self._h, ctypes.byref(d), _stream_handle(),
+                                                       ctypes.byref(st)), "nxg_run_noalloc",
+                            allow=(_lib.NXG_ENOTCONV,))
+        res = st.as_dict()
+        res["status"] = rc
+        return out, res
+
     def ppr(self, seeds, iters, damping=0.85, tol=0.0, out=None, capture=False):
         """Batched personalised PageRank: column b teleports to seeds[b]; returns
         x [n, B] FP32 (B = len(seeds) <= 64). The graph must be built with

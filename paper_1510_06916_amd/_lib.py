@@ -114,6 +114,9 @@ SIGNATURES = {
                                 ctypes.c_void_p, ctypes.POINTER(TuneResult)]),
     "nxg_pagerank_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AdjointDesc),
                                             ctypes.c_void_p, ctypes.POINTER(RunStats)]),
+    "nxg_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RunDesc), ctypes.c_void_p,
+                                       ctypes.POINTER(RunStats)]),
+    "nxg_noalloc_scratch_bytes": (ctypes.c_size_t, []),
 }
 
 _lib = None

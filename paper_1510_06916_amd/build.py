@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnxgraph.so")
-SOURCES = ["builder.hip", "iterate.hip", "tune.hip", "capi.hip", "probe.hip"]
+SOURCES = ["builder.hip", "iterate.hip", "tune.hip", "capi.hip", "probe.hip", "noalloc.hip"]
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

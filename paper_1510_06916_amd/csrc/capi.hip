@@ -36,23 +36,6 @@ void dev_free(void* p, size_t bytes, hipStream_t s) {
         (void)hipFree(p);
 }
 
-template <class F>
-nxg_status guarded(F&& f) {
-    try {
-        g_last_error.clear();
-        return f();
-    } catch (const Error& e) {
-        g_last_error = e.msg;
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return NXG_ENOMEM;
-    } catch (...) {
-        g_last_error = "unexpected internal error";
-        return NXG_EDEVICE;
-    }
-}
-
 }  // namespace nxg
 
 nxg_dsss::~nxg_dsss() {
@@ -194,6 +177,7 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
                 build_layout(dd, true, s, g->rev, spread);
                 g->has_rev = true;
             }
+            if (spread) prepare_pagerank_plan(g, s);
         } catch (...) {
             delete g;
             throw;

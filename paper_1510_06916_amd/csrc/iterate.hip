@@ -1859,6 +1859,39 @@ inline int grid_for(int64_t work, int threads = 256, int cap = 8192) {
     return (int)b;
 }
 
+// Sets n elements to v with a kernel (no memset node, so it can be captured).
+template <typename V>
+void fill(V* p, int64_t n, V v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_val<V>, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    NXG_CHECK_LAUNCH();
+}
+
+// Where a run's workspace comes from: the allocator (no arena), or a device
+// region the caller owns, carved into 256-byte aligned pieces. A measuring
+// arena touches nothing and only counts the bytes the run would take.
+struct Arena {
+    unsigned char* base = nullptr;
+    size_t cap = 0, used = 0;
+    bool measure = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // timing events the region's owner keeps
+    void take(DevBuf& b, size_t bytes) {
+        bytes = bytes ? bytes : 16;
+        const size_t off = (used + 255) & ~(size_t)255;
+        used = off + bytes;
+        if (measure) return;
+        if (used > cap) fail(NXG_EINVAL, "run workspace exceeds the scratch region");
+        b.borrow(base + off, bytes);
+    }
+};
+
+inline void take(DevBuf& b, size_t bytes, hipStream_t s, Arena* a) {
+    if (a)
+        a->take(b, bytes);
+    else
+        b.alloc(bytes, s);
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -1878,12 +1911,17 @@ int num_cus(int device) {
 // Splits every tile into pieces of at most piece_chunks chunks; heavy tiles
 // first. With whole_tiles every piece carries the tile's full chunk range (the
 // pieces then split the tile's compacted active list at run time).
-Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s,
-               bool tile_order = false) {
+Plan* find_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, bool tile_order) {
     for (Plan* p : g->plans)
         if (p->layout == &L && p->piece_chunks == piece_chunks && p->whole_tiles == whole_tiles &&
             p->tile_order == tile_order)
             return p;
+    return nullptr;
+}
+
+Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s,
+               bool tile_order = false) {
+    if (Plan* q = find_plan(g, L, piece_chunks, whole_tiles, tile_order)) return q;
     Plan* p = new Plan();
     p->layout = &L;
     p->tile_order = tile_order;
@@ -2210,18 +2248,20 @@ Geo make_geo(const Layout& L, const Plan& p, Workspace& w, size_t ab) {
 size_t iter_lds(const Geo&, const Layout& L, size_t ab) { return ((size_t)L.T + kSpill) * ab; }
 
 void alloc_common(Workspace& w, const Layout& L, const Plan& p, size_t vb, int max_iters,
-                  hipStream_t s, bool min_identity) {
+                  hipStream_t s, bool min_identity, Arena* a = nullptr) {
     // one tile-sized partial per piece of a split tile (written before read)
     (void)min_identity;
     const int64_t hub_elems = (int64_t)std::max(p.n_slots, 1) * L.T;
-    w.partial.alloc((size_t)hub_elems * vb, s);
+    take(w.partial, (size_t)hub_elems * vb, s, a);
     const size_t slots = (size_t)L.n_tiles + p.h_fseg.size();
-    w.tile_s.alloc(sizeof(double) * 3 * slots, s);
-    w.tile_flag.alloc(sizeof(int32_t) * slots, s);
-    w.stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
-    NXG_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(double) * 4 * (size_t)(max_iters + 2), s));
-    w.done.alloc(sizeof(int32_t), s);
-    NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
+    take(w.tile_s, sizeof(double) * 3 * slots, s, a);
+    take(w.tile_flag, sizeof(int32_t) * slots, s, a);
+    take(w.stats, sizeof(double) * 4 * (size_t)(max_iters + 2), s, a);
+    take(w.done, sizeof(int32_t), s, a);
+    if (a && a->measure) return;
+    // stats and the stop flag start at zero (scratch memory keeps the last run's)
+    fill<double>(w.stats.as<double>(), 4 * (int64_t)(max_iters + 2), 0.0, s);
+    fill<int32_t>(w.done.as<int32_t>(), 1, 0, s);
 }
 
 // A PageRank run recorded into a hipGraph (NXG_RUN_CAPTURE) with the
@@ -2476,8 +2516,56 @@ nxg_status run_scatter(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     return (d.tol > 0 && !conv) ? NXG_ENOTCONV : NXG_OK;
 }
 
+// The workspace of one PageRank run (allocated, carved out of an arena, or
+// only measured by a measuring arena).
 template <typename V>
-nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+void pr_workspace(Workspace& w, const Layout& L, const Plan& p, int max_iters, bool relabeled,
+                  bool tele, hipStream_t s, Arena* a) {
+    alloc_common(w, L, p, sizeof(double), max_iters, s, false, a);
+    take(w.buf[0], sizeof(V) * (size_t)L.n, s, a);
+    take(w.buf[1], sizeof(V) * (size_t)L.n, s, a);
+    take(w.part, sizeof(double) * grid_for(L.n, 256, 1024), s, a);
+    if (relabeled) {
+        take(w.mvals, sizeof(V) * (size_t)L.n, s, a);
+        if (tele) take(w.mtele, sizeof(V) * (size_t)L.n, s, a);
+    }
+}
+
+// First iteration (of iters) whose residual met tol, or -1; *resid receives the
+// residual of the last iteration counted. Reads the device stats in blocks into
+// a fixed host array.
+int first_converged(const double* d_stats, int iters, double tol, hipStream_t s, double* resid) {
+    constexpr int kBlk = 64;
+    double h[4 * kBlk];
+    int conv = -1;
+    *resid = 0.0;
+    if (iters <= 0) return conv;
+    if (tol <= 0) {  // no stop test: only the last residual
+        NXG_HIP(hipMemcpyAsync(h, d_stats + 4 * (size_t)(iters - 1) + 1, sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        *resid = h[0];
+        return conv;
+    }
+    for (int i0 = 0; i0 < iters; i0 += kBlk) {
+        const int cnt = std::min(kBlk, iters - i0);
+        NXG_HIP(hipMemcpyAsync(h, d_stats + 4 * (size_t)i0, sizeof(double) * 4 * cnt,
+                               hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < cnt; ++j) {
+            *resid = h[4 * j + 1];
+            if (h[4 * j + 1] <= tol) return i0 + j;
+        }
+    }
+    return conv;
+}
+
+// PageRank (plain or weighted) run. With an arena the workspace is carved out of
+// the arena's region and the run allocates nothing: the plan must already exist
+// and the arena supplies the timing events.
+template <typename V>
+nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st,
+                        Arena* arena = nullptr) {
     const Layout& L = g->fwd;
     const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
     if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
@@ -2491,6 +2579,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * ab, cus);
     std::unique_ptr<Streamer> str;
     if (L.host_stream) {
+        if (arena) fail(NXG_EINVAL, "a HOST_STREAM handle cannot run without allocating");
         if (d.flags & NXG_RUN_CAPTURE) fail(NXG_EINVAL, "HOST_STREAM runs cannot be captured");
         // staging buffer size; pieces never exceed one buffer
         const int64_t mb = std::max(1, env_int("NXG_STREAM_MB", 256));
@@ -2500,24 +2589,38 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         Plan* sp = get_plan(g, L, piece, false, s, true);
         str->init(L, *sp, cap, s);
     } else if (d.flags & NXG_RUN_CAPTURE) {
+        if (arena) fail(NXG_EINVAL, "NXG_RUN_CAPTURE is not available without allocating");
         return run_pagerank_captured<V>(g, d, s, st, piece);
     }
-    Plan* p = get_plan(g, L, piece, false, s, L.host_stream);
-    Workspace w;
+    Plan* p = nullptr;
+    if (arena) {
+        p = find_plan(g, L, piece, false, false);
+        if (!p)
+            fail(NXG_EINVAL, "no iteration plan for " + std::to_string(piece) +
+                                 " chunks per piece on this handle (the build prepares the "
+                                 "planner's; run nxg_run once with this piece size first)");
+    } else {
+        p = get_plan(g, L, piece, false, s, L.host_stream);
+    }
     const int max_iters = d.max_iters;
-    alloc_common(w, L, *p, ab, max_iters, s, false);
-    w.buf[0].alloc(vb * (L.n), s);
-    w.buf[1].alloc(vb * (L.n), s);
-    const int nb = grid_for(L.n, 256, 1024);
-    w.part.alloc(sizeof(double) * nb, s);
     // a relabeled build works on copies in internal ids
     const VMap vm = vmap_of(g);
+    Workspace w;
+    if (arena) {
+        Arena probe;
+        probe.measure = true;
+        pr_workspace<V>(w, L, *p, max_iters, (bool)vm, d.d_teleport != nullptr, s, &probe);
+        if (probe.used > arena->cap)
+            fail(NXG_EINVAL, "the run needs " + std::to_string(probe.used) +
+                                 " bytes of workspace; the scratch region holds " +
+                                 std::to_string(arena->cap));
+    }
+    pr_workspace<V>(w, L, *p, max_iters, (bool)vm, d.d_teleport != nullptr, s, arena);
+    const int nb = grid_for(L.n, 256, 1024);
     const V* tele = (const V*)d.d_teleport;
     V* vals = (V*)d.d_values;
     if (vm) {
-        w.mvals.alloc(vb * L.n, s);
         if (tele) {
-            w.mtele.alloc(vb * L.n, s);
             permute_rows<V>(tele, vm.n2o, L.n, 1, w.mtele.as<V>(), s);
             tele = w.mtele.as<V>();
         }
@@ -2533,9 +2636,16 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     NXG_CHECK_LAUNCH();
     Geo geo = make_geo(L, *p, w, ab);
     const size_t lds = iter_lds(geo, L, ab);
-    const int n_items = (int)p->h_items.size();
-    Events ev;
-    hipEvent_t e0 = ev.a, e1 = ev.b;
+    std::unique_ptr<Events> ev;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (arena) {
+        e0 = arena->e0;
+        e1 = arena->e1;
+    } else {
+        ev.reset(new Events());
+        e0 = ev->a;
+        e1 = ev->b;
+    }
     NXG_HIP(hipEventRecord(e0, s));
     int k = 0;
     int done_h = 0;
@@ -2571,7 +2681,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
             // x = gathered value * outdeg; reuse the carry-over path of the kernel
             Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), k, d.tol};
             ProgPR<V> pr{cur, w.buf[(k + 1) & 1].as<V>(), nullptr, vals, d.damping};
-            NXG_HIP(hipMemsetAsync(w.done.p, 0xFF, sizeof(int32_t), s));
+            fill<int32_t>(w.done.as<int32_t>(), 1, -1, s);
             launch_plain_pr<V>(L, geo, ctl, pr, *p, lds, s);
         }
         NXG_CHECK_LAUNCH();
@@ -2580,34 +2690,24 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     NXG_HIP(hipEventRecord(e1, s));
     nxg_status rc = NXG_OK;
     if (st || d.tol > 0) {
-        std::vector<double> hs(4 * (size_t)(max_iters + 2));
-        NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * hs.size(),
-                               hipMemcpyDeviceToHost, s));
-        NXG_HIP(hipStreamSynchronize(s));
-        int iters = k;
+        double resid = 0.0;
         // with early exit the kernels after convergence only carried data over
-        int conv_at = -1;
-        for (int i = 0; i < iters; ++i)
-            if (d.tol > 0 && hs[4 * i + 1] <= d.tol) {
-                conv_at = i;
-                break;
-            }
-        if (conv_at >= 0) iters = conv_at + 1;
+        const int conv_at = first_converged(w.stats.as<double>(), k, d.tol, s, &resid);
+        const int iters = conv_at >= 0 ? conv_at + 1 : k;
         float ms = 0.f;
         NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (st) {
             memset(st, 0, sizeof(*st));
             st->iterations = iters;
             st->converged = conv_at >= 0 ? 1 : 0;
-            st->residual = iters > 0 ? hs[4 * (iters - 1) + 1] : 0.0;
+            st->residual = iters > 0 ? resid : 0.0;
             st->device_ms = ms;
         }
         if (d.tol > 0 && conv_at < 0) rc = NXG_ENOTCONV;
     }
-    if (!st && d.tol <= 0) {
-        // buffers are released through the allocator on the same stream, so
-        // stream-ordered allocators see the frees after the kernels
-    }
+    // the buffers are released through the allocator on the same stream (so
+    // stream-ordered allocators see the frees after the kernels); a carved
+    // workspace is not released at all
     NXG_HIP(hipStreamSynchronize(s));
     return rc;
 }
@@ -3462,6 +3562,39 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         default:
             fail(NXG_EINVAL, "unknown program");
     }
+}
+
+nxg_status run_pagerank_in(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st,
+                           void* region, size_t cap, hipEvent_t e0, hipEvent_t e1) {
+    if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
+    if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    if (d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED)
+        fail(NXG_EUNSUPPORTED, "only PageRank runs without allocating");
+    if (d.batch > 1 || d.d_seeds) fail(NXG_EUNSUPPORTED, "batched runs allocate; run them through nxg_run");
+    if (d.batch != 1 && d.batch != 0) fail(NXG_EINVAL, "batch must be >= 1");
+    if (d.flags & ~(uint32_t)NXG_RUN_WARM_START)
+        fail(NXG_EINVAL, "only NXG_RUN_WARM_START is accepted without allocating");
+    if ((g->flags & NXG_BUILD_SCATTER) || g->fwd.host_stream)
+        fail(NXG_EINVAL, "SCATTER and HOST_STREAM handles cannot run without allocating");
+    if (g->fwd.pairs && d.program != NXG_PAGERANK) fail(NXG_EINVAL, "a PAIRS handle runs plain PageRank only");
+    if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+    Arena a;
+    a.base = static_cast<unsigned char*>(region);
+    a.cap = cap;
+    a.e0 = e0;
+    a.e1 = e1;
+    if (d.dtype == NXG_F32) return run_pagerank<float>(g, d, s, st, &a);
+    if (d.dtype == NXG_F64) return run_pagerank<double>(g, d, s, st, &a);
+    fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
+}
+
+void prepare_pagerank_plan(nxg_dsss* g, hipStream_t s) {
+    const Layout& L = g->fwd;
+    if (L.host_stream || (g->flags & NXG_BUILD_SCATTER)) return;
+    if (((size_t)L.T + kSpill) * sizeof(double) > (size_t)lds_budget_bytes(g->device)) return;
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * sizeof(double), num_cus(g->device));
+    (void)get_plan(g, L, piece, false, s);
 }
 
 }  // namespace nxg

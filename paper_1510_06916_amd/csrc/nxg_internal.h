@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,24 @@ void set_last_error(const std::string& msg);
 
 #define NXG_CHECK_LAUNCH() NXG_HIP(hipGetLastError())
 
+// Runs an entry point's body and turns what it throws into a status.
+template <class F>
+nxg_status guarded(F&& f) {
+    try {
+        set_last_error(std::string());
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return NXG_ENOMEM;
+    } catch (...) {
+        set_last_error("unexpected internal error");
+        return NXG_EDEVICE;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Device memory through the caller-settable allocator.
 // ---------------------------------------------------------------------------
@@ -43,6 +62,7 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
+    bool owned = true;  // false: a view of memory someone else owns (never freed here)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -53,8 +73,10 @@ struct DevBuf {
             p = o.p;
             bytes = o.bytes;
             stream = o.stream;
+            owned = o.owned;
             o.p = nullptr;
             o.bytes = 0;
+            o.owned = true;
         }
         return *this;
     }
@@ -65,10 +87,18 @@ struct DevBuf {
         bytes = b ? b : 16;
         p = dev_alloc(bytes, s);
     }
+    // a view of `b` bytes at q (memory owned elsewhere)
+    void borrow(void* q, size_t b) {
+        reset();
+        p = q;
+        bytes = b;
+        owned = false;
+    }
     void reset() {
-        if (p) dev_free(p, bytes, stream);
+        if (p && owned) dev_free(p, bytes, stream);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     template <class T>
     T* as() const {
@@ -241,6 +271,13 @@ int32_t relabel_input(const nxg_build_desc& d, hipStream_t s, bool by_degree, bo
 nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread = true);
 // runtime entry (iterate.hip)
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st);
+// PageRank with its whole workspace carved out of the device region [region,
+// region + cap) and the given timing events: allocates nothing (iterate.hip)
+nxg_status run_pagerank_in(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st,
+                           void* region, size_t cap, hipEvent_t e0, hipEvent_t e1);
+// the iteration plan PageRank runs use by default, made at build time so that a
+// run without allocation finds it (iterate.hip)
+void prepare_pagerank_plan(nxg_dsss* g, hipStream_t s);
 nxg_status pagerank_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nxg_run_stats* st);
 void dsss_set_weights(nxg_dsss* g, const float* d_w, hipStream_t s);
 nxg_status tune(const nxg_build_desc& desc, int program, int dtype, int batch, hipStream_t s,
