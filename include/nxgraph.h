@@ -129,6 +129,14 @@ nxg_status nxg_read_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                                      nxg_multi_build; nxg_dsss_export and
                                      nxg_dsss_set_weights refuse such a handle. */
 
+#define NXG_BUILD_SHUFFLE_SCHEDULE 0x200u /* debug: the work items of every run (tile
+                                     pieces) and the finishing segments of split tiles
+                                     are issued in a seeded random order instead of
+                                     heaviest first. Results do not depend on the
+                                     order (BFS/WCC bit-identical, PageRank equal up to
+                                     the rounding of sums taken in another order):
+                                     the sub-shards of one destination interval can be
+                                     processed in any order (Sec. II-A) */
 #define NXG_BUILD_PAIRS 0x100u    /* source-order sub-shards (NXG_ORDER_SRC) with the
                                      edges of one source into one destination tile
                                      packed two to a word: a header word names the
@@ -278,6 +286,14 @@ typedef struct nxg_run_desc {
     int32_t piece_chunks;   /* chunks per workgroup piece of a destination tile (0 = planner);
                                larger tiles are split, and a second launch sums the
                                pieces' partials in piece order (two phases) */
+    double* d_stats;        /* single-column PageRank only (else NULL): device
+                               [4 * max_iters] FP64 written on the stream at the end of
+                               the run (also by every replay of a captured one), so
+                               statistics need no host synchronisation. Entry 4k+0 is
+                               the dangling mass entering iteration k (Alg. 1's
+                               scalar), 4k+1 the residual ||x^{k+1} - x^k||_1, 4k+2
+                               sum(x^{k+1}), 4k+3 unused (0); iterations after a
+                               tolerance stop read 0. NULL = not written */
 } nxg_run_desc;
 
 typedef struct nxg_run_stats {

@@ -117,7 +117,7 @@ class DSSS:
     def build(cls, src, dst, n, P=None, interval=None, weights=None, tile=0, chunk=0,
               value_bytes=0, keep_perm=False, transpose=False, symmetrize=False, dedup=False,
               order="dst", relabel=False, scatter=False, degree=False, host_stream=False,
-              pairs=False, stream=None):
+              pairs=False, shuffle_schedule=False, stream=None):
         """scatter=True builds the coarse-grained source-sorted layout
         (NXG_BUILD_SCATTER) that only pagerank(..., scatter=True) runs.
         degree=True drops the ids that appear in no edge (NXG_BUILD_DEGREE);
@@ -125,7 +125,8 @@ class DSSS:
         edge stream in pinned host memory and streams it every iteration
         (NXG_BUILD_HOST_STREAM; PageRank only). pairs=True (with order="src")
         packs two destinations of one source per word (NXG_BUILD_PAIRS; plain
-        PageRank only)."""
+        PageRank only). shuffle_schedule=True issues the work items in a seeded
+        random order (NXG_BUILD_SHUFFLE_SCHEDULE, a debug check of order freedom)."""
         install_torch_allocator()
         src = _dev_i32(src, "src")
         dst = _dev_i32(dst, "dst")
@@ -147,7 +148,8 @@ class DSSS:
                  (_lib.NXG_BUILD_SCATTER if scatter else 0) |
                  (_lib.NXG_BUILD_DEGREE if degree else 0) |
                  (_lib.NXG_BUILD_HOST_STREAM if host_stream else 0) |
-                 (_lib.NXG_BUILD_PAIRS if pairs else 0))
+                 (_lib.NXG_BUILD_PAIRS if pairs else 0) |
+                 (_lib.NXG_BUILD_SHUFFLE_SCHEDULE if shuffle_schedule else 0))
         d = _lib.BuildDesc(n=n, m=src.numel(), d_src=src.data_ptr() if src.numel() else None,
                            d_dst=dst.data_ptr() if dst.numel() else None,
                            d_weight=w.data_ptr() if w is not None else None,
@@ -223,7 +225,14 @@ class DSSS:
         return out
 
     def pagerank(self, iters, damping=0.85, dtype=torch.float32, tol=0.0, teleport=None,
-                 x0=None, weighted=False, out=None, capture=False, piece_chunks=0, scatter=False):
+                 x0=None, weighted=False, out=None, capture=False, piece_chunks=0, scatter=False,
+                 stats_out=None):
+        """stats_out: optional FP64 device tensor of 4 * iters entries that the run
+        (and every replay of a captured one) fills with the per-iteration
+        statistics (dangling mass, residual, sum of x, 0) without a host sync.
+        capture=True records the run into a hipGraph kept by the handle (at most
+        8 per handle, least recently used released first), replayed when a
+        later call passes the same buffers."""
         n = self.n
         if dtype not in _DT:
             raise ValueError("dtype must be float32 or float64")
@@ -238,14 +247,19 @@ class DSSS:
         if scatter:
             flags |= _lib.NXG_RUN_SCATTER
         if capture:
+            # a recorded graph reads and writes the buffers at the addresses it was
+            # recorded with; it is only replayed for a call passing those addresses
             flags |= _lib.NXG_RUN_CAPTURE
-            self._keep = getattr(self, "_keep", [])
-            self._keep += [x, tp]  # captured graphs hold these pointers
+        if stats_out is not None and (stats_out.dtype != torch.float64 or not stats_out.is_contiguous()
+                                      or stats_out.numel() < 4 * int(iters)
+                                      or stats_out.device != self.device):
+            raise ValueError("stats_out must be a contiguous FP64 device tensor of 4 * iters entries")
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK_WEIGHTED if weighted else _lib.NXG_PAGERANK,
                          dtype=_DT[dtype], batch=1, damping=float(damping),
                          max_iters=int(iters), tol=float(tol),
                          d_teleport=tp.data_ptr() if tp is not None else None, roots=None,
-                         d_values=x.data_ptr(), flags=flags, piece_chunks=int(piece_chunks))
+                         d_values=x.data_ptr(), flags=flags, piece_chunks=int(piece_chunks),
+                         d_stats=stats_out.data_ptr() if stats_out is not None else None)
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 
@@ -292,8 +306,6 @@ class DSSS:
         flags = 0
         if capture:
             flags |= _lib.NXG_RUN_CAPTURE
-            self._keep = getattr(self, "_keep", [])
-            self._keep += [x, seeds]  # captured graphs hold these pointers
         d = _lib.RunDesc(program=_lib.NXG_PAGERANK, dtype=_lib.NXG_F32, batch=B,
                          damping=float(damping), max_iters=int(iters), tol=float(tol),
                          d_teleport=None, roots=None, d_values=x.data_ptr(), flags=flags,
@@ -355,7 +367,9 @@ class WeightedPageRank(torch.autograd.Function):
     """x* = WeightedPageRank.apply(w, t, dsss, damping, tol, max_iters).
 
     Forward: stores w (input edge order) in the DSSS and iterates weighted
-    PageRank in FP64 to ||x^{k+1} - x^k||_1 <= tol. Only x* is saved. Backward:
+    PageRank in FP64 to ||x^{k+1} - x^k||_1 <= tol. Only x* is saved (with a
+    reference to the input w, put back into the handle if another forward has
+    stored other weights since). Backward:
     the hand-written adjoint over the transposed sub-shards returns dL/dw (the
     given weights, no renormalisation) and dL/dt. The DSSS must be built with
     weights, transpose=True, keep_perm=True.
@@ -369,7 +383,9 @@ class WeightedPageRank(torch.autograd.Function):
         if st["status"] != _lib.NXG_OK:
             raise RuntimeError("weighted PageRank did not reach tol=%g in %d iterations"
                                % (tol, max_iters))
-        ctx.save_for_backward(x)
+        # x* is the only computed state kept; w is the caller's own input, held
+        # to restore the stored weights if the handle was given others since
+        ctx.save_for_backward(x, w)
         ctx.dsss = dsss
         ctx.version = dsss.weights_version
         ctx.damping = damping
@@ -382,9 +398,11 @@ class WeightedPageRank(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, w = ctx.saved_tensors
         if ctx.dsss.weights_version != ctx.version:
-            raise RuntimeError("DSSS weights changed between forward and backward")
+            # another forward stored other weights in the handle: put these back
+            ctx.dsss.set_weights(w)
+            ctx.version = ctx.dsss.weights_version
         _, gw, gt, _ = ctx.dsss.pagerank_adjoint(x, gx, damping=ctx.damping, tol=ctx.adj_tol,
                                                  max_iters=ctx.max_iters)
         gt_out = gt.to(ctx.t_dtype) if ctx.t_dtype is not None else None

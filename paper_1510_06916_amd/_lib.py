@@ -18,6 +18,7 @@ NXG_BUILD_SCATTER = 0x20
 NXG_BUILD_DEGREE = 0x40
 NXG_BUILD_HOST_STREAM = 0x80
 NXG_BUILD_PAIRS = 0x100
+NXG_BUILD_SHUFFLE_SCHEDULE = 0x200
 
 NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
@@ -53,7 +54,7 @@ class RunDesc(ctypes.Structure):
                 ("tol", ctypes.c_double), ("d_teleport", ctypes.c_void_p),
                 ("roots", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("d_seeds", ctypes.c_void_p),
-                ("piece_chunks", ctypes.c_int32)]
+                ("piece_chunks", ctypes.c_int32), ("d_stats", ctypes.c_void_p)]
 
 
 class RunStats(ctypes.Structure):

@@ -125,7 +125,8 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
         if (d.m > 0 && (!d.d_src || !d.d_dst)) fail(NXG_EINVAL, "d_src/d_dst is NULL");
         if (d.flags & ~(uint32_t)(NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |
                                   NXG_BUILD_DEDUP | NXG_BUILD_RELABEL | NXG_BUILD_SCATTER |
-                                  NXG_BUILD_DEGREE | NXG_BUILD_HOST_STREAM | NXG_BUILD_PAIRS))
+                                  NXG_BUILD_DEGREE | NXG_BUILD_HOST_STREAM | NXG_BUILD_PAIRS |
+                                  NXG_BUILD_SHUFFLE_SCHEDULE))
             fail(NXG_EINVAL, "unknown build flag");
         if ((d.flags & NXG_BUILD_PAIRS) &&
             (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE | NXG_BUILD_SYMMETRIZE |

@@ -1813,18 +1813,28 @@ __global__ __launch_bounds__(256) void k_init_batched(int32_t n, int B, const in
     (void)part;
 }
 
-// delta^0[b] = sum over dangling v of x^0[v][b]: one thread per column.
-__global__ void k_init_batched_delta(int32_t n, int B, const int32_t* __restrict__ deg,
-                                     const int32_t* __restrict__ seeds, double* __restrict__ stats) {
-    const int b = threadIdx.x;
-    if (b >= B) return;
+// delta^0[b] = sum over dangling v of x^0[v][b]. One-hot columns read their
+// seed's degree; uniform columns all get (dangling vertices) / n, counted by
+// the workgroup's 1024 threads over coalesced strides and summed in LDS (an
+// integer count, so the order of the additions does not matter).
+__global__ __launch_bounds__(1024) void k_init_batched_delta(int32_t n, int B, const int32_t* __restrict__ deg,
+                                                             const int32_t* __restrict__ seeds,
+                                                             double* __restrict__ stats) {
     if (seeds) {
-        stats[b] = deg[seeds[b]] == 0 ? 1.0 : 0.0;
-    } else {
-        // uniform: (number of dangling vertices) / n, counted by this thread
-        int64_t cnt = 0;
-        for (int64_t v = 0; v < n; ++v) cnt += deg[v] == 0;
-        stats[b] = (double)cnt / n;
+        if (threadIdx.x < B) stats[threadIdx.x] = deg[seeds[threadIdx.x]] == 0 ? 1.0 : 0.0;
+        return;
+    }
+    __shared__ unsigned long long part[16];
+    unsigned long long cnt = 0;
+    for (int64_t v = threadIdx.x; v < n; v += 1024) cnt += deg[v] == 0 ? 1ull : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x < B) {
+        unsigned long long tot = 0;
+        for (int w = 0; w < 16; ++w) tot += part[w];
+        stats[threadIdx.x] = (double)tot / n;
     }
 }
 
@@ -1911,6 +1921,69 @@ int num_cus(int device) {
 // Splits every tile into pieces of at most piece_chunks chunks; heavy tiles
 // first. With whole_tiles every piece carries the tile's full chunk range (the
 // pieces then split the tile's compacted active list at run time).
+// Fisher-Yates shuffle driven by splitmix64 (a fixed, seeded order).
+template <class T>
+void shuffle_items(std::vector<T>& v, uint64_t seed) {
+    uint64_t x = seed;
+    for (size_t i = v.size(); i > 1; --i) {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        std::swap(v[i - 1], v[(size_t)(z % i)]);
+    }
+}
+
+// A cache entry added to a handle before it is complete: if an error is thrown
+// while it is being set up, it is taken out again, so no later run finds it
+// half made.
+struct PendingEntry {
+    nxg_dsss* g;
+    Cached* c;
+    PendingEntry(nxg_dsss* g_, Cached* c_) : g(g_), c(c_) {}
+    PendingEntry(const PendingEntry&) = delete;
+    PendingEntry& operator=(const PendingEntry&) = delete;
+    ~PendingEntry() {
+        if (!c) return;
+        auto it = std::find(g->cached.begin(), g->cached.end(), c);
+        if (it != g->cached.end()) g->cached.erase(it);
+        delete c;
+    }
+    void commit() { c = nullptr; }
+};
+
+// Captured runs kept per handle and kind; a new capture beyond this releases
+// the least recently used one of its kind.
+constexpr int kMaxCaptures = 8;
+
+// Moves cached entry e to the back of the handle's list (most recently used).
+void touch_cached(nxg_dsss* g, Cached* e) {
+    auto it = std::find(g->cached.begin(), g->cached.end(), e);
+    if (it != g->cached.end()) {
+        g->cached.erase(it);
+        g->cached.push_back(e);
+    }
+}
+
+// Before a new capture of kind C: if the handle already keeps kMaxCaptures of
+// them, releases the least recently used (after the device has drained, since
+// its graph may still be running on some stream).
+template <class C>
+void evict_captures(nxg_dsss* g) {
+    int cnt = 0;
+    for (Cached* c : g->cached)
+        if (dynamic_cast<C*>(c)) ++cnt;
+    if (cnt < kMaxCaptures) return;
+    NXG_HIP(hipDeviceSynchronize());
+    for (auto it = g->cached.begin(); it != g->cached.end(); ++it)
+        if (dynamic_cast<C*>(*it)) {
+            delete *it;
+            g->cached.erase(it);
+            return;
+        }
+}
+
 Plan* find_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, bool tile_order) {
     for (Plan* p : g->plans)
         if (p->layout == &L && p->piece_chunks == piece_chunks && p->whole_tiles == whole_tiles &&
@@ -1922,7 +1995,8 @@ Plan* find_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles
 Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles, hipStream_t s,
                bool tile_order = false) {
     if (Plan* q = find_plan(g, L, piece_chunks, whole_tiles, tile_order)) return q;
-    Plan* p = new Plan();
+    std::unique_ptr<Plan> owner(new Plan());  // released to the handle once complete
+    Plan* p = owner.get();
     p->layout = &L;
     p->tile_order = tile_order;
     p->piece_chunks = piece_chunks;
@@ -1960,6 +2034,9 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
             int64_t wb = np_whole ? (b.c1 - b.c0) / b.npieces : b.c1 - b.c0;
             return wa > wb;
         });
+        // debug schedule: the work items (and below the finishing segments) in a
+        // seeded random order instead, to show the results do not depend on it
+        if (g->flags & NXG_BUILD_SHUFFLE_SCHEDULE) shuffle_items(items, 0x9E3779B97F4A7C15ull ^ items.size());
     }
     p->h_items = items;
     p->n_slots = slots;
@@ -1987,12 +2064,18 @@ Plan* get_plan(nxg_dsss* g, const Layout& L, int piece_chunks, bool whole_tiles,
             p->h_fseg.push_back(f);
         }
     }
+    if (g->flags & NXG_BUILD_SHUFFLE_SCHEDULE) {
+        // segments in a random order; their scalar slots keep the segment order,
+        // so a segment's slot moves with it
+        shuffle_items(p->h_fseg, 0xD1B54A32D192ED03ull ^ p->h_fseg.size());
+        for (size_t i = 0; i < p->h_fseg.size(); ++i) p->h_fseg[i].sslot = L.n_tiles + (int32_t)i;
+    }
     p->fseg.alloc(sizeof(FinSeg) * std::max<size_t>(p->h_fseg.size(), 1), s);
     if (!p->h_fseg.empty())
         NXG_HIP(hipMemcpyAsync(p->fseg.p, p->h_fseg.data(), sizeof(FinSeg) * p->h_fseg.size(),
                                hipMemcpyHostToDevice, s));
     NXG_HIP(hipStreamSynchronize(s));
-    g->plans.push_back(p);
+    g->plans.push_back(owner.release());
     return p;
 }
 
@@ -2272,6 +2355,7 @@ struct CapturedPR : Cached {
     double damping = 0.0;
     const void* values = nullptr;
     const void* tele = nullptr;
+    const void* stats_out = nullptr;
     Workspace w;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -2298,6 +2382,15 @@ struct CapturedBatched : Cached {
         if (graph) (void)hipGraphDestroy(graph);
     }
 };
+
+// The run's per-iteration statistics into the caller's device buffer (if any).
+void copy_stats_out(const Workspace& w, const nxg_run_desc& d, hipStream_t s) {
+    if (!d.d_stats || d.max_iters < 1) return;
+    const int64_t cnt = 4 * (int64_t)d.max_iters;
+    hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(cnt)), dim3(256), 0, s, w.stats.as<double>(),
+                       d.d_stats, cnt);
+    NXG_CHECK_LAUNCH();
+}
 
 // Enqueues x^0 and max_iters iterations of (weighted) PageRank; no syncs.
 template <typename V>
@@ -2337,6 +2430,7 @@ void enqueue_pagerank(const Layout& L, const Plan& p, Workspace& w, const nxg_ru
         }
     }
     if (vm) permute_rows<V>(vals, vm.o2n, vm.n, 1, (V*)d.d_values, s);
+    copy_stats_out(w, d, s);
 }
 
 template <typename V>
@@ -2351,12 +2445,14 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         CapturedPR* r = dynamic_cast<CapturedPR*>(c);
         if (r && r->program == d.program && r->dtype == d.dtype && r->iters == d.max_iters &&
             r->piece == piece && r->flags == d.flags && r->damping == d.damping &&
-            r->values == d.d_values && r->tele == d.d_teleport) {
+            r->values == d.d_values && r->tele == d.d_teleport && r->stats_out == d.d_stats) {
             e = r;
             break;
         }
     }
+    if (e) touch_cached(g, e);
     if (!e) {
+        evict_captures<CapturedPR>(g);
         Plan* p = get_plan(g, L, piece, false, s);
         std::unique_ptr<CapturedPR> n(new CapturedPR());
         n->program = d.program;
@@ -2367,6 +2463,7 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
         n->damping = d.damping;
         n->values = d.d_values;
         n->tele = d.d_teleport;
+        n->stats_out = d.d_stats;
         Workspace& w = n->w;
         alloc_common(w, L, *p, sizeof(double), d.max_iters, s, false);
         w.buf[0].alloc(sizeof(V) * (L.n), s);
@@ -2687,6 +2784,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         NXG_CHECK_LAUNCH();
     }
     if (vm) permute_rows<V>(vals, vm.o2n, vm.n, 1, (V*)d.d_values, s);
+    copy_stats_out(w, d, s);
     NXG_HIP(hipEventRecord(e1, s));
     nxg_status rc = NXG_OK;
     if (st || d.tol > 0) {
@@ -2767,6 +2865,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if (!c) {
         c = new MinprogCache();
         g->cached.push_back(c);
+        PendingEntry pend(g, c);
         c->bfs = bfs;
         c->piece = piece;
         c->block = first_block;
@@ -2790,6 +2889,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         // streamed-chunk count, reached edges, maximum level, then the BFS
         // outputs' per-block partials
         w.bfsout.alloc(sizeof(unsigned long long) * (3 + 2 * kFinalBlocks), s);
+        pend.commit();
     }
     Workspace& w = c->w;
     const int bs = c->bs, seg = c->seg, nseg = c->nseg;
@@ -2943,6 +3043,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     // a captured run keeps its workspace (and graph) in the handle
     CapturedBatched* cap = nullptr;
     bool fresh = true;
+    PendingEntry pend(g, nullptr);  // a new capture, until its graph is instantiated
     if (capture) {
         for (Cached* x : g->cached) {
             CapturedBatched* c = dynamic_cast<CapturedBatched*>(x);
@@ -2951,9 +3052,12 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
                 cap = c;
         }
         fresh = cap == nullptr;
+        if (!fresh) touch_cached(g, cap);
         if (fresh) {
+            evict_captures<CapturedBatched>(g);
             cap = new CapturedBatched();
             g->cached.push_back(cap);
+            pend.c = cap;
             cap->B = B;
             cap->iters = max_iters;
             cap->piece = piece;
@@ -3009,7 +3113,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, cs,
                            L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
         NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, cs, L.n, B, L.outdeg.as<int32_t>(),
+        hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(1024), 0, cs, L.n, B, L.outdeg.as<int32_t>(),
                            seeds, w.stats.as<double>());
         NXG_CHECK_LAUNCH();
     };
@@ -3074,6 +3178,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             }
             NXG_HIP(hipStreamEndCapture(cs, &cap->graph));
             NXG_HIP(hipGraphInstantiate(&cap->exec, cap->graph, nullptr, nullptr, 0));
+            pend.commit();
         }
         NXG_HIP(hipEventRecord(e0, s));
         NXG_HIP(hipGraphLaunch(cap->exec, s));
@@ -3527,6 +3632,9 @@ int lds_budget_bytes(int device) {
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
     if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
+    if (d.d_stats && ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 ||
+                      d.d_seeds || (d.flags & NXG_RUN_SCATTER)))
+        fail(NXG_EUNSUPPORTED, "d_stats is written by single-column PageRank runs only");
     if (g->fwd.host_stream &&
         ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 || d.d_seeds ||
          (d.flags & NXG_RUN_SCATTER)))
