@@ -162,7 +162,7 @@ nxg_status nxg_read_probe(int64_t bytes, int32_t reps, void* stream, double* gbp
                            lets the lanes of one gather read adjacent sources */
 
 typedef struct nxg_build_desc {
-    int32_t n;              /* vertices, >= 1 */
+    int32_t n;              /* vertices, in [1, 2^29) (NXG_EUNSUPPORTED above) */
     int64_t m;              /* input edges, >= 0 (< 2^31, and < 2^30 with SYMMETRIZE) */
     const int32_t* d_src;   /* [m] source ids in [0, n) */
     const int32_t* d_dst;   /* [m] destination ids in [0, n) */

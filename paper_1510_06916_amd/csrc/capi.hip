@@ -118,6 +118,8 @@ namespace nxg {
 nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
     {
         if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
+        // gathers address the value arrays with 32-bit byte offsets (8-byte values)
+        if (d.n >= (1 << 29)) fail(NXG_EUNSUPPORTED, "n must be below 2^29");
         if (d.m < 0) fail(NXG_EINVAL, "m must be >= 0");
         const bool sym = (d.flags & NXG_BUILD_SYMMETRIZE) != 0;
         if (d.m >= ((int64_t)1 << 31) || (sym && d.m >= ((int64_t)1 << 30)))

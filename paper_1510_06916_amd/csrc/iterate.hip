@@ -6,9 +6,10 @@
 // LDS, and its wavefronts stream the tile's edge words chunk by chunk. They
 // follow the source-interval markers, gather the source values and add
 // (PageRank) or min-reduce (BFS, WCC) into LDS -- the write-conflict-free
-// destination ownership of Sec. III-D. In destination order a lane loads four
-// consecutive words and merges runs of equal destination first; in source order
-// the 64 lanes of a gather take 64 consecutive edges. A tile handled by one
+// destination ownership of Sec. III-D. The 64 lanes of a load take 64
+// consecutive edges: in destination order runs of equal destination are summed
+// across the wave before they reach LDS; in source order the lanes of a gather
+// read adjacent sources. A tile handled by one
 // workgroup applies the vertex update straight from LDS (single phase). A tile
 // split into k pieces writes k partial arrays (the hub of Sec. III-B2), which a
 // second launch sums in piece order and applies (two phase); a third launch
@@ -50,6 +51,40 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
+
+// Third word of a raw buffer resource on gfx9-class GPUs (no format, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+// One sub-block of padding words (and of zero weights), read by loads that fall
+// outside the edge stream so that no load needs a branch or a select. Never
+// written; not const, so that they sit in global memory like the stream and a
+// choice between the two stays a global load (a generic one would make the
+// compiler wait for every load in flight before the next LDS operation).
+__device__ __align__(16) uint32_t kPadWords[256] = {
+#define NXG_PAD8 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu
+#define NXG_PAD64 NXG_PAD8, NXG_PAD8, NXG_PAD8, NXG_PAD8, NXG_PAD8, NXG_PAD8, NXG_PAD8, NXG_PAD8
+    NXG_PAD64, NXG_PAD64, NXG_PAD64, NXG_PAD64
+#undef NXG_PAD64
+#undef NXG_PAD8
+};
+__device__ __align__(16) float kPadZeros[256] = {};
+
+// A gathered value by byte offset from a buffer resource; offsets past the
+// buffer's size read 0.
+template <typename T>
+__device__ inline T load_val(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline float load_val<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ inline int32_t load_val<int32_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <>
+__device__ inline double load_val<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
 
 struct Geo {
     const uint32_t* words;
@@ -318,6 +353,53 @@ __device__ inline A combine(A a, A b) {
         return b < a ? b : a;
 }
 
+// DPP controls of gfx9: row_shr:n (0x110 + n) shifts inside rows of 16 lanes,
+// row_bcast:15 / row_bcast:31 pass lane 15 of each row (lane 31) to the rows
+// after it, wave_shr:1 shifts the whole wave by one lane. A lane with no source
+// keeps `old`.
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int kCtl, int kRowMask>
+__device__ inline uint32_t dpp_u32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, kCtl, kRowMask, 0xF, false);
+}
+template <int kCtl, int kRowMask>
+__device__ inline int32_t dpp_val(int32_t old, int32_t v) {
+    return __builtin_amdgcn_update_dpp(old, v, kCtl, kRowMask, 0xF, false);
+}
+template <int kCtl, int kRowMask>
+__device__ inline double dpp_val(double old, double v) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = dpp_u32<kCtl, kRowMask>((uint32_t)o, (uint32_t)x);
+    const uint32_t hi = dpp_u32<kCtl, kRowMask>((uint32_t)(o >> 32), (uint32_t)(x >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Segmented reduction across a wave: the lanes of every run (consecutive lanes
+// start..lane, `start` being the run's first lane) are combined so that each
+// lane ends with the combination of its run up to itself -- the run's last lane
+// holds the run's total. Steps of 1, 2, 4 and 8 lanes inside rows of 16, then
+// the last lane of each row passed on to the rows after it.
+template <bool kSum, typename A>
+__device__ inline A run_reduce(A v, int start, int lane, A ident) {
+    A s;
+    s = dpp_val<kDppRowShr + 1, 0xF>(ident, v);
+    if (lane - 1 >= start) v = combine<kSum>(v, s);
+    s = dpp_val<kDppRowShr + 2, 0xF>(ident, v);
+    if (lane - 2 >= start) v = combine<kSum>(v, s);
+    s = dpp_val<kDppRowShr + 4, 0xF>(ident, v);
+    if (lane - 4 >= start) v = combine<kSum>(v, s);
+    s = dpp_val<kDppRowShr + 8, 0xF>(ident, v);
+    if (lane - 8 >= start) v = combine<kSum>(v, s);
+    // rows 1 and 3 take lane 15 / 47, when their run began in the row before
+    s = dpp_val<kDppRowBcast15, 0xA>(ident, v);
+    if (start < (lane & ~15)) v = combine<kSum>(v, s);
+    // rows 2 and 3 take lane 31, when their run began in row 0 or 1
+    s = dpp_val<kDppRowBcast31, 0xC>(ident, v);
+    if (lane >= 32 && start < 32) v = combine<kSum>(v, s);
+    return v;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -510,7 +592,7 @@ __device__ void gather_hub(const Geo& g, const Prog& prog, const FinSeg& it, typ
 }
 
 // Processes one work item (a tile, or a piece of a heavy tile) of one iteration.
-template <class Prog, int WG>
+template <class Prog, int WG, bool kDstOrder>
 __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, const Item& it,
                              unsigned char* smem) {
     using acc_t = typename Prog::acc_t;
@@ -561,132 +643,48 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
     const uint32_t tmask = (1u << g.t) - 1u;
     const int steps = g.C >> 8;
 
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
-    if (g.order != NXG_ORDER_SRC) {
-        // A wave step covers kU sub-blocks of 256 words (64 lanes x 4 consecutive
-        // words, one 16-byte load each): all word loads of the step are issued
-        // first, then all gathers, then the LDS reductions, so each lane keeps up to
-        // 4 * kU independent gathers in flight.
-        constexpr int kU = 4;
-        for (int64_t ci = c_lo + wave; ci < c_hi; ci += WG / 64) {
-            const int64_t c = list ? list[ci] : ci;
-            uint32_t row = (uint32_t)g.chunk_row[c];
-            const u32x4* wp = reinterpret_cast<const u32x4*>(g.words + c * (int64_t)g.C);
-            const f32x4* wwp = nullptr;
-            if constexpr (Prog::kWeights)
-                wwp = reinterpret_cast<const f32x4*>(prog.w + c * (int64_t)g.C);
-            for (int s = 0; s < steps; s += kU) {
-                uint32_t wd[kU * 4];
-                float wf[kU * 4];
-    #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    u32x4 w4 = {kNone, kNone, kNone, kNone};  // padding words
-                    if (s + u < steps) w4 = __builtin_nontemporal_load(wp + (s + u) * 64 + lane);
-                    wd[4 * u + 0] = w4.x;
-                    wd[4 * u + 1] = w4.y;
-                    wd[4 * u + 2] = w4.z;
-                    wd[4 * u + 3] = w4.w;
-                    if constexpr (Prog::kWeights) {
-                        f32x4 f4 = {0.f, 0.f, 0.f, 0.f};
-                        if (s + u < steps) f4 = __builtin_nontemporal_load(wwp + (s + u) * 64 + lane);
-                        wf[4 * u + 0] = f4.x;
-                        wf[4 * u + 1] = f4.y;
-                        wf[4 * u + 2] = f4.z;
-                        wf[4 * u + 3] = f4.w;
-                    } else {
-                        wf[4 * u + 0] = wf[4 * u + 1] = wf[4 * u + 2] = wf[4 * u + 3] = 0.f;
-                    }
-                }
-                // decode: source index and destination (kNone for markers, padding and
-                // edges out of inactive source intervals)
-                uint32_t sidx[kU * 4], dl[kU * 4];
-    #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const uint32_t* w = wd + 4 * u;
-                    const uint64_t mm = __ballot(((w[0] | w[1] | w[2] | w[3]) >> 31) != 0);
-                    if (mm == 0) {
-                        // whole sub-block inside one source interval (uniform)
-                        const uint32_t rb = row * (uint32_t)g.I;
-                        const bool on = prog.row_active(row);
-    #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
-                            dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
-                        }
-                    } else {
-                        uint32_t last = 0;
-    #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (w[k] & kMarker) last = w[k] & ~kMarker;
-                        const uint64_t prev = mm & lt;
-                        const int from = prev ? 63 - __clzll(prev) : lane;
-                        const uint32_t got = __shfl(last, from);
-                        uint32_t r = prev ? got : row;
-                        row = (uint32_t)__builtin_amdgcn_readlane((int)(last), 63 - __clzll(mm));
-                        uint32_t rb = r * (uint32_t)g.I;
-                        bool on = prog.row_active(r);
-    #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (w[k] & kMarker) {
-                                r = w[k] & ~kMarker;
-                                rb = r * (uint32_t)g.I;
-                                on = prog.row_active(r);
-                                sidx[4 * u + k] = 0;
-                                dl[4 * u + k] = kNone;
-                            } else {
-                                sidx[4 * u + k] = rb + ((w[k] >> g.sshift) & lmask);
-                                dl[4 * u + k] = on ? ((w[k] >> g.dshift) & tmask) : kNone;
-                            }
-                        }
-                    }
-                }
-                acc_t val[kU * 4];
-    #pragma unroll
-                for (int k = 0; k < kU * 4; ++k)
-                    val[k] = dl[k] != kNone ? prog.gather(sidx[k], wf[k]) : prog.identity();
-                // reduce: merge runs of equal destination inside the lane's 4 words
-    #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    uint32_t pd = kNone;
-                    acc_t pv = prog.identity();
-    #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t d = dl[4 * u + k];
-                        if (d == kNone) continue;
-                        if (d == pd) {
-                            pv = combine<Prog::kSum>(pv, val[4 * u + k]);
-                        } else {
-                            if (pd != kNone && (Prog::kSum || pv != prog.identity()))
-                                lds_combine(&acc[pd], pv, Prog::kSum);
-                            pd = d;
-                            pv = val[4 * u + k];
-                        }
-                    }
-                    if (pd != kNone && (Prog::kSum || pv != prog.identity()))
-                        lds_combine(&acc[pd], pv, Prog::kSum);
-                }
-            }
-        }
-    } else {
-        // Source-major groups. Load k of a lane reads word 64k + lane of a 256-word
-        // sub-block, so each gather serves 64 consecutive edges, whose sources
-        // are adjacent. The wave walks its units (kU sub-blocks of one chunk)
-        // through two word buffers: the loads of unit u + 2 are issued right
-        // after the gathers of unit u, so every unit's words have a whole unit of
-        // work to arrive, and waiting for a unit's gathers never waits for them.
+    // Both edge orders share one loop. Load k of a lane reads word 64k + lane of
+    // a 256-word sub-block, so the 64 lanes of a load, a gather and an LDS
+    // reduction hold 64 consecutive edges: in source order their sources are
+    // adjacent (a gather touches few cache lines); in destination order runs of
+    // equal destination lie in consecutive lanes and are summed across the wave
+    // before they reach LDS. The wave walks its units (kU sub-blocks of one
+    // chunk) through two word buffers, and gathers run one unit ahead of the
+    // reductions: a unit's gathers are issued before the previous unit's LDS
+    // reductions, so each lane keeps two units of gathers and two units of word
+    // loads in flight (the 6-bit load counter holds exactly that many).
+    //
+    // Per word the decode keeps two 32-bit numbers: the byte offset of the
+    // gathered value from the value array's base, and the LDS slot it adds
+    // into. Gathers are buffer loads with 32-bit offsets; a marker or padding
+    // word asks for an offset past the array and reads 0 (the hardware's range
+    // check), so a summing program needs no select for non-edges, and such
+    // words add into the lane's own discard slot past the tile.
+    auto stream = [&](auto dst_tag) {
+        constexpr bool kDst = decltype(dst_tag)::value;
         using val_t = typename Prog::val_t;
-        // 16 edges per lane and unit; 8 when weights or 8-byte values need the registers
-        constexpr int kU = (Prog::kWeights || sizeof(val_t) > 4) ? 2 : 4, kQ = 4 * kU;
-        // pair layout: header words set the source of the pair words after them
-        // (carried across lanes and units like the interval markers), and a pair
-        // word adds its one gathered value to two destinations
-        constexpr bool kPairs = pairs_of<Prog>::value;
+        // 16 edges per lane and unit in source order; 8 when weights, 8-byte values
+        // or the cross-lane run sums of the destination order need the registers
+        constexpr int kU = (Prog::kWeights || sizeof(val_t) > 4 || kDst) ? 2 : 4, kQ = 4 * kU;
+        // pair layout (source order only): header words set the source of the
+        // pair words after them (carried across lanes and units like the
+        // interval markers), and a pair word adds its one gathered value to two
+        // destinations
+        constexpr bool kPairs = pairs_of<Prog>::value && !kDst;
+        constexpr uint32_t kVs = sizeof(val_t) == 8 ? 3u : 2u;  // log2 of the value bytes
+        constexpr uint32_t kOOB = 0xFFFFFFF0u;                 // past any value array
+        // destination order: a slice whose 64 edges form at most this many runs
+        // of equal destination is summed across the wave first
+        constexpr int kRunSlice = 16;
         const uint32_t* const wordsp = g.words;
         const int64_t Cw = g.C;
         const int32_t* const rowp = g.chunk_row;
-        const val_t* const curp = prog.cur;
         const float* wtsp = nullptr;
         if constexpr (Prog::kWeights) wtsp = prog.w;
+        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)prog.cur, (short)0, (int)((uint32_t)g.n << kVs), kBufWord3);
+        const uint32_t ival = (uint32_t)g.I;  // interval size (any size, not only powers of two)
+        const uint32_t disc = (uint32_t)g.T + lane;   // this lane's discard slot
         // loader cursor: chunk (index into the item's range or list) and sub-block
         int64_t lci = c_lo + wave;
         int ls = 0;
@@ -696,13 +694,12 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         bool vA = false, vB = false, nA = false, nB = false;  // valid, starts a chunk
         uint32_t rA = 0, rB = 0;                              // chunk's first interval
         uint32_t sA = 0, sB = 0;  // pair layout: header source at the chunk's first word
-        uint32_t iA = 0, iB = 0;  // sub-blocks of the unit that hold stream words (bit u)
-        // Issues the loads of the next unit. Every load is unconditional (past the
-        // end it reads a chunk this wave owns and the words become padding), so
-        // the code has no branch around memory operations and the compiler keeps
-        // exact counts of the loads in flight.
-        auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0,
-                        uint32_t& s0, uint32_t& inm) {
+        // Issues the loads of the next unit. Every load is unconditional, so the
+        // code has no branch around memory operations and the compiler keeps
+        // exact counts of the loads in flight: a sub-block outside the stream
+        // (past the wave's range, or past the chunk's end) is read from a
+        // constant block of padding words (weights: zeros) instead.
+        auto next = [&](uint32_t* wo, float* fo, bool& valid, bool& starts, uint32_t& r0, uint32_t& s0) {
             valid = lci < c_hi;
             const int64_t cl = valid ? lci : lprev;
             const int sl = valid ? ls : 0;
@@ -711,20 +708,18 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
             if constexpr (Prog::kActivity) c_ = list ? list[cl] : cl;
             r0 = (uint32_t)rowp[c_];
             if constexpr (kPairs) s0 = (uint32_t)g.chunk_src[c_];
-            const int64_t base = c_ * Cw + (int64_t)sl * 256 + lane;
-            inm = 0;
+            const int64_t base = c_ * Cw + (int64_t)sl * 256;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const bool in = valid && sl + u < steps;
-                inm |= (in ? 1u : 0u) << u;
+                const uint32_t* wb = in ? wordsp + base + u * 256 : kPadWords;
+                const float* fb = nullptr;
+                if constexpr (Prog::kWeights) fb = in ? wtsp + base + u * 256 : kPadZeros;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    // words of a sub-block outside the stream are loaded from sub-block
-                    // 0 and treated as padding by the decode
-                    const int64_t off = base + (in ? u * 256 : 0) + k * 64;
-                    wo[4 * u + k] = __builtin_nontemporal_load(wordsp + off);
+                    wo[4 * u + k] = __builtin_nontemporal_load(wb + k * 64 + lane);
                     if constexpr (Prog::kWeights)
-                        fo[4 * u + k] = __builtin_nontemporal_load(wtsp + off);
+                        fo[4 * u + k] = __builtin_nontemporal_load(fb + k * 64 + lane);
                     else
                         fo[4 * u + k] = 0.f;
                 }
@@ -738,28 +733,30 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                 }
             }
         };
-        if (lci < c_hi) {
-        next(wA, fA, vA, nA, rA, sA, iA);
-        next(wB, fB, vB, nB, rB, sB, iB);
+        if (lci >= c_hi) return;
+        next(wA, fA, vA, nA, rA, sA);
+        next(wB, fB, vB, nB, rB, sB);
         uint32_t row = 0, hsrc = 0;
-        // one unit: decode, gathers, loads of the unit two ahead, LDS reductions
-        auto unit = [&](uint32_t* w_, float* f_, bool& valid, bool& starts, uint32_t& r0,
-                        uint32_t& s0, uint32_t& inm) {
+        // decode: offsets of the gathers and LDS slots of one unit's words
+        auto decode = [&](const uint32_t* w_, bool starts, uint32_t r0, uint32_t s0, uint32_t* off,
+                          uint32_t* li, uint32_t* li2) {
             if (starts) {
                 row = r0;
                 if constexpr (kPairs) hsrc = s0;
             }
-            const uint32_t in_now = inm;
-            uint32_t sidx[kQ], dl[kQ], dl2[kPairs ? kQ : 1];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const uint32_t w = ((in_now >> (q >> 2)) & 1u) ? w_[q] : kNone;
-                const uint64_t mm = __ballot((w >> 31) != 0);
-                uint32_t r = row;
+                const uint32_t w = w_[q];
+                // markers and padding have bit 31 set; the lane's interval is the
+                // last marker at or before it in the slice, else the carried one
+                const uint64_t mm = __ballot((int32_t)w < 0);
+                // byte offset of the interval's first value: a scalar unless the
+                // slice holds a marker
+                uint32_t rb = (uint32_t)__builtin_amdgcn_readfirstlane((int)((row * ival) << kVs));
                 if (mm) {
                     const uint64_t upto = mm & (lt | (1ull << lane));
                     const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
-                    r = upto ? got : row;
+                    rb = ((upto ? got : row) * ival) << kVs;
                     row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
                 }
                 if constexpr (kPairs) {
@@ -774,46 +771,79 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                         sv = upto ? got : hsrc;
                         hsrc = (uint32_t)__builtin_amdgcn_readlane((int)(w & 0x3FFFFFFFu), 63 - __clzll(hm));
                     }
-                    const bool on = prog.row_active(r);
-                    const bool pr = kind == 1u && on, pl = kind == 0u && on;
-                    sidx[q] = (pr || pl) ? r * (uint32_t)g.I + (pr ? sv : ((w >> g.sshift) & lmask)) : 0u;
-                    dl[q] = (pr || pl) ? (w & tmask) : kNone;
-                    dl2[q] = pr ? ((w >> 14) & tmask) : kNone;
+                    const bool pr = kind == 1u, pl = kind == 0u;
+                    const uint32_t loc = pr ? sv : __builtin_amdgcn_ubfe(w, (uint32_t)g.sshift, (uint32_t)g.L);
+                    off[q] = (pr || pl) ? (loc << kVs) + rb : kOOB;
+                    li[q] = (pr || pl) ? (w & tmask) : disc;
+                    li2[q] = pr ? ((w >> 14) & tmask) : disc;
                 } else {
-                    const bool edge = (w >> 31) == 0 && prog.row_active(r);
-                    sidx[q] = edge ? r * (uint32_t)g.I + ((w >> g.sshift) & lmask) : 0u;
-                    dl[q] = edge ? ((w >> g.dshift) & tmask) : kNone;
-                }
-            }
-            val_t raw[kQ];
-            float wq[kQ];
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                wq[q] = f_[q];
-                raw[q] = curp[sidx[q]];  // non-edges read vertex 0: no divergent branch
-            }
-            next(w_, f_, valid, starts, r0, s0, inm);
-            // branch-free reductions: markers and padding add the identity to
-            // the lane's own discard slot (a conditional block here would let the
-            // compiler sink a gather into it and wait on every load in flight)
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const bool e = dl[q] != kNone;
-                const acc_t v = e ? prog.from_val(raw[q], wq[q]) : prog.identity();
-                lds_combine(&acc[e ? dl[q] : (uint32_t)g.T + lane], v, Prog::kSum);
-                if constexpr (kPairs) {
-                    const bool e2 = dl2[q] != kNone;
-                    if (__ballot(e2)) lds_combine(&acc[e2 ? dl2[q] : (uint32_t)g.T + lane], e2 ? v : prog.identity(), Prog::kSum);
+                    const bool e = (int32_t)w >= 0;
+                    off[q] = e ? (__builtin_amdgcn_ubfe(w, (uint32_t)g.sshift, (uint32_t)g.L) << kVs) + rb : kOOB;
+                    li[q] = e ? __builtin_amdgcn_ubfe(w, (uint32_t)g.dshift, (uint32_t)g.t) : disc;
                 }
             }
         };
-        while (vA) {
-            unit(wA, fA, vA, nA, rA, sA, iA);
-            if (!vB) break;
-            unit(wB, fB, vB, nB, rB, sB, iB);
+        auto gather = [&](const uint32_t* off, const float* f_, val_t* raw, float* wq) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                wq[q] = f_[q];
+                raw[q] = load_val<val_t>(vrs, off[q]);  // non-edges read 0
+            }
+        };
+        // branch-free reductions: a summing program adds the gathered 0 of a
+        // non-edge to the lane's discard slot; a minimum program offers its
+        // identity there (a conditional block around the gathered value would let
+        // the compiler sink a gather into it and wait on every load in flight)
+        auto reduce = [&](const val_t* raw, const float* wq, const uint32_t* li, const uint32_t* li2) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                acc_t v = prog.from_val(raw[q], wq[q]);
+                if constexpr (!Prog::kSum) v = li[q] != disc ? v : prog.identity();
+                uint32_t slot = li[q];
+                if constexpr (kDst) {
+                    // Runs of equal destination (the slice's keys; a marker or
+                    // padding lane has its own slot, so it ends any run) are summed
+                    // across the wave into their last lane, which alone adds to
+                    // LDS, when the slice has few enough runs for that to pay
+                    const uint32_t kp = dpp_u32<kDppWaveShr1, 0xF>(~slot, slot);
+                    const uint64_t heads = __ballot(kp != slot);
+                    if (__popcll(heads) <= kRunSlice) {
+                        const int start = 63 - (int)__clzll(heads & ((2ull << lane) - 1ull));
+                        v = run_reduce<Prog::kSum>(v, start, lane, prog.identity());
+                        const bool tail = lane == 63 || (((heads >> lane) >> 1) & 1ull);
+                        slot = tail ? slot : disc;
+                        v = tail ? v : prog.identity();
+                    }
+                }
+                lds_combine(&acc[slot], v, Prog::kSum);
+                if constexpr (kPairs) {
+                    if (__ballot(li2[q] != disc)) lds_combine(&acc[li2[q]], v, Prog::kSum);
+                }
+            }
+        };
+        uint32_t off[kQ], lA[kQ], lB[kQ], l2A[kPairs ? kQ : 1], l2B[kPairs ? kQ : 1];
+        val_t gA[kQ], gB[kQ];
+        float qA[kQ], qB[kQ];
+        // unit 0 decoded and its gathers issued; its buffer takes unit 2
+        decode(wA, nA, rA, sA, off, lA, l2A);
+        gather(off, fA, gA, qA);
+        bool okA = vA, okB = false;  // the unit held in gA / gB is part of the stream
+        next(wA, fA, vA, nA, rA, sA);
+        while (okA) {
+            decode(wB, nB, rB, sB, off, lB, l2B);
+            gather(off, fB, gB, qB);
+            okB = vB;
+            next(wB, fB, vB, nB, rB, sB);
+            reduce(gA, qA, lA, l2A);
+            if (!okB) break;
+            decode(wA, nA, rA, sA, off, lA, l2A);
+            gather(off, fA, gA, qA);
+            okA = vA;
+            next(wA, fA, vA, nA, rA, sA);
+            reduce(gB, qB, lB, l2B);
         }
-        }
-    }
+    };
+    stream(std::integral_constant<bool, kDstOrder>{});
     __syncthreads();
 
     // a piece stores its partial in its hub slot; k_finish combines them (its
@@ -830,10 +860,13 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
     apply_range<Prog, WG>(g, ctl, prog, base, len, tile, acc);
 }
 
-template <class Prog, int WG>
+// kDstOrder: the stream's sub-shards are in destination order (runs of equal
+// destination summed across the wave); a kernel of its own per order, so each
+// loop gets its own register allocation.
+template <class Prog, int WG, bool kDstOrder>
 __global__ __launch_bounds__(WG) void k_iterate(Geo g, Ctl ctl, Prog prog) {
     extern __shared__ __align__(16) unsigned char smem[];
-    iterate_item<Prog, WG>(g, ctl, prog, g.items[blockIdx.x], smem);
+    iterate_item<Prog, WG, kDstOrder>(g, ctl, prog, g.items[blockIdx.x], smem);
 }
 
 // One workgroup per vertex segment of a split tile.
@@ -880,7 +913,7 @@ struct MultiGraph {
     float* user;         // the caller's result buffer (written from xout when o2n is set)
 };
 
-template <int WG>
+template <int WG, bool kDstOrder>
 __global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict__ graphs,
                                                    const int32_t* __restrict__ item_graph,
                                                    const Item* __restrict__ items, int k, int iters,
@@ -891,7 +924,7 @@ __global__ __launch_bounds__(WG) void k_multi_iter(const MultiGraph* __restrict_
     Ctl ctl{mg.stats, mg.done0, k, 0.0};
     ProgPR<float> prog{(k & 1) ? mg.buf1 : mg.buf0, (k & 1) ? mg.buf0 : mg.buf1, nullptr,
                        k == iters - 1 ? mg.xout : nullptr, damping};
-    iterate_item<ProgPR<float>, WG>(mg.geo, ctl, prog, items[r], smem);
+    iterate_item<ProgPR<float>, WG, kDstOrder>(mg.geo, ctl, prog, items[r], smem);
 }
 
 // A finishing segment of graph `graph`.
@@ -2158,10 +2191,22 @@ template <class Prog, int WG>
 void prepare_iter(size_t lds) {
     static size_t attr_lds = 0;
     if (lds > attr_lds) {
-        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG>,
+        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        NXG_HIP(hipFuncSetAttribute((const void*)k_iterate<Prog, WG, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_lds = lds;
     }
+}
+
+// The edge kernel of one iteration for the stream's edge order.
+template <class Prog, int WG>
+void launch_items(int n_items, size_t lds, hipStream_t s, const Geo& geo, const Ctl& ctl, const Prog& prog) {
+    if (geo.order == NXG_ORDER_DST)
+        hipLaunchKernelGGL((k_iterate<Prog, WG, true>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
+    else
+        hipLaunchKernelGGL((k_iterate<Prog, WG, false>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
+    NXG_CHECK_LAUNCH();
 }
 
 // A host-resident edge stream (NXG_BUILD_HOST_STREAM) is fed to the edge
@@ -2252,10 +2297,7 @@ struct Streamer {
             if constexpr (Prog::kWeights)
                 pb.w = reinterpret_cast<const float*>(reinterpret_cast<uintptr_t>(fst[buf].p) -
                                                       (uintptr_t)b.c0 * L->C * sizeof(float));
-            if (b.i1 > b.i0) {
-                hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(b.i1 - b.i0), dim3(WG), lds, s, gb, ctl, pb);
-                NXG_CHECK_LAUNCH();
-            }
+            if (b.i1 > b.i0) launch_items<Prog, WG>(b.i1 - b.i0, lds, s, gb, ctl, pb);
             NXG_HIP(hipEventRecord(used[buf], s));
             ++launched;
             if (issued == launched) issue(issued++);  // the next batch into the other buffer
@@ -2273,8 +2315,7 @@ void launch_iter(const Geo& geo, const Ctl& ctl, const Prog& prog, const Plan& p
     if (str) {
         str->launch<Prog, WG>(geo, ctl, prog, lds, s);
     } else if (n_items > 0) {
-        hipLaunchKernelGGL((k_iterate<Prog, WG>), dim3(n_items), dim3(WG), lds, s, geo, ctl, prog);
-        NXG_CHECK_LAUNCH();
+        launch_items<Prog, WG>(n_items, lds, s, geo, ctl, prog);
     }
     if (!p.h_fseg.empty()) {
         hipLaunchKernelGGL((k_finish<Prog, kFinWG>), dim3((int)p.h_fseg.size()), dim3(kFinWG),
@@ -3377,7 +3418,9 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     NXG_HIP(hipMemcpyAsync(c->ddesc.p, c->hdesc.data(), sizeof(MultiGraph) * G, hipMemcpyHostToDevice, s));
     static size_t attr = 0;
     if (lds > attr) {
-        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024>,
+        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        NXG_HIP(hipFuncSetAttribute((const void*)k_multi_iter<1024, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = lds;
     }
@@ -3389,8 +3432,12 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
                            c->dpart.as<double>());
         NXG_CHECK_LAUNCH();
         for (int k = 0; k < iters; ++k) {
-            hipLaunchKernelGGL(k_multi_iter<1024>, dim3(c->per_iter), dim3(1024), lds, cs, ddesc,
-                               c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
+            if (mg->graphs[0]->fwd.order == NXG_ORDER_DST)
+                hipLaunchKernelGGL((k_multi_iter<1024, true>), dim3(c->per_iter), dim3(1024), lds, cs, ddesc,
+                                   c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
+            else
+                hipLaunchKernelGGL((k_multi_iter<1024, false>), dim3(c->per_iter), dim3(1024), lds, cs, ddesc,
+                                   c->dgraph.as<int32_t>(), c->ditems.as<Item>(), k, iters, d.damping);
             NXG_CHECK_LAUNCH();
             if (c->n_fin > 0) {
                 hipLaunchKernelGGL(k_multi_finish<kFinWG>, dim3(c->n_fin), dim3(kFinWG),
