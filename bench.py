@@ -11,7 +11,10 @@ Other workloads (--mode): bfs, wcc (scale 22, ef 16, 32 intervals), ppr (64
 seeds, scale 22), multi (256 graphs, scales 10..18), adjoint (scale 20, fwd to
 1e-8 residual + backward), degree (scale 22 over 2^23 sparse ids, with and
 without degreeing), hoststream (the headline graph with its edge stream in
-host memory); --mode all runs every one (one JSON line each).
+host memory); --mode all runs every one (one JSON line each). The default run
+also times batched PPR, forward+backward, the 256-graph launch, BFS and WCC
+and reports them under "forms" on the headline's line (--no-forms: headline
+only).
 
   python bench.py [--steps K] [--warmup W]
                   [--mode pagerank|bfs|wcc|ppr|multi|adjoint|degree|hoststream|all]
@@ -74,7 +77,19 @@ def cpu_baseline_pagerank(src_d, dst_d, n, stride):
     return {"value": m / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "one FP64 PageRank iteration of the single-threaded C oracle over %s "
                       "(%d edges, n=%d): %.1f s" % ("every edge" if stride == 1 else
-                                                    "every %d-th edge" % stride, m, n, dt)}
+                                                    "every %d-th edge" % stride, m, n, dt),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def rmat(scale, ef, seed, dev):
@@ -132,22 +147,28 @@ def bench_pagerank(args, dev):
     achieved = b_iter / (kern_ms * 1e-3) / 1e9
     log("sum(x) = %.9f" % float(x.double().sum()))
     x = None
-    # the paper's own order (natural ids, destination-sorted sub-shards), same geometry
-    dsss_ms = None
-    if not args.no_ablation and (order != "dst" or best["relabel"]):
+    # the paper's own order (destination-sorted sub-shards), same geometry: with
+    # natural ids (the DSSS of Sec. II-A as is) and with out-degree numbering
+    dsss_ms = {}
+    if not args.no_ablation:
         del g, x
         torch.cuda.empty_cache()
-        g2 = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"], chunk=best["chunk"])
-        out2 = torch.empty(n, dtype=torch.float32, device=dev)
-        g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
-        torch.cuda.synchronize()
-        dsss_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        log("destination-sorted sub-shards, natural ids: %.3f ms/step" % dsss_ms)
-        del g2
-        torch.cuda.empty_cache()
+        for relabel in (False, True):
+            if order == "dst" and bool(best["relabel"]) == relabel:
+                continue
+            g2 = DSSS.build(src, dst, n, interval=best["interval"], tile=best["tile"], chunk=best["chunk"],
+                            relabel=relabel)
+            out2 = torch.empty(n, dtype=torch.float32, device=dev)
+            g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g2.pagerank(args.steps, dtype=torch.float32, capture=True, out=out2, piece_chunks=piece)
+            torch.cuda.synchronize()
+            dsss_ms[relabel] = (time.perf_counter() - t0) * 1e3 / args.steps
+            log("destination-sorted sub-shards, %s: %.3f ms/step" % (
+                "out-degree numbering" if relabel else "natural ids", dsss_ms[relabel]))
+            del g2, out2
+            torch.cuda.empty_cache()
     # the paper's comparison scheme: the edge list sorted by source, pushed into
     # global sums with atomics (coarse-grained, Sec. IV-B1)
     scatter_ms = None
@@ -182,7 +203,8 @@ def bench_pagerank(args, dev):
                    "order": order, "relabel": bool(best["relabel"]), "pairs": pairs,
                    "words": inf["n_words"], "damping": 0.85,
                    "tuned_candidates": best["candidates"],
-                   "dst_sorted_natural_ids_ms_per_step": dsss_ms,
+                   "dst_sorted_natural_ids_ms_per_step": dsss_ms.get(False),
+                   "dst_sorted_relabeled_ms_per_step": dsss_ms.get(True),
                    "coarse_scatter_ms_per_step": scatter_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -191,7 +213,7 @@ def bench_pagerank(args, dev):
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_pagerank(src, dst, n, args.cpu_stride)
-    print(json.dumps(res), flush=True)
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -242,7 +264,7 @@ def bench_bfs_wcc(args, dev, which):
                "config": {"workload": "wcc rmat-s22-ef16 symmetrised P=32", "n": n,
                           "m_sym": g.m, "rounds": st["changed_rounds"], "ms": dt * 1e3,
                           "stream_passes": st["streamed_chunks"] / g.info()["n_chunks"]}}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_ppr(args, dev):
@@ -290,6 +312,9 @@ def bench_ppr(args, dev):
         gp.pagerank(iters, teleport=tele, out=out, capture=True)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    # the last plain run had seed B - 1: its column of the batched result against it
+    xb = outs[-1][:, -1].double()
+    acc = float((xb - out.double()).abs().sum() / out.double().abs().sum())
     res = {"metric": "batched PPR edge-vector updates per second", "value": B * gb.m * iters / tb / 1e9,
            "unit": "G updates/s", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
            "config": {"workload": "ppr rmat-s22-ef16 B=64 30 iterations", "n": n, "m": gb.m,
@@ -298,8 +323,8 @@ def bench_ppr(args, dev):
                       "tuned_candidates": best["candidates"],
                       "plain_order": args.order, "plain_relabel": int(args.relabel),
                       "batched_ms": tb * 1e3, "plain_64_runs_ms": tp * 1e3,
-                      "speedup_vs_plain": tp / tb}}
-    print(json.dumps(res), flush=True)
+                      "speedup_vs_plain": tp / tb, "rel_l1_vs_plain_last_column": acc}}
+    return res
 
 
 def bench_multi(args, dev):
@@ -336,6 +361,7 @@ def bench_multi(args, dev):
         g.pagerank(30, out=o, capture=True)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    acc = max(float((a.double() - b.double()).abs().sum() / b.double().abs().sum()) for a, b in zip(xs, outs))
     res = {"metric": "256-graph PageRank (30 iterations) edges per second", "value": m_total * 30 / tm / 1e9,
            "unit": "GTEPS", "n_gpus": 1, "dtype": "f32", "higher_is_better": True,
            "config": {"workload": "multi 256 rmat graphs s10..18 ef8..32", "m_total": m_total,
@@ -343,8 +369,8 @@ def bench_multi(args, dev):
                       "one_launch_per_iteration_ms": tm * 1e3, "device_ms": st["device_ms"],
                       "captured": True,
                       "plain_captured_runs_ms": tp * 1e3,
-                      "speedup_vs_plain": tp / tm}}
-    print(json.dumps(res), flush=True)
+                      "speedup_vs_plain": tp / tm, "max_rel_l1_vs_plain": acc}}
+    return res
 
 
 def bench_degree(args, dev):
@@ -382,7 +408,7 @@ def bench_degree(args, dev):
         res["config"][key + "_vertices"] = g.info()["n_kept"]
         del g
     res["value"] = res["config"]["degreed_ms_per_iter"]
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_hoststream(args, dev):
@@ -423,7 +449,7 @@ def bench_hoststream(args, dev):
            "config": {"workload": "hoststream rmat-s%d-ef%d" % (args.scale, args.ef), "n": n, "m": inf["m"],
                       "stream_gb": stream_bytes / 1e9, "stream_gbs": stream_bytes / (ms * 1e-3) / 1e9,
                       "h2d_copy_gbs": h2d, "gteps": inf["m"] / (ms * 1e-3) / 1e9}}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_adjoint(args, dev):
@@ -477,7 +503,7 @@ def bench_adjoint(args, dev):
                       "tuned_candidates": best["candidates"], "timing": "median of 3",
                       "forward_iterations": st["iterations"], "forward_alone_ms": tf * 1e3,
                       "fwd_bwd_over_fwd": tfb / tf}}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -501,7 +527,10 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true",
-                    help="skip timing the destination-sorted, natural-id layout beside the tuned one")
+                    help="skip timing the destination-sorted layouts and the coarse scatter beside the tuned one")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="headline only: skip the batched PPR, forward+backward, 256-graph, BFS and WCC "
+                         "figures the default run adds to its line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the DSSS iteration runs on a single MI355X "
@@ -512,23 +541,27 @@ def main():
     dev = torch.device("cuda:0")
     modes = (["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "hoststream"]
              if args.mode == "all" else [args.mode])
+    runners = {"pagerank": bench_pagerank, "bfs": lambda a, d: bench_bfs_wcc(a, d, "bfs"),
+               "wcc": lambda a, d: bench_bfs_wcc(a, d, "wcc"), "ppr": bench_ppr, "multi": bench_multi,
+               "degree": bench_degree, "hoststream": bench_hoststream, "adjoint": bench_adjoint}
     for mode in modes:
         log("== mode %s" % mode)
-        if mode == "pagerank":
-            bench_pagerank(args, dev)
-        elif mode in ("bfs", "wcc"):
-            bench_bfs_wcc(args, dev, mode)
-        elif mode == "ppr":
-            bench_ppr(args, dev)
-        elif mode == "multi":
-            bench_multi(args, dev)
-        elif mode == "degree":
-            bench_degree(args, dev)
-        elif mode == "hoststream":
-            bench_hoststream(args, dev)
-        else:
-            bench_adjoint(args, dev)
+        res = runners[mode](args, dev)
         torch.cuda.empty_cache()
+        if mode == "pagerank" and args.mode == "pagerank" and not args.no_forms:
+            # the rest of the metric on the same line: batched PPR and
+            # forward+backward against the plain path, the many-graph launch, and
+            # the BFS / WCC rates of the scale-22 graph
+            res["forms"] = {}
+            for name in ("ppr", "adjoint", "multi", "bfs", "wcc"):
+                log("== form %s" % name)
+                t0 = time.perf_counter()
+                r = runners[name](args, dev)
+                torch.cuda.empty_cache()
+                res["forms"][name] = {"metric": r["metric"], "value": r["value"], "unit": r["unit"],
+                                      "dtype": r["dtype"], **r["config"],
+                                      "bench_s": round(time.perf_counter() - t0, 1)}
+        print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

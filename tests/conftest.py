@@ -19,3 +19,20 @@ def gpu_device():
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
     return torch.device("cuda:0")
+
+
+@pytest.fixture
+def progress(request):
+    """Writes a line to the terminal right away, past pytest's output capture:
+    long tests report each step of their work (an oracle iteration, a root), so
+    a run of many minutes is never silent."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        if capman is not None:
+            with capman.global_and_fixture_disabled():
+                sys.stdout.write("\n" + msg + "\n")
+                sys.stdout.flush()
+        else:
+            print(msg, flush=True)
+    return say
