@@ -265,6 +265,22 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
                                    lock-based source-sorted comparison (Sec. IV-B1). Same
                                    results as the DSSS runs up to the order of the additions;
                                    not combinable with NXG_RUN_CAPTURE */
+#define NXG_RUN_MPU 0x10        /* single-column PageRank (plain or weighted, F32 or F64) with the
+                                   mixed-phase update of Sec. III-B3 (Alg. 7), host memory as the
+                                   slower tier: only the first Q source intervals keep their values
+                                   in device memory, Q chosen from vertex_budget (each resident
+                                   vertex costs two values and an 8-byte accumulator, plus one
+                                   staged interval; the resident range is a whole number of
+                                   intervals and tiles). The other intervals' values stay in pinned
+                                   host memory, are staged one interval at a time while their row of
+                                   sub-shards is processed, and sub-shards whose source and
+                                   destination are both non-resident pass through shard hubs in
+                                   host memory (dense, one tile-sized FP64 array per sub-shard).
+                                   Q = P is the SPU, Q = 0 the DPU. Needs a build with natural ids
+                                   (no RELABEL or DEGREE), a power-of-two interval, and no PAIRS,
+                                   HOST_STREAM or SCATTER; not combinable with NXG_RUN_CAPTURE.
+                                   d_values and d_teleport may be pinned host memory. The run
+                                   stats report Q and the bytes moved to and from host memory */
 
 typedef struct nxg_run_desc {
     nxg_program program;
@@ -294,6 +310,8 @@ typedef struct nxg_run_desc {
                                scalar), 4k+1 the residual ||x^{k+1} - x^k||_1, 4k+2
                                sum(x^{k+1}), 4k+3 unused (0); iterations after a
                                tolerance stop read 0. NULL = not written */
+    int64_t vertex_budget;  /* NXG_RUN_MPU: device bytes for the run's vertex data; 0 = the
+                               environment variable NXG_VERTEX_BUDGET_MB */
 } nxg_run_desc;
 
 typedef struct nxg_run_stats {
@@ -310,6 +328,11 @@ typedef struct nxg_run_stats {
                                changed in the previous round and, for BFS, its destination
                                id range holds a block with an unreached vertex; 0 for
                                other programs */
+    int32_t resident_intervals; /* NXG_RUN_MPU: Q, the source intervals kept in device memory */
+    int64_t host_read_bytes;    /* NXG_RUN_MPU: bytes read from host memory (staged intervals,
+                                   shard hubs, old values of non-resident vertices) */
+    int64_t host_write_bytes;   /* NXG_RUN_MPU: bytes written to host memory (shard hubs, new
+                                   values of non-resident vertices) */
 } nxg_run_stats;
 
 /* Runs the program on the stored graph. With stats == NULL the call is fully

@@ -226,13 +226,16 @@ class DSSS:
 
     def pagerank(self, iters, damping=0.85, dtype=torch.float32, tol=0.0, teleport=None,
                  x0=None, weighted=False, out=None, capture=False, piece_chunks=0, scatter=False,
-                 stats_out=None):
+                 stats_out=None, mpu_budget=None):
         """stats_out: optional FP64 device tensor of 4 * iters entries that the run
         (and every replay of a captured one) fills with the per-iteration
         statistics (dangling mass, residual, sum of x, 0) without a host sync.
         capture=True records the run into a hipGraph kept by the handle (at most
         8 per handle, least recently used released first), replayed when a
-        later call passes the same buffers."""
+        later call passes the same buffers. mpu_budget (bytes, or 0 for the
+        environment variable NXG_VERTEX_BUDGET_MB) runs the mixed-phase update
+        (NXG_RUN_MPU): only the vertex values that fit the budget stay in device
+        memory, the rest in pinned host memory."""
         n = self.n
         if dtype not in _DT:
             raise ValueError("dtype must be float32 or float64")
@@ -246,6 +249,8 @@ class DSSS:
             tp = teleport.to(device=self.device, dtype=dtype).contiguous()
         if scatter:
             flags |= _lib.NXG_RUN_SCATTER
+        if mpu_budget is not None:
+            flags |= _lib.NXG_RUN_MPU
         if capture:
             # a recorded graph reads and writes the buffers at the addresses it was
             # recorded with; it is only replayed for a call passing those addresses
@@ -259,7 +264,8 @@ class DSSS:
                          max_iters=int(iters), tol=float(tol),
                          d_teleport=tp.data_ptr() if tp is not None else None, roots=None,
                          d_values=x.data_ptr(), flags=flags, piece_chunks=int(piece_chunks),
-                         d_stats=stats_out.data_ptr() if stats_out is not None else None)
+                         d_stats=stats_out.data_ptr() if stats_out is not None else None,
+                         vertex_budget=int(mpu_budget or 0))
         st = self._run(d, allow=(_lib.NXG_ENOTCONV,))
         return x, st
 

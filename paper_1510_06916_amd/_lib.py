@@ -26,6 +26,7 @@ NXG_RUN_WARM_START = 0x1
 NXG_RUN_PERSISTENT = 0x2
 NXG_RUN_CAPTURE = 0x4
 NXG_RUN_SCATTER = 0x8
+NXG_RUN_MPU = 0x10
 NXG_ORDER_DST, NXG_ORDER_SRC = 0, 1
 
 
@@ -54,14 +55,17 @@ class RunDesc(ctypes.Structure):
                 ("tol", ctypes.c_double), ("d_teleport", ctypes.c_void_p),
                 ("roots", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
                 ("flags", ctypes.c_uint32), ("d_seeds", ctypes.c_void_p),
-                ("piece_chunks", ctypes.c_int32), ("d_stats", ctypes.c_void_p)]
+                ("piece_chunks", ctypes.c_int32), ("d_stats", ctypes.c_void_p),
+                ("vertex_budget", ctypes.c_int64)]
 
 
 class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("max_level", ctypes.c_int32),
                 ("changed_rounds", ctypes.c_int32), ("reached_edges", ctypes.c_int64),
-                ("device_ms", ctypes.c_double), ("streamed_chunks", ctypes.c_int64)]
+                ("device_ms", ctypes.c_double), ("streamed_chunks", ctypes.c_int64),
+                ("resident_intervals", ctypes.c_int32), ("host_read_bytes", ctypes.c_int64),
+                ("host_write_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -178,6 +178,34 @@ struct pairs_of : std::false_type {};
 template <class P>
 struct pairs_of<P, std::void_t<decltype(P::kPairs)>> : std::bool_constant<P::kPairs> {};
 
+// Mixed-phase update (Alg. 7, Sec. III-B3) with host memory as the slower
+// tier: a PageRank program (plain or weighted) whose launch covers only the
+// source intervals [r_lo, r_hi) of each tile, and whose tiles do one of three
+// things with their sums: store them in a slot of g.partial (a shard hub, or a
+// resident tile's device accumulators), add them into such a slot, or apply the
+// update after adding hub slots [slot, slot + npieces). The apply reads the old
+// value from `own` (the values of the tile's vertices, wherever they live), so
+// a tile whose values are in host memory can gather resident sources.
+constexpr int kMpuApply = 0, kMpuStore = 1, kMpuAdd = 2;
+template <class Base>
+struct ProgMPU : Base {
+    static constexpr bool kRowRange = true;
+    using V = typename Base::val_t;
+    uint32_t r_lo, r_hi;
+    int32_t mode;
+    const V* own;  // the apply's old gathered values, by vertex id
+    __device__ bool row_in(uint32_t r) const { return r - r_lo < r_hi - r_lo; }
+    __device__ typename Base::Ld load(int64_t v) const {
+        return typename Base::Ld{own[v], this->tele ? this->tele[v] : (V)0};
+    }
+};
+
+// Whether a program restricts its launch to a range of source intervals.
+template <class P, class = void>
+struct row_range_of : std::false_type {};
+template <class P>
+struct row_range_of<P, std::void_t<decltype(P::kRowRange)>> : std::bool_constant<P::kRowRange> {};
+
 // PageRank with the stored edge weights: gathers x_u and multiplies by w_e
 // (FP64 accumulation as above).
 template <typename V>
@@ -671,6 +699,7 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         // interval markers), and a pair word adds its one gathered value to two
         // destinations
         constexpr bool kPairs = pairs_of<Prog>::value && !kDst;
+        constexpr bool kRows = row_range_of<Prog>::value;
         constexpr uint32_t kVs = sizeof(val_t) == 8 ? 3u : 2u;  // log2 of the value bytes
         constexpr uint32_t kOOB = 0xFFFFFFF0u;                 // past any value array
         // destination order: a slice whose 64 edges form at most this many runs
@@ -753,12 +782,18 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                 // byte offset of the interval's first value: a scalar unless the
                 // slice holds a marker
                 uint32_t rb = (uint32_t)__builtin_amdgcn_readfirstlane((int)((row * ival) << kVs));
+                uint32_t rl = row;  // the lane's source interval
                 if (mm) {
                     const uint64_t upto = mm & (lt | (1ull << lane));
                     const uint32_t got = __shfl(w & ~kMarker, upto ? 63 - __clzll(upto) : lane);
-                    rb = ((upto ? got : row) * ival) << kVs;
+                    rl = upto ? got : row;
+                    rb = (rl * ival) << kVs;
                     row = (uint32_t)__builtin_amdgcn_readlane((int)(w & ~kMarker), 63 - __clzll(mm));
                 }
+                // a launch over a range of source intervals treats the words of
+                // other intervals as padding
+                bool in_rows = true;
+                if constexpr (kRows) in_rows = prog.row_in(rl);
                 if constexpr (kPairs) {
                     // word kinds by the top three bits: 1xx marker or padding,
                     // 01x header, 001 pair, 000 plain edge
@@ -777,7 +812,7 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                     li[q] = (pr || pl) ? (w & tmask) : disc;
                     li2[q] = pr ? ((w >> 14) & tmask) : disc;
                 } else {
-                    const bool e = (int32_t)w >= 0;
+                    const bool e = (int32_t)w >= 0 && in_rows;
                     off[q] = e ? (__builtin_amdgcn_ubfe(w, (uint32_t)g.sshift, (uint32_t)g.L) << kVs) + rb : kOOB;
                     li[q] = e ? __builtin_amdgcn_ubfe(w, (uint32_t)g.dshift, (uint32_t)g.t) : disc;
                 }
@@ -845,6 +880,28 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
     };
     stream(std::integral_constant<bool, kDstOrder>{});
     __syncthreads();
+
+    if constexpr (row_range_of<Prog>::value) {
+        // mixed-phase update: the tile's sums go to its slot (store or add), or
+        // the hub slots after it are added and the update applied
+        acc_t* hub = reinterpret_cast<acc_t*>(g.partial) + (int64_t)it.slot * g.T;
+        if (prog.mode == kMpuStore) {
+            for (int64_t x = threadIdx.x; x < len; x += WG) hub[x] = acc[x];
+            return;
+        }
+        if (prog.mode == kMpuAdd) {
+            for (int64_t x = threadIdx.x; x < len; x += WG) hub[x] += acc[x];
+            return;
+        }
+        for (int64_t x = threadIdx.x; x < len; x += WG) {
+            acc_t sum = acc[x];
+            for (int p = 0; p < it.npieces; ++p) sum += hub[(int64_t)p * g.T + x];
+            acc[x] = sum;
+        }
+        __syncthreads();
+        apply_range<Prog, WG>(g, ctl, prog, base, len, tile, acc);
+        return;
+    }
 
     // a piece stores its partial in its hub slot; k_finish combines them (its
     // segments carry the tile's scalars, the tile's own slot holds zeros)
@@ -2556,6 +2613,7 @@ nxg_status run_pagerank_captured(nxg_dsss* g, const nxg_run_desc& d, hipStream_t
                                hipMemcpyDeviceToHost, s));
         NXG_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
+        NXG_HIP(hipEventSynchronize(e1));
         NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
         memset(st, 0, sizeof(*st));
         st->iterations = d.max_iters;
@@ -2642,6 +2700,7 @@ nxg_status run_scatter(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.p, sizeof(double) * nstat, hipMemcpyDeviceToHost, s));
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(e1));
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
     const bool conv = d.tol > 0 && done_h;
     if (st) {
@@ -2834,6 +2893,7 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
         const int conv_at = first_converged(w.stats.as<double>(), k, d.tol, s, &resid);
         const int iters = conv_at >= 0 ? conv_at + 1 : k;
         float ms = 0.f;
+        NXG_HIP(hipEventSynchronize(e1));
         NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (st) {
             memset(st, 0, sizeof(*st));
@@ -2847,6 +2907,307 @@ nxg_status run_pagerank(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_r
     // the buffers are released through the allocator on the same stream (so
     // stream-ordered allocators see the frees after the kernels); a carved
     // workspace is not released at all
+    NXG_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-phase update with host memory as the slower tier (NXG_RUN_MPU)
+// ---------------------------------------------------------------------------
+// The first Q source intervals (vertices [0, R), R = Q * I, a whole number of
+// tiles) keep their ping-pong values in device memory; the others keep them in
+// pinned host memory and are staged into a one-interval device buffer when
+// their row of sub-shards is processed. Sub-shards whose source and
+// destination are both outside the resident range go through shard hubs in
+// host memory (Alg. 6's ToHub / FromHub); all others update in place. One
+// iteration follows Alg. 7:
+//   P1  resident tiles, resident source rows: sums stored in the tiles' device
+//       accumulators;
+//   P2  for each non-resident row i (its values staged): resident tiles add
+//       into their accumulators, non-resident tiles store hub slot (tile, i);
+//   P3  non-resident tiles: resident source rows, plus their hub slots in row
+//       order, then the update, written to host memory;
+//   P4  resident tiles: the update from their accumulators.
+// The scalar reduction then works as in every other run.
+
+// x^0 (or the caller's x^0) as gathered values, split at vertex R between the
+// device array and the host array (indexed from R); per-block dangling mass.
+template <typename V>
+__global__ __launch_bounds__(256) void k_init_mpu(int32_t n, int64_t R, const int32_t* __restrict__ deg,
+                                                  const V* __restrict__ tele, const V* __restrict__ x0,
+                                                  int divide, V* __restrict__ cur_d, V* __restrict__ cur_h,
+                                                  double* __restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const V x = x0 ? x0[v] : (tele ? tele[v] : (V)(1.0 / n));
+        const int32_t dg = deg[v];
+        if (dg == 0) s += (double)x;
+        const V c = (divide && dg) ? (V)((double)x / dg) : x;
+        if (v < R)
+            cur_d[v] = c;
+        else
+            cur_h[v - R] = c;
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// x^0 into the caller's output (a run of zero iterations).
+template <typename V>
+__global__ void k_x0_out(int32_t n, const V* __restrict__ tele, V* __restrict__ x) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        x[v] = tele ? tele[v] : (V)(1.0 / n);
+}
+
+// Device address of pinned host memory.
+void* host_dev_ptr(const HostBuf& h) {
+    void* dp = nullptr;
+    NXG_HIP(hipHostGetDevicePointer(&dp, h.p, 0));
+    return dp;
+}
+
+template <typename V>
+nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const Layout& L = g->fwd;
+    const bool weighted = d.program == NXG_PAGERANK_WEIGHTED;
+    if (weighted && !L.has_weight) fail(NXG_EINVAL, "weighted PageRank needs a build with weights");
+    if (g->relabeled) fail(NXG_EUNSUPPORTED, "NXG_RUN_MPU needs natural vertex ids (no RELABEL or DEGREE build)");
+    if (L.host_stream || L.pairs || (g->flags & NXG_BUILD_SCATTER))
+        fail(NXG_EUNSUPPORTED, "NXG_RUN_MPU runs on plain device-resident layouts");
+    if (d.flags & (NXG_RUN_CAPTURE | NXG_RUN_SCATTER | NXG_RUN_PERSISTENT))
+        fail(NXG_EINVAL, "NXG_RUN_MPU cannot be combined with CAPTURE, SCATTER or PERSISTENT");
+    if (L.I & (L.I - 1)) fail(NXG_EUNSUPPORTED, "NXG_RUN_MPU needs an interval size that is a power of two");
+    if (((size_t)L.T + kSpill) * sizeof(double) > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "destination tile does not fit in LDS; rebuild with value_bytes = 8");
+    if ((int64_t)L.n_tiles * L.P > ((int64_t)1 << 24))
+        fail(NXG_EUNSUPPORTED, "too many sub-shards for the mixed-phase schedule; use larger intervals or tiles");
+    int64_t budget = d.vertex_budget;
+    if (budget <= 0) budget = (int64_t)env_int("NXG_VERTEX_BUDGET_MB", 0) << 20;
+    if (budget <= 0)
+        fail(NXG_EINVAL, "NXG_RUN_MPU needs a device memory budget (vertex_budget, or NXG_VERTEX_BUDGET_MB)");
+    const int64_t n = L.n, I = L.I, T = L.T, P = L.P, vb = sizeof(V);
+    // Planner (Sec. III-B3: Q <= B_M / (2 n B_a / P)): each resident vertex costs
+    // its two values and an FP64 accumulator, plus one staged interval; the
+    // resident range moves in whole intervals and whole tiles
+    const int64_t unit = std::max(I, T);
+    int64_t R = (budget - I * vb) / (2 * vb + 8);
+    R = std::max<int64_t>(0, R / unit * unit);
+    const int64_t n_up = (n + unit - 1) / unit * unit;
+    if (R >= n_up) R = n_up;
+    const int64_t Q = std::min<int64_t>(P, R / I);
+    const int64_t Rv = std::min<int64_t>(R, n);                 // resident vertices
+    const int64_t Qt = std::min<int64_t>(L.n_tiles, R / T);     // resident tiles
+    const int64_t Nt = L.n_tiles - Qt, Nr = P - Q;              // non-resident tiles and rows
+    const int64_t hub_slots = Nt * Nr;
+    if (hub_slots * T * 8 > ((int64_t)16 << 30))
+        fail(NXG_EUNSUPPORTED, "shard hubs would exceed 16 GiB of host memory; raise the budget");
+    // group word positions (host) -> chunk ranges of (tile, source rows [a, b))
+    std::vector<int64_t> gw((size_t)L.n_tiles * P + 1);
+    NXG_HIP(hipMemcpyAsync(gw.data(), L.group_word.p, sizeof(int64_t) * gw.size(), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    auto range = [&](int64_t tau, int64_t a, int64_t b, Item& it) {
+        const int64_t w0 = gw[tau * P + a], w1 = gw[tau * P + b];
+        it.c0 = w0 / L.C;
+        it.c1 = w1 > w0 ? (w1 + L.C - 1) / L.C : it.c0;
+    };
+    auto item = [](int64_t tau, int64_t slot, int np) {
+        Item it;
+        it.tile = (int32_t)tau;
+        it.piece = 0;
+        it.npieces = np;
+        it.slot = (int32_t)slot;
+        it.c0 = it.c1 = 0;
+        return it;
+    };
+    // item lists: P1, P2a(i), P2b(i) for each non-resident row, P3, P4
+    std::vector<Item> items;
+    std::vector<int64_t> off;  // first item of each list
+    off.push_back((int64_t)items.size());
+    for (int64_t tau = 0; tau < Qt; ++tau) {  // P1
+        Item it = item(tau, tau, 1);
+        range(tau, 0, Q, it);
+        items.push_back(it);
+    }
+    for (int64_t i = Q; i < P; ++i) {
+        off.push_back((int64_t)items.size());
+        for (int64_t tau = 0; tau < Qt; ++tau) {  // P2a: only tiles the row reaches
+            Item it = item(tau, tau, 1);
+            range(tau, i, i + 1, it);
+            if (it.c1 > it.c0) items.push_back(it);
+        }
+        off.push_back((int64_t)items.size());
+        for (int64_t tau = Qt; tau < L.n_tiles; ++tau) {  // P2b: every hub slot is written
+            Item it = item(tau, (tau - Qt) * Nr + (i - Q), 1);
+            range(tau, i, i + 1, it);
+            items.push_back(it);
+        }
+    }
+    off.push_back((int64_t)items.size());
+    for (int64_t tau = Qt; tau < L.n_tiles; ++tau) {  // P3
+        Item it = item(tau, (tau - Qt) * Nr, (int)Nr);
+        range(tau, 0, Q, it);
+        items.push_back(it);
+    }
+    off.push_back((int64_t)items.size());
+    for (int64_t tau = 0; tau < Qt; ++tau) items.push_back(item(tau, tau, 1));  // P4
+    off.push_back((int64_t)items.size());
+    // device and host memory of the run
+    DevBuf ditems, cur_d, nxt_d, acc_d, stage, tile_s, tile_flag, stats, done, zero, part;
+    ditems.alloc(sizeof(Item) * std::max<size_t>(items.size(), 1), s);
+    NXG_HIP(hipMemcpyAsync(ditems.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
+    cur_d.alloc(vb * std::max<int64_t>(Rv, 1), s);
+    nxt_d.alloc(vb * std::max<int64_t>(Rv, 1), s);
+    acc_d.alloc(sizeof(double) * std::max<int64_t>(Qt * T, 1), s);
+    stage.alloc(vb * I, s);
+    tile_s.alloc(sizeof(double) * 3 * L.n_tiles, s);
+    tile_flag.alloc(sizeof(int32_t) * L.n_tiles, s);
+    const int max_iters = d.max_iters;
+    stats.alloc(sizeof(double) * 4 * (size_t)(max_iters + 2), s);
+    fill<double>(stats.as<double>(), 4 * (int64_t)(max_iters + 2), 0.0, s);
+    done.alloc(sizeof(int32_t), s);
+    fill<int32_t>(done.as<int32_t>(), 1, 0, s);
+    zero.alloc(sizeof(int32_t), s);  // the edge kernels' stop flag, never set
+    fill<int32_t>(zero.as<int32_t>(), 1, 0, s);
+    const int nb = grid_for(n, 256, 1024);
+    part.alloc(sizeof(double) * nb, s);
+    HostBuf cur_h, nxt_h, hub_h;
+    cur_h.alloc(vb * std::max<int64_t>(n - Rv, 1));
+    nxt_h.alloc(vb * std::max<int64_t>(n - Rv, 1));
+    hub_h.alloc(sizeof(double) * std::max<int64_t>(hub_slots * T, 1));
+    V* curh = static_cast<V*>(host_dev_ptr(cur_h));
+    V* nxth = static_cast<V*>(host_dev_ptr(nxt_h));
+    double* hubd = static_cast<double*>(host_dev_ptr(hub_h));
+    const V* tele = (const V*)d.d_teleport;
+    V* vals = (V*)d.d_values;
+    const V* x0 = (d.flags & NXG_RUN_WARM_START) ? vals : nullptr;
+    hipLaunchKernelGGL(k_init_mpu<V>, dim3(nb), dim3(256), 0, s, (int32_t)n, Rv, L.outdeg.as<int32_t>(), tele,
+                       x0, weighted ? 0 : 1, cur_d.as<V>(), curh, part.as<double>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part.as<double>(), nb, stats.as<double>());
+    NXG_CHECK_LAUNCH();
+    if (max_iters == 0 && !x0) {
+        hipLaunchKernelGGL(k_x0_out<V>, dim3(grid_for(n)), dim3(256), 0, s, (int32_t)n, tele, vals);
+        NXG_CHECK_LAUNCH();
+    }
+    Geo geo;
+    memset(&geo, 0, sizeof(geo));
+    geo.words = L.words.as<uint32_t>();
+    geo.chunk_row = L.chunk_row.as<int32_t>();
+    geo.deg = L.outdeg.as<int32_t>();
+    geo.n = L.n;
+    geo.I = L.I;
+    geo.P = L.P;
+    geo.L = L.L;
+    geo.T = L.T;
+    geo.t = L.t;
+    geo.sshift = L.order == NXG_ORDER_SRC ? L.t : 0;
+    geo.dshift = L.order == NXG_ORDER_SRC ? 0 : L.L;
+    geo.order = L.order;
+    geo.n_tiles = L.n_tiles;
+    geo.C = L.C;
+    geo.tile_s = tile_s.as<double>();
+    geo.n_sslots = L.n_tiles;
+    geo.tile_flag = tile_flag.as<int32_t>();
+    const size_t lds = ((size_t)L.T + kSpill) * sizeof(double);
+    using Base = std::conditional_t<std::is_same<V, float>::value, ProgPR<float>, ProgPR<double>>;
+    using BaseW = std::conditional_t<std::is_same<V, float>::value, ProgPRW<float>, ProgPRW<double>>;
+    int64_t host_rd = 0, host_wr = 0;
+    auto launch = [&](int list, const V* cur, const V* own, V* nxt, V* xout, uint32_t r_lo, uint32_t r_hi,
+                      int mode, void* slots, const Ctl& ctl) {
+        const int64_t a = off[list], b = off[list + 1];
+        if (b <= a) return;
+        Geo gl = geo;
+        gl.items = ditems.as<Item>() + a;
+        gl.partial = slots;
+        if (weighted) {
+            ProgMPU<BaseW> pr;
+            static_cast<BaseW&>(pr) = BaseW{cur, nxt, tele, xout, L.weight.as<float>(), d.damping};
+            pr.r_lo = r_lo;
+            pr.r_hi = r_hi;
+            pr.mode = mode;
+            pr.own = own;
+            prepare_iter<ProgMPU<BaseW>, 1024>(lds);
+            launch_items<ProgMPU<BaseW>, 1024>((int)(b - a), lds, s, gl, ctl, pr);
+        } else {
+            ProgMPU<Base> pr;
+            static_cast<Base&>(pr) = Base{cur, nxt, tele, xout, d.damping};
+            pr.r_lo = r_lo;
+            pr.r_hi = r_hi;
+            pr.mode = mode;
+            pr.own = own;
+            prepare_iter<ProgMPU<Base>, 1024>(lds);
+            launch_items<ProgMPU<Base>, 1024>((int)(b - a), lds, s, gl, ctl, pr);
+        }
+    };
+    Events ev;
+    NXG_HIP(hipEventRecord(ev.a, s));
+    V* cd = cur_d.as<V>();
+    V* nd = nxt_d.as<V>();
+    V* ch = curh;  // device addresses of the host arrays (kernels)
+    V* nh = nxth;
+    const V* chost = cur_h.as<V>();  // their host addresses (copies)
+    const V* nhost = nxt_h.as<V>();
+    int k = 0, done_h = 0;
+    const int list_p3 = 1 + 2 * (int)Nr, list_p4 = list_p3 + 1;
+    for (; k < max_iters; ++k) {
+        Ctl ctl{stats.as<double>(), zero.as<int32_t>(), k, d.tol};     // edge kernels: never stop
+        Ctl rctl{stats.as<double>(), done.as<int32_t>(), k, d.tol};    // the scalar reduction
+        V* xout = (d.tol > 0 || k == max_iters - 1) ? vals : nullptr;
+        // P1: resident tiles, resident rows, sums stored in their accumulators
+        launch(0, cd, nullptr, nullptr, nullptr, 0u, (uint32_t)Q, kMpuStore, acc_d.p, ctl);
+        // P2: the non-resident rows, one staged interval at a time
+        for (int64_t i = Q; i < P; ++i) {
+            const int64_t cnt = std::min<int64_t>(I, n - i * I);
+            NXG_HIP(hipMemcpyAsync(stage.p, chost + (i * I - Rv), vb * cnt, hipMemcpyHostToDevice, s));
+            host_rd += vb * cnt;
+            const V* sb = stage.as<V>() - i * I;  // indexed by global vertex id
+            const int l = 1 + 2 * (int)(i - Q);
+            launch(l, sb, nullptr, nullptr, nullptr, (uint32_t)i, (uint32_t)(i + 1), kMpuAdd, acc_d.p, ctl);
+            launch(l + 1, sb, nullptr, nullptr, nullptr, (uint32_t)i, (uint32_t)(i + 1), kMpuStore, hubd, ctl);
+            host_wr += Nt * T * 8;
+        }
+        // P3: non-resident tiles: resident rows, hub slots, update into host memory
+        launch(list_p3, cd, ch - Rv, nh - Rv, xout, 0u, (uint32_t)Q, kMpuApply, hubd, ctl);
+        host_rd += hub_slots * T * 8 + (n - Rv) * vb;
+        host_wr += (n - Rv) * vb;
+        // P4: resident tiles from their accumulators
+        launch(list_p4, cd, cd, nd, xout, 0u, 0u, kMpuApply, acc_d.p, ctl);
+        hipLaunchKernelGGL((k_reduce<ProgPR<V>, 1024>), dim3(1), dim3(1024), 0, s, geo, rctl);
+        NXG_CHECK_LAUNCH();
+        std::swap(cd, nd);
+        std::swap(ch, nh);
+        std::swap(chost, nhost);
+        if (d.tol > 0) {
+            NXG_HIP(hipMemcpyAsync(&done_h, done.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            if (done_h) {
+                ++k;
+                break;
+            }
+        }
+    }
+    NXG_HIP(hipEventRecord(ev.b, s));
+    nxg_status rc = NXG_OK;
+    double resid = 0.0;
+    const int conv_at = first_converged(stats.as<double>(), k, d.tol, s, &resid);
+    const int iters = conv_at >= 0 ? conv_at + 1 : k;
+    float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(ev.b));
+    NXG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = iters;
+        st->converged = conv_at >= 0 ? 1 : 0;
+        st->residual = iters > 0 ? resid : 0.0;
+        st->device_ms = ms;
+        st->resident_intervals = (int32_t)Q;
+        st->host_read_bytes = host_rd;
+        st->host_write_bytes = host_wr;
+    }
+    if (d.tol > 0 && conv_at < 0) rc = NXG_ENOTCONV;
     NXG_HIP(hipStreamSynchronize(s));
     return rc;
 }
@@ -3045,6 +3406,7 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if (!finished) finish_work(k);
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(e1));
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (st) {
         memset(st, 0, sizeof(*st));
@@ -3232,6 +3594,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
             for (int b = 0; b < B; ++b)
                 resid = std::max(resid, hs[(size_t)(max_iters - 1) * 3 * B + B + b]);
             float ms = 0.f;
+            NXG_HIP(hipEventSynchronize(e1));
             NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
             memset(st, 0, sizeof(*st));
             st->iterations = max_iters;
@@ -3284,6 +3647,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     }
     if (conv_at >= 0) iters = conv_at + 1;
     float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(e1));
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (st) {
         memset(st, 0, sizeof(*st));
@@ -3495,6 +3859,7 @@ nxg_status run_multi(nxg_multi* mg, const nxg_run_desc& d, void* const* d_values
     }
     NXG_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(e1));
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (st) {
         double worst = 0.0;
@@ -3631,6 +3996,7 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
         }
     if (conv_at >= 0) iters = conv_at + 1;
     float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(e1));
     NXG_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (st) {
         memset(st, 0, sizeof(*st));
@@ -3698,6 +4064,9 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         if (d.dtype == NXG_F64) return run_scatter<double>(g, d, s, st);
         fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
     }
+    if ((d.flags & NXG_RUN_MPU) &&
+        ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 || d.d_seeds))
+        fail(NXG_EUNSUPPORTED, "NXG_RUN_MPU runs single-column PageRank");
     if (d.batch > 1 || d.d_seeds) {
         if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
         return run_batched(g, d, s, st);
@@ -3707,6 +4076,11 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         case NXG_PAGERANK:
         case NXG_PAGERANK_WEIGHTED:
             if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+            if (d.flags & NXG_RUN_MPU) {
+                if (d.dtype == NXG_F32) return run_pagerank_mpu<float>(g, d, s, st);
+                if (d.dtype == NXG_F64) return run_pagerank_mpu<double>(g, d, s, st);
+                fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
+            }
             if (d.dtype == NXG_F32) return run_pagerank<float>(g, d, s, st);
             if (d.dtype == NXG_F64) return run_pagerank<double>(g, d, s, st);
             fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
