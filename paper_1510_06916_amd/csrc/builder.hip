@@ -110,29 +110,100 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint64_t* __restric
 }
 
 // Exclusive scan of N uint32 counts into int64 offsets, one block of 1024.
-__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t* __restrict__ in,
-                                                   int64_t* __restrict__ out, int64_t N,
-                                                   int64_t* __restrict__ total) {
+// Exclusive prefix sums of N uint32 counts into int64 offsets, in three
+// launches: each block scans its segment of kScanSeg counts (read and written
+// through LDS, so global accesses are coalesced) and stores the segment's
+// total; one block scans the totals; every element then adds its segment's
+// offset.
+constexpr int kScanSeg = 4096;  // counts per block: 1024 threads x 4
+
+__global__ __launch_bounds__(1024) void k_scan_seg(const uint32_t* __restrict__ in, int64_t* __restrict__ out,
+                                                   int64_t N, int64_t* __restrict__ seg_total) {
+    __shared__ uint32_t v[kScanSeg];
     __shared__ int64_t part[1024];
-    const int64_t per = (N + 1023) / 1024;
-    const int64_t a = threadIdx.x * per, b = min(N, a + per);
-    int64_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += in[i];
-    part[threadIdx.x] = s;
+    const int64_t s0 = (int64_t)blockIdx.x * kScanSeg;
+    for (int i = threadIdx.x; i < kScanSeg; i += 1024) v[i] = s0 + i < N ? in[s0 + i] : 0u;
+    __syncthreads();
+    const int a = threadIdx.x * 4;
+    int64_t sum = (int64_t)v[a] + v[a + 1] + v[a + 2] + v[a + 3];
+    part[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        const int64_t x = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
-        part[threadIdx.x] += v;
+        part[threadIdx.x] += x;
         __syncthreads();
     }
     int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (int64_t i = a; i < b; ++i) {
-        uint32_t v = in[i];
-        out[i] = run;
-        run += v;
+    int64_t ex[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ex[k] = run;
+        run += v[a + k];
+    }
+    __syncthreads();
+    __shared__ int64_t res[kScanSeg / 2];
+    // write the 4096 results in two halves through LDS, coalesced
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = a + k - h * (kScanSeg / 2);
+            if (i >= 0 && i < kScanSeg / 2) res[i] = ex[k];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kScanSeg / 2; i += 1024) {
+            const int64_t gi = s0 + h * (kScanSeg / 2) + i;
+            if (gi < N) out[gi] = res[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 1023) seg_total[blockIdx.x] = part[1023];
+}
+
+// Exclusive scan of the segment totals in place (one block); the grand total
+// to *total when given.
+__global__ __launch_bounds__(1024) void k_scan_totals(int64_t* __restrict__ seg, int nseg,
+                                                      int64_t* __restrict__ total) {
+    __shared__ int64_t part[1024];
+    const int per = (nseg + 1023) / 1024;
+    const int a = threadIdx.x * per, b = min(nseg, a + per);
+    int64_t sum = 0;
+    for (int i = a; i < b; ++i) sum += seg[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t x = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = a; i < b; ++i) {
+        const int64_t x = seg[i];
+        seg[i] = run;
+        run += x;
     }
     if (total && threadIdx.x == 1023) *total = part[1023];
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t N, const int64_t* __restrict__ seg) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] += seg[i / kScanSeg];
+}
+
+// out[i] = sum of in[0, i) for i < N; *total (device, nullable) = sum of all.
+void scan_u32(const uint32_t* in, int64_t* out, int64_t N, int64_t* total, hipStream_t s) {
+    const int nseg = (int)std::max<int64_t>(1, (N + kScanSeg - 1) / kScanSeg);
+    DevBuf seg;
+    seg.alloc(sizeof(int64_t) * nseg, s);
+    hipLaunchKernelGGL(k_scan_seg, dim3(nseg), dim3(1024), 0, s, in, out, N, seg.as<int64_t>());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, seg.as<int64_t>(), nseg, total);
+    NXG_CHECK_LAUNCH();
+    if (nseg > 1) {
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)std::min<int64_t>((N + 255) / 256, 8192)), dim3(256), 0, s, out, N, seg.as<int64_t>());
+        NXG_CHECK_LAUNCH();
+    }
 }
 
 // Stable scatter: inside a block keys are ranked in input order (step, thread).
@@ -617,9 +688,7 @@ int radix_sort(DevBuf* kb, DevBuf* vb, int64_t m, int bits, hipStream_t s) {
         hipLaunchKernelGGL(k_rs_count, dim3(nb), dim3(kRsBlock), 0, s, kb[cur].as<uint64_t>(), m,
                            per_block, shift, hist.as<uint32_t>(), nb);
         NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist.as<uint32_t>(),
-                           offs.as<int64_t>(), (int64_t)256 * nb, (int64_t*)nullptr);
-        NXG_CHECK_LAUNCH();
+        scan_u32(hist.as<uint32_t>(), offs.as<int64_t>(), (int64_t)256 * nb, nullptr, s);
         if (hv)
             hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kRsBlock), 0, s,
                                kb[cur].as<uint64_t>(), vb[cur].as<uint32_t>(),
@@ -648,9 +717,7 @@ int64_t dedup(DevBuf* kb, DevBuf* vb, int cur, int64_t m, hipStream_t s) {
     hipLaunchKernelGGL(k_uniq_count, dim3(nb), dim3(kRsBlock), 0, s, kb[cur].as<uint64_t>(), m,
                        per_block, cnt.as<uint32_t>());
     NXG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, cnt.as<uint32_t>(),
-                       off.as<int64_t>(), (int64_t)nb, off.as<int64_t>() + nb);
-    NXG_CHECK_LAUNCH();
+    scan_u32(cnt.as<uint32_t>(), off.as<int64_t>(), (int64_t)nb, off.as<int64_t>() + nb, s);
     if (vb[0].p)
         hipLaunchKernelGGL(k_uniq_scatter<true>, dim3(nb), dim3(kRsBlock), 0, s,
                            kb[cur].as<uint64_t>(), vb[cur].as<uint32_t>(),
