@@ -206,6 +206,13 @@ struct row_range_of : std::false_type {};
 template <class P>
 struct row_range_of<P, std::void_t<decltype(P::kRowRange)>> : std::bool_constant<P::kRowRange> {};
 
+// Whether a program's accumulators start from the current values and an edge
+// into a destination that already holds a value is skipped (no gather).
+template <class P, class = void>
+struct early_exit_of : std::false_type {};
+template <class P>
+struct early_exit_of<P, std::void_t<decltype(P::kEarlyExit)>> : std::bool_constant<P::kEarlyExit> {};
+
 // PageRank with the stored edge weights: gathers x_u and multiplies by w_e
 // (FP64 accumulation as above).
 template <typename V>
@@ -251,6 +258,13 @@ struct ProgBFS {
     using acc_t = int32_t;
     using val_t = int32_t;
     static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    // Bottom-up early exit: rounds are level-synchronous, so an unreached
+    // destination can only be offered level r + 1 in round r + 1 (a source with
+    // a smaller level would have reached it in an earlier round). The first
+    // offer it takes is therefore final, and so is the level of a vertex reached
+    // before; the tile's accumulators start from the current levels and the
+    // remaining edges into a destination that holds a level read nothing.
+    static constexpr bool kEarlyExit = true;
     const int32_t* cur;
     int32_t* nxt;
     uint8_t* chg;  // [n >> bs] block flags: a vertex of the block changed in this round
@@ -660,7 +674,11 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         }
     }
 
-    for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
+    if constexpr (early_exit_of<Prog>::value) {
+        for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.cur[base + x];
+    } else {
+        for (int64_t x = threadIdx.x; x < len; x += WG) acc[x] = prog.identity();
+    }
     __syncthreads();
 
     // the wave index is uniform: chunk indices and interval rows then live in
@@ -812,9 +830,13 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
                     li[q] = (pr || pl) ? (w & tmask) : disc;
                     li2[q] = pr ? ((w >> 14) & tmask) : disc;
                 } else {
-                    const bool e = (int32_t)w >= 0 && in_rows;
+                    bool e = (int32_t)w >= 0 && in_rows;
+                    const uint32_t dl = __builtin_amdgcn_ubfe(w, (uint32_t)g.dshift, (uint32_t)g.t);
+                    // (dl < T for any word, so the read stays in the array; a
+                    // value written by another wave after it is only a missed skip)
+                    if constexpr (early_exit_of<Prog>::value) e = e && acc[dl] == prog.identity();
                     off[q] = e ? (__builtin_amdgcn_ubfe(w, (uint32_t)g.sshift, (uint32_t)g.L) << kVs) + rb : kOOB;
-                    li[q] = e ? __builtin_amdgcn_ubfe(w, (uint32_t)g.dshift, (uint32_t)g.t) : disc;
+                    li[q] = e ? dl : disc;
                 }
             }
         };
