@@ -8,7 +8,7 @@ the GPU library and never imports it.
 Functions follow the paper (Chi et al., "NXgraph", 2015): PageRank by
 synchronous iteration (Alg. 1, Sec. II-B, Sec. III-B1), BFS (Algs. 2-4), WCC
 by minimum-label propagation on the symmetrised graph (Sec. II-A, Sec. IV-D),
-the DSSS edge order (Sec. II-A, Sec. III-A), plus the adjoint of weighted
+SCC by its definition (mutual reachability; named in Sec. IV-D), the DSSS edge order (Sec. II-A, Sec. III-A), plus the adjoint of weighted
 PageRank (not in the paper: the gradient of g^T x* at the fixed point).
 """
 import ctypes
@@ -43,8 +43,9 @@ def _L():
         lib.orc_wcc.argtypes = [i64, i64, p, p, p, p]
         lib.orc_pagerank_adjoint.argtypes = [i64, i64, p, p, p, p, p, dbl, dbl, i64, p, p, p, p]
         lib.orc_dsss_order.argtypes = [i64, i64, p, p, i64, p, p]
+        lib.orc_scc.argtypes = [i64, i64, p, p, p, p]
         for f in (lib.orc_outdeg, lib.orc_pagerank, lib.orc_bfs, lib.orc_wcc,
-                  lib.orc_pagerank_adjoint, lib.orc_dsss_order):
+                  lib.orc_pagerank_adjoint, lib.orc_dsss_order, lib.orc_scc):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -111,6 +112,17 @@ def wcc(n, src, dst):
     rc = _L().orc_wcc(int(n), len(src), _ptr(src), _ptr(dst), _ptr(lab), ctypes.byref(rounds))
     _check(rc, "wcc")
     return lab, int(rounds.value)
+
+
+def scc(n, src, dst):
+    """Returns (labels int32 = smallest vertex id of the strongly connected
+    component, number of components)."""
+    src, dst = _edges(src, dst)
+    lab = np.empty(int(n), dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    rc = _L().orc_scc(int(n), len(src), _ptr(src), _ptr(dst), _ptr(lab), ctypes.byref(cnt))
+    _check(rc, "scc")
+    return lab, int(cnt.value)
 
 
 def pagerank_adjoint(n, src, dst, w, xstar, g, d=0.85, tol=1e-10, max_iters=100000):

@@ -300,3 +300,114 @@ int orc_dsss_order(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
     free(keys);
     return 0;
 }
+
+/*
+ * Strongly connected components. The paper names SCC among its targeted
+ * queries (Sec. IV-D) but gives no algorithm; the reading used is the
+ * definition: u and v share a component when each reaches the other (every
+ * vertex reaches itself), and label[v] is the smallest vertex id of v's
+ * component. Computed with Kosaraju's two depth-first passes: the finishing
+ * order of a search over the graph, then searches over the reversed graph
+ * started in decreasing finishing time, each of which collects exactly one
+ * component. Both searches use explicit stacks. *count = components.
+ */
+static int orc_csr(int64_t n, int64_t m, const int32_t* from, const int32_t* to, int64_t** off_out,
+                   int32_t** adj_out) {
+    int64_t* off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!off || !adj || !pos) {
+        free(off);
+        free(adj);
+        free(pos);
+        return 3;
+    }
+    for (int64_t e = 0; e < m; ++e) off[from[e] + 1] += 1;
+    for (int64_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    for (int64_t v = 0; v < n; ++v) pos[v] = off[v];
+    for (int64_t e = 0; e < m; ++e) adj[pos[from[e]]++] = to[e];
+    free(pos);
+    *off_out = off;
+    *adj_out = adj;
+    return 0;
+}
+
+int orc_scc(int64_t n, int64_t m, const int32_t* src, const int32_t* dst, int32_t* label,
+            int64_t* count) {
+    int rc = check_edges(n, m, src, dst);
+    if (rc) return rc;
+    int64_t *fo = NULL, *ro = NULL;
+    int32_t *fa = NULL, *ra = NULL;
+    if (orc_csr(n, m, src, dst, &fo, &fa)) return 3;
+    if (orc_csr(n, m, dst, src, &ro, &ra)) {
+        free(fo);
+        free(fa);
+        return 3;
+    }
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * nn);   /* vertices by finishing time */
+    int32_t* stk = (int32_t*)malloc(sizeof(int32_t) * nn);     /* search stack: vertices */
+    int64_t* nxt = (int64_t*)malloc(sizeof(int64_t) * nn);     /* next edge to try, per vertex */
+    char* seen = (char*)calloc(nn, 1);
+    int32_t* members = (int32_t*)malloc(sizeof(int32_t) * nn); /* one component's vertices */
+    if (!order || !stk || !nxt || !seen || !members) {
+        free(fo); free(fa); free(ro); free(ra);
+        free(order); free(stk); free(nxt); free(seen); free(members);
+        return 3;
+    }
+    /* pass 1: depth-first over the graph; a vertex is appended to `order`
+       when all its out-neighbours are done */
+    int64_t nfin = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        if (seen[r]) continue;
+        int64_t top = 0;
+        stk[top++] = (int32_t)r;
+        seen[r] = 1;
+        nxt[r] = fo[r];
+        while (top > 0) {
+            int32_t u = stk[top - 1];
+            if (nxt[u] < fo[u + 1]) {
+                int32_t w = fa[nxt[u]++];
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    nxt[w] = fo[w];
+                    stk[top++] = w;
+                }
+            } else {
+                order[nfin++] = u;
+                --top;
+            }
+        }
+    }
+    /* pass 2: over the reversed graph, roots in decreasing finishing time;
+       each search collects one component */
+    memset(seen, 0, nn);
+    int64_t comps = 0;
+    for (int64_t k = n - 1; k >= 0; --k) {
+        int32_t r = order[k];
+        if (seen[r]) continue;
+        int64_t top = 0, cnt = 0;
+        stk[top++] = r;
+        seen[r] = 1;
+        while (top > 0) {
+            int32_t u = stk[--top];
+            members[cnt++] = u;
+            for (int64_t e = ro[u]; e < ro[u + 1]; ++e) {
+                int32_t w = ra[e];
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    stk[top++] = w;
+                }
+            }
+        }
+        int32_t lo = members[0];
+        for (int64_t i = 1; i < cnt; ++i)
+            if (members[i] < lo) lo = members[i];
+        for (int64_t i = 0; i < cnt; ++i) label[members[i]] = lo;
+        ++comps;
+    }
+    *count = comps;
+    free(fo); free(fa); free(ro); free(ra);
+    free(order); free(stk); free(nxt); free(seen); free(members);
+    return 0;
+}
