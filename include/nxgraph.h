@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NXG_ABI_VERSION 8
+#define NXG_ABI_VERSION 9
 
 typedef enum nxg_status {
     NXG_OK = 0,
@@ -244,7 +244,19 @@ typedef enum nxg_program {
     NXG_PAGERANK = 0,          /* x' = d (W x + delta/n) + (1-d) t, W = 1/outdeg */
     NXG_PAGERANK_WEIGHTED = 1, /* same with the stored edge weights as W */
     NXG_BFS = 2,               /* Algs. 2-4: levels from a root, INT32_MAX = unreached */
-    NXG_WCC = 3                /* min-label propagation; needs a SYMMETRIZE build */
+    NXG_WCC = 3,               /* min-label propagation; needs a SYMMETRIZE build */
+    NXG_SCC = 4                /* strongly connected components (named among the targeted
+                                  queries of Sec. IV-D, no algorithm given there): d_values[v]
+                                  = the smallest caller id of v's component. Needs a TRANSPOSE
+                                  build (the backward step streams the reversed layout), dtype
+                                  I32, batch 1, no run flags. Computed by colouring rounds:
+                                  forward min-colour propagation over the unassigned vertices,
+                                  then, per colour, backward reachability of the colour's root
+                                  inside the colour; max_iters bounds the passes of all rounds
+                                  together (NXG_ENOTCONV when they run out, d_values then
+                                  unspecified). Stats: iterations = colouring rounds,
+                                  changed_rounds = passes that changed a value,
+                                  streamed_chunks = chunks streamed over both layouts */
 } nxg_program;
 
 typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
@@ -284,7 +296,7 @@ typedef enum nxg_dtype { NXG_F32 = 0, NXG_F64 = 1, NXG_I32 = 2 } nxg_dtype;
 
 typedef struct nxg_run_desc {
     nxg_program program;
-    nxg_dtype dtype;        /* F32 or F64 for PageRank, I32 for BFS/WCC */
+    nxg_dtype dtype;        /* F32 or F64 for PageRank, I32 for BFS/WCC/SCC */
     int32_t batch;          /* B in [1, 64] value columns. B > 1 (or d_seeds set) runs batched
                                PageRank, FP32, values [n, B] row-major; the build needs
                                value_bytes >= 8 * B (FP64 sums per column in LDS) */
@@ -295,7 +307,7 @@ typedef struct nxg_run_desc {
                                when a round changes nothing (bounded by max_iters). */
     const void* d_teleport; /* [n, B] row-major, dtype of the run; NULL = uniform 1/n */
     const int32_t* roots;   /* BFS: host [B] root ids */
-    void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC label) */
+    void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC/SCC label) */
     uint32_t flags;         /* NXG_RUN_* */
     const int32_t* d_seeds; /* batched personalised PageRank: device [B] seed vertices;
                                column b teleports to seeds[b] (one-hot t). NULL = uniform */

@@ -337,6 +337,16 @@ class DSSS:
                          d_teleport=None, roots=None, d_values=lab.data_ptr(), flags=0)
         return lab, self._run(d)
 
+    def scc(self, max_passes=None):
+        """Strongly connected components: label[v] = smallest caller id of v's
+        component. Needs a build with transpose=True."""
+        n = self.n
+        lab = torch.empty(n, dtype=torch.int32, device=self.device)
+        d = _lib.RunDesc(program=_lib.NXG_SCC, dtype=_lib.NXG_I32, batch=1, damping=0.0,
+                         max_iters=int(max_passes if max_passes is not None else 2**31 - 1), tol=0.0,
+                         d_teleport=None, roots=None, d_values=lab.data_ptr(), flags=0)
+        return lab, self._run(d, allow=(_lib.NXG_ENOTCONV,))
+
     # ---- weighted PageRank and its adjoint ------------------------------
     def set_weights(self, w):
         """Replaces the stored edge weights (input edge order)."""

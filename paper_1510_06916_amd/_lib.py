@@ -20,7 +20,7 @@ NXG_BUILD_HOST_STREAM = 0x80
 NXG_BUILD_PAIRS = 0x100
 NXG_BUILD_SHUFFLE_SCHEDULE = 0x200
 
-NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC = range(4)
+NXG_PAGERANK, NXG_PAGERANK_WEIGHTED, NXG_BFS, NXG_WCC, NXG_SCC = range(5)
 NXG_F32, NXG_F64, NXG_I32 = range(3)
 NXG_RUN_WARM_START = 0x1
 NXG_RUN_PERSISTENT = 0x2

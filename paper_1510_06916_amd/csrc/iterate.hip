@@ -326,6 +326,82 @@ struct ProgWCC {
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
 
+// Strongly connected components (named among the targeted queries of
+// Sec. IV-D, with no algorithm given) by colouring, in rounds over the
+// vertices not yet assigned to a component:
+//   forward  col[v] starts at v's caller id and takes the minimum over the
+//            edges u -> v between unassigned vertices: at the fixed point it is
+//            the smallest caller id among the unassigned vertices reaching v;
+//   backward the vertex whose caller id is its colour (the colour's root)
+//            joins; over the reversed layout v joins when an out-neighbour w
+//            that joined has col[w] == col[v]. The joined vertices of colour c
+//            are those of colour c that reach c: c's component, whose smallest
+//            caller id is c (every member has the same ancestors);
+//   assign   joined vertices take label col[v] and leave.
+// An assigned vertex holds colour kInf, which offers nothing and never changes.
+struct ProgSCCF {
+    using acc_t = int32_t;
+    using val_t = int32_t;
+    static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    const int32_t* cur;
+    int32_t* nxt;
+    uint8_t* chg;
+    uint8_t* opn;  // unused
+    int32_t bs;
+    __device__ acc_t identity() const { return kInf; }
+    __device__ acc_t from_val(int32_t c, float) const { return c; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
+    __device__ bool row_active(uint32_t) const { return true; }
+    static __device__ bool converged(double, double, double) { return false; }
+    struct Ld {
+        int32_t c;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
+                          int& flag) const {
+        const int32_t o = l.c;
+        const int32_t nv = o == kInf ? kInf : (acc < o ? acc : o);
+        nxt[v] = nv;
+        flag = nv != o ? 1 : 0;
+    }
+    __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
+// The backward step on the reversed layout. A joined vertex holds
+// kInf - 1 - col[v], any other kInf (colours are in [0, n), so the two never
+// meet), and the minimum offered to v is kInf - 1 minus the largest colour
+// among its joined out-neighbours. Along a forward edge v -> w between
+// unassigned vertices col[w] <= col[v] (w has every ancestor of v), so v joins
+// exactly when that minimum is kInf - 1 - col[v].
+struct ProgSCCB {
+    using acc_t = int32_t;
+    using val_t = int32_t;
+    static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    const int32_t* cur;
+    int32_t* nxt;
+    uint8_t* chg;
+    uint8_t* opn;  // unused
+    int32_t bs;
+    const int32_t* col;
+    __device__ acc_t identity() const { return kInf; }
+    __device__ acc_t from_val(int32_t q, float) const { return q; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
+    __device__ bool row_active(uint32_t) const { return true; }
+    static __device__ bool converged(double, double, double) { return false; }
+    struct Ld {
+        int32_t q, c;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v], col[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
+                          int& flag) const {
+        const int32_t o = l.q;
+        const int32_t nv = o != kInf ? o : ((l.c != kInf && acc == kInf - 1 - l.c) ? acc : kInf);
+        nxt[v] = nv;
+        flag = nv != o ? 1 : 0;
+    }
+    __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
 // Adjoint of weighted PageRank, iterated on the reversed graph: the gathered
 // array is lambda (indexed by the forward destination), the edge carries the
 // forward weight, and the tile owns forward sources u:
@@ -3444,6 +3520,291 @@ nxg_status run_minprog(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
 }
 
 
+// ---------------------------------------------------------------------------
+// SCC rounds (see ProgSCCF). Every kernel below takes vertices in internal
+// ids; `ids` (NULL: the identity) gives a vertex's caller id.
+// ---------------------------------------------------------------------------
+// Block flags of a wave's 64 consecutive vertices from per-vertex predicates
+// (blocks of 2^bs <= 64 vertices lie inside one wave, the wave's first vertex
+// a multiple of 64): a block's first lane writes its flag, when that vertex is
+// in the graph (in). Called by every lane of the wave.
+__device__ inline void set_block_flags(uint8_t* __restrict__ chg, int64_t v, bool in, bool any, int bs) {
+    const uint64_t m = __ballot(any);
+    const int bl = 1 << bs, lane = lane_id();
+    const int first = lane & ~(bl - 1);
+    const uint64_t bm = (bl == 64 ? ~0ull : (1ull << bl) - 1ull) << first;
+    if (lane == first && in) chg[v >> bs] = (m & bm) != 0;
+}
+
+// Round start: colours of the unassigned vertices (their caller ids; kInf for
+// assigned ones) into both buffers; a block is flagged when it holds an
+// unassigned vertex. Clears the count of vertices left.
+__global__ __launch_bounds__(256) void k_scc_init_fwd(int32_t n, const int32_t* __restrict__ lab,
+                                                      const int32_t* __restrict__ ids,
+                                                      int32_t* __restrict__ c0, int32_t* __restrict__ c1,
+                                                      uint8_t* __restrict__ chg, int bs,
+                                                      unsigned long long* __restrict__ left) {
+    const int64_t n64 = n, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n64; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool in = v < n64;
+        const bool open = in && lab[v] < 0;
+        if (in) c0[v] = c1[v] = open ? (ids ? ids[v] : (int32_t)v) : kInf;
+        set_block_flags(chg, v, in, open, bs);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *left = 0;
+}
+
+// Backward start: each colour's root joins (kInf - 1 - colour), every other vertex
+// holds kInf; a block is flagged when it holds a root.
+__global__ __launch_bounds__(256) void k_scc_init_bwd(int32_t n, const int32_t* __restrict__ lab,
+                                                      const int32_t* __restrict__ ids,
+                                                      const int32_t* __restrict__ col,
+                                                      int32_t* __restrict__ q0, int32_t* __restrict__ q1,
+                                                      uint8_t* __restrict__ chg, int bs) {
+    const int64_t n64 = n, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n64; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool in = v < n64;
+        bool root = false;
+        if (in) {
+            const int32_t c = col[v];
+            root = lab[v] < 0 && c == (ids ? ids[v] : (int32_t)v);
+            q0[v] = q1[v] = root ? kInf - 1 - c : kInf;
+        }
+        set_block_flags(chg, v, in, root, bs);
+    }
+}
+
+// Round end: joined vertices take their colour as label; the others are
+// counted (one atomic per wave).
+__global__ __launch_bounds__(256) void k_scc_assign(int32_t n, int32_t* __restrict__ lab,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ q,
+                                                    unsigned long long* __restrict__ left) {
+    const int64_t n64 = n, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n64; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        bool still = false;
+        if (v < n64 && lab[v] < 0) {
+            if (q[v] != kInf)
+                lab[v] = col[v];
+            else
+                still = true;
+        }
+        const uint64_t m = __ballot(still);
+        if (lane_id() == 0 && m) atomicAdd(left, (unsigned long long)__popcll(m));
+    }
+}
+
+// One layout's state for taking an integer program to its fixed point with
+// block activity, as the BFS/WCC runs do: both value buffers, the block flags
+// and their prefix counts, the compacted chunk lists and the changed flags of
+// one synchronisation block of passes.
+struct ActiveSweep {
+    Layout* L = nullptr;
+    Plan* p = nullptr;
+    Workspace w;
+    int bs = 0, seg = 0, nseg = 0, block = 0;
+    int64_t nb = 0;
+    Geo geo;
+    size_t lds = 0;
+    uint8_t* chg() const { return w.blk.as<uint8_t>(); }
+    unsigned long long* streamed() const { return w.bfsout.as<unsigned long long>(); }
+
+    void init(nxg_dsss* g, Layout& Lr, int piece, int block_, hipStream_t s) {
+        ensure_chunk_ranges(Lr, s);
+        L = &Lr;
+        block = block_;
+        p = get_plan(g, Lr, -piece, true, s);
+        alloc_common(w, Lr, *p, 4, block, s, true);
+        w.buf[0].alloc(sizeof(int32_t) * Lr.n, s);
+        w.buf[1].alloc(sizeof(int32_t) * Lr.n, s);
+        bs = std::min(6, Lr.t);
+        nb = ((int64_t)Lr.n + (1 << bs) - 1) >> bs;
+        seg = 4096;
+        while ((nb + seg) / seg > 256) seg *= 2;
+        nseg = (int)((nb + seg) / seg);
+        w.blk.alloc((size_t)nb, s);
+        w.bpre.alloc(sizeof(int32_t) * (size_t)(nb + 1), s);
+        w.btot.alloc(sizeof(int32_t) * (size_t)nseg, s);
+        w.clist.alloc(sizeof(int64_t) * std::max<int64_t>(Lr.n_chunks, 1), s);
+        w.ccount.alloc(sizeof(int32_t) * Lr.n_tiles, s);
+        w.bfsout.alloc(sizeof(unsigned long long), s);
+        fill<int32_t>(w.ccount.as<int32_t>(), Lr.n_tiles, 0, s);
+        fill<unsigned long long>(streamed(), 1, 0ull, s);
+        geo = make_geo(Lr, *p, w, 4);
+        geo.clist = w.clist.as<int64_t>();
+        geo.ccount = w.ccount.as<int32_t>();
+        geo.split_min = piece;
+        lds = iter_lds(geo, Lr, 4);
+    }
+
+    // Passes from the values in buf[0] until one changes nothing, at most
+    // `budget` of them in all (counted down). mk(cur, nxt) makes the program of
+    // a pass. Returns the buffer that holds the fixed point; *changed = passes
+    // that changed a value. A monotone program changes a value in at most
+    // n + 1 passes; more means the device state is broken (error, no loop).
+    template <class Prog, class Make>
+    int32_t* settle(Make mk, int64_t& budget, int64_t* changed, bool* ok, hipStream_t s) {
+        std::vector<double> hs(4 * (size_t)block);
+        int64_t k = 0;
+        for (;;) {
+            if (k > (int64_t)L->n + 1 + block)
+                fail(NXG_EDEVICE, "SCC pass did not settle within n + 1 passes");
+            if (budget <= 0) {
+                *ok = false;
+                return w.buf[k & 1].as<int32_t>();
+            }
+            const int nb_ = (int)std::min<int64_t>(block, budget);
+            for (int j = 0; j < nb_; ++j, ++k) {
+                hipLaunchKernelGGL(k_blkscan, dim3(nseg), dim3(1024), 0, s, chg(), (const uint8_t*)nullptr,
+                                   nb, seg, w.bpre.as<int32_t>(), (int32_t*)nullptr, w.btot.as<int32_t>(),
+                                   (int32_t*)nullptr, w.ccount.as<int32_t>(), L->n_tiles, streamed(),
+                                   w.stats.as<double>() + 4 * j + 3);
+                NXG_CHECK_LAUNCH();
+                if (L->n_chunks > 0) {
+                    hipLaunchKernelGGL(k_compact, dim3(grid_for(L->n_chunks, 256, 4096)), dim3(256), 0, s,
+                                       L->tile_chunk.as<int64_t>(), L->chunk_tile.as<int32_t>(), L->n_chunks,
+                                       L->chunk_rng.as<int4>(), bs, seg, nseg, w.bpre.as<int32_t>(),
+                                       w.btot.as<int32_t>(), (const int32_t*)nullptr, (const int32_t*)nullptr,
+                                       w.clist.as<int64_t>(), w.ccount.as<int32_t>());
+                    NXG_CHECK_LAUNCH();
+                }
+                Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), j, 0.0};
+                const Prog pr = mk(w.buf[k & 1].as<int32_t>(), w.buf[(k + 1) & 1].as<int32_t>());
+                launch_iter<Prog, 1024>(geo, ctl, pr, *p, lds, s);
+            }
+            budget -= nb_;
+            NXG_HIP(hipMemcpyAsync(hs.data(), w.stats.as<double>(), sizeof(double) * 4 * nb_,
+                                   hipMemcpyDeviceToHost, s));
+            NXG_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < nb_; ++j) {
+                if (hs[4 * j + 3] == 0.0) {
+                    // a pass that changes nothing leaves both buffers equal
+                    return w.buf[k & 1].as<int32_t>();
+                }
+                ++*changed;
+            }
+        }
+    }
+};
+
+struct SccCache : Cached {
+    int piece = 0;
+    ActiveSweep f, b;
+    DevBuf lab, left;
+};
+
+nxg_status run_scc(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    if (!g->has_rev) fail(NXG_EINVAL, "SCC needs a build with NXG_BUILD_TRANSPOSE");
+    if (d.dtype != NXG_I32) fail(NXG_EINVAL, "SCC needs dtype I32");
+    if (d.batch != 1 && d.batch != 0) fail(NXG_EUNSUPPORTED, "SCC runs one problem per call");
+    if (d.flags) fail(NXG_EINVAL, "SCC takes no run flags");
+    if (((size_t)g->fwd.T + kSpill) * 4 > (size_t)lds_budget_bytes(g->device) || g->fwd.T > 65536)
+        fail(NXG_EINVAL, "tile does not fit in LDS");
+    const VMap vm = vmap_of(g);
+    Layout& Lf = g->fwd;
+    const int32_t n = Lf.n;
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = default_piece(Lf.n_chunks, Lf.C, (size_t)Lf.T * 4, cus);
+    const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
+    SccCache* c = nullptr;
+    for (Cached* x : g->cached) {
+        SccCache* m = dynamic_cast<SccCache*>(x);
+        if (m && m->piece == piece && m->f.block == block) c = m;
+    }
+    if (!c) {
+        c = new SccCache();
+        g->cached.push_back(c);
+        PendingEntry pend(g, c);
+        c->piece = piece;
+        c->f.init(g, g->fwd, piece, block, s);
+        c->b.init(g, g->rev, piece, block, s);
+        c->lab.alloc(sizeof(int32_t) * (size_t)n, s);
+        c->left.alloc(sizeof(unsigned long long), s);
+        pend.commit();
+    } else {
+        touch_cached(g, c);
+        fill<unsigned long long>(c->f.streamed(), 1, 0ull, s);
+        fill<unsigned long long>(c->b.streamed(), 1, 0ull, s);
+    }
+    int32_t* lab = c->lab.as<int32_t>();
+    unsigned long long* left = c->left.as<unsigned long long>();
+    const int32_t* ids = vm ? vm.n2o : nullptr;
+    Events ev;
+    NXG_HIP(hipEventRecord(ev.a, s));
+    fill<int32_t>(lab, n, -1, s);
+    int64_t budget = d.max_iters, changed = 0;
+    int32_t rounds = 0;
+    bool ok = true;
+    unsigned long long h_left = (unsigned long long)n;
+    while (h_left > 0 && ok) {
+        ActiveSweep& F = c->f;
+        ActiveSweep& B = c->b;
+        hipLaunchKernelGGL(k_scc_init_fwd, dim3(grid_for(n)), dim3(256), 0, s, n, (const int32_t*)lab, ids,
+                           F.w.buf[0].as<int32_t>(), F.w.buf[1].as<int32_t>(), F.chg(), F.bs, left);
+        NXG_CHECK_LAUNCH();
+        const int bsf = F.bs;
+        int32_t* col = F.settle<ProgSCCF>(
+            [&](const int32_t* cu, int32_t* nx) { return ProgSCCF{cu, nx, F.chg(), nullptr, bsf}; }, budget,
+            &changed, &ok, s);
+        if (!ok) break;
+        hipLaunchKernelGGL(k_scc_init_bwd, dim3(grid_for(n)), dim3(256), 0, s, n, (const int32_t*)lab, ids,
+                           (const int32_t*)col, B.w.buf[0].as<int32_t>(), B.w.buf[1].as<int32_t>(), B.chg(),
+                           B.bs);
+        NXG_CHECK_LAUNCH();
+        const int bsb = B.bs;
+        int32_t* q = B.settle<ProgSCCB>(
+            [&](const int32_t* cu, int32_t* nx) { return ProgSCCB{cu, nx, B.chg(), nullptr, bsb, col}; },
+            budget, &changed, &ok, s);
+        if (!ok) break;
+        hipLaunchKernelGGL(k_scc_assign, dim3(grid_for(n)), dim3(256), 0, s, n, lab, (const int32_t*)col,
+                           (const int32_t*)q, left);
+        NXG_CHECK_LAUNCH();
+        const unsigned long long before = h_left;
+        NXG_HIP(hipMemcpyAsync(&h_left, left, sizeof(h_left), hipMemcpyDeviceToHost, s));
+        NXG_HIP(hipStreamSynchronize(s));
+        ++rounds;
+        // the smallest unassigned caller id is its own colour's root, so a round
+        // assigns at least its component
+        if (h_left >= before) fail(NXG_EDEVICE, "SCC round assigned no vertex");
+    }
+    // the last passes' chunk lists into the streamed counts
+    unsigned long long strm[2] = {0, 0};
+    hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, c->f.w.ccount.as<int32_t>(), Lf.n_tiles,
+                       c->f.streamed());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, c->b.w.ccount.as<int32_t>(),
+                       g->rev.n_tiles, c->b.streamed());
+    NXG_CHECK_LAUNCH();
+    NXG_HIP(hipEventRecord(ev.b, s));
+    // labels out in caller ids; a vertex dropped by degreeing is its own component
+    if (vm)
+        permute_rows<int32_t>(lab, vm.o2n, vm.n, 1, (int32_t*)d.d_values, s, 1, 0, 1);
+    else {
+        hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_for(n)), dim3(256), 0, s, (const int32_t*)lab,
+                           (int32_t*)d.d_values, (int64_t)n);
+        NXG_CHECK_LAUNCH();
+    }
+    NXG_HIP(hipMemcpyAsync(&strm[0], c->f.streamed(), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipMemcpyAsync(&strm[1], c->b.streamed(), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(ev.b));
+    NXG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = rounds;
+        st->converged = ok ? 1 : 0;
+        st->changed_rounds = (int32_t)std::min<int64_t>(changed, INT32_MAX);
+        st->device_ms = ms;
+        st->streamed_chunks = (int64_t)(strm[0] + strm[1]);
+    }
+    return ok ? NXG_OK : NXG_ENOTCONV;
+}
+
 nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     const Layout& L = g->fwd;
     const int B = d.batch;
@@ -4110,6 +4471,8 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         case NXG_WCC:
             if (d.dtype != NXG_I32) fail(NXG_EINVAL, "BFS/WCC need dtype I32");
             return run_minprog(g, d, s, st);
+        case NXG_SCC:
+            return run_scc(g, d, s, st);
         default:
             fail(NXG_EINVAL, "unknown program");
     }
