@@ -249,6 +249,25 @@ def bench_bfs_wcc(args, dev, which):
                "config": {"workload": "bfs rmat-s22-ef16 P=32", "n": n, "m": g.m,
                           "mean_ms": 1e3 * float(np.mean(times)), "roots": len(roots),
                           "stream_passes_per_bfs": float(np.mean(passes))}}
+    elif which == "scc":
+        g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, transpose=True,
+                       order=args.order, relabel=bool(args.relabel))
+        g.scc()  # warm-up (makes the workspace)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lab, st = g.scc()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        _, sizes = np.unique(lab.cpu().numpy(), return_counts=True)
+        res = {"metric": "SCC time (colouring rounds, labels = smallest id per component)",
+               "value": dt * 1e3, "unit": "ms", "n_gpus": 1, "dtype": "i32", "higher_is_better": False,
+               "config": {"workload": "scc rmat-s22-ef16 P=32", "n": n, "m": g.m, "timing": "median of 3",
+                          "rounds": st["iterations"], "changing_passes": st["changed_rounds"],
+                          "stream_passes": st["streamed_chunks"] / g.info()["n_chunks"],
+                          "components": int(len(sizes)), "largest_component": int(sizes.max())}}
     else:
         g = DSSS.build(src, dst, n, interval=interval, value_bytes=4, symmetrize=True,
                        order=args.order, relabel=bool(args.relabel))
@@ -452,6 +471,61 @@ def bench_hoststream(args, dev):
     return res
 
 
+def bench_mpu(args, dev):
+    """Mixed-phase update (Sec. III-B3, Alg. 7) with host memory as the slower
+    tier, on the headline graph with natural ids (edge order from --order):
+    FP32 PageRank iterations at budgets that keep Q of P source intervals in
+    device memory, from Q = P (the SPU) to Q = 0 (the DPU). Beside each, the
+    host bytes the schedule moved and the paper's I/O bound for the same Q
+    (B_e = 4, B_a = 4, B_v = 4; its hubs hold (id, value) pairs per edge, these
+    hold one dense FP64 array per tile and sub-shard)."""
+    import torch
+    from paper_1510_06916_amd import DSSS
+    n = 1 << args.scale
+    src, dst = rmat(args.scale, args.ef, args.seed, dev)
+    I, T = 1 << (args.scale - 4), 16384
+    g = DSSS.build(src, dst, n, interval=I, tile=T, chunk=1024, order=args.order)
+    del src, dst
+    torch.cuda.empty_cache()
+    inf = g.info()
+    m, P = inf["m"], inf["P"]
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    iters = 3
+    rows = []
+    for Q in (P, 3 * P // 4, P // 2, P // 4, 0):
+        budget = Q * I * (2 * 4 + 8) + I * 4
+        g.pagerank(1, out=out, mpu_budget=budget)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = g.pagerank(iters, out=out, mpu_budget=budget)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        rd, wr = st["host_read_bytes"] / iters, st["host_write_bytes"] / iters
+        f = (P - Q) / P
+        paper_rd = m * (4 + f * f * 8) + f * n * 4
+        paper_wr = f * f * m * 8 + f * n * 4
+        rows.append({"Q": st["resident_intervals"], "ms_per_iter": ms, "host_read_gb": rd / 1e9,
+                     "host_write_gb": wr / 1e9, "host_gbs": (rd + wr) / (ms * 1e-3) / 1e9,
+                     "paper_model_read_gb": paper_rd / 1e9, "paper_model_write_gb": paper_wr / 1e9})
+        log("MPU Q=%d: %.2f ms/iter, host read %.2f GB write %.2f GB" % (rows[-1]["Q"], ms, rd / 1e9, wr / 1e9))
+    # the same layout through the plain (all-resident) path
+    g.pagerank(1, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.pagerank(iters, out=out)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / iters
+    mid = [r for r in rows if r["Q"] == P // 2][0]
+    res = {"metric": "PageRank iteration with Q of P intervals resident (MPU)", "value": mid["ms_per_iter"],
+           "unit": "ms", "n_gpus": 1, "dtype": "f32", "higher_is_better": False,
+           "config": {"workload": "mpu rmat-s%d-ef%d natural ids" % (args.scale, args.ef), "n": n,
+                      "order": args.order,
+                      "m": m, "P": P, "interval": I, "tile": T, "value_at_Q": P // 2, "iterations": iters,
+                      "plain_path_ms_per_iter": plain_ms,
+                      "by_Q": rows}}
+    return res
+
+
 def bench_adjoint(args, dev):
     import numpy as np
     import torch
@@ -512,8 +586,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="pagerank",
-                    choices=["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "hoststream",
-                             "all"])
+                    choices=["pagerank", "bfs", "wcc", "scc", "ppr", "multi", "adjoint", "degree",
+                             "hoststream", "mpu", "all"])
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--ef", type=int, default=48)
     ap.add_argument("--seed", type=int, default=3)
@@ -529,8 +603,8 @@ def main():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip timing the destination-sorted layouts and the coarse scatter beside the tuned one")
     ap.add_argument("--no-forms", action="store_true",
-                    help="headline only: skip the batched PPR, forward+backward, 256-graph, BFS and WCC "
-                         "figures the default run adds to its line")
+                    help="headline only: skip the batched PPR, forward+backward, 256-graph, BFS, WCC and "
+                         "SCC figures the default run adds to its line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the DSSS iteration runs on a single MI355X "
@@ -539,11 +613,13 @@ def main():
         sys.exit(2)
     import torch
     dev = torch.device("cuda:0")
-    modes = (["pagerank", "bfs", "wcc", "ppr", "multi", "adjoint", "degree", "hoststream"]
+    modes = (["pagerank", "bfs", "wcc", "scc", "ppr", "multi", "adjoint", "degree", "hoststream", "mpu"]
              if args.mode == "all" else [args.mode])
     runners = {"pagerank": bench_pagerank, "bfs": lambda a, d: bench_bfs_wcc(a, d, "bfs"),
-               "wcc": lambda a, d: bench_bfs_wcc(a, d, "wcc"), "ppr": bench_ppr, "multi": bench_multi,
-               "degree": bench_degree, "hoststream": bench_hoststream, "adjoint": bench_adjoint}
+               "wcc": lambda a, d: bench_bfs_wcc(a, d, "wcc"), "scc": lambda a, d: bench_bfs_wcc(a, d, "scc"),
+               "ppr": bench_ppr, "multi": bench_multi,
+               "degree": bench_degree, "hoststream": bench_hoststream, "adjoint": bench_adjoint,
+               "mpu": bench_mpu}
     for mode in modes:
         log("== mode %s" % mode)
         res = runners[mode](args, dev)
@@ -551,9 +627,9 @@ def main():
         if mode == "pagerank" and args.mode == "pagerank" and not args.no_forms:
             # the rest of the metric on the same line: batched PPR and
             # forward+backward against the plain path, the many-graph launch, and
-            # the BFS / WCC rates of the scale-22 graph
+            # the BFS / WCC rates and the SCC time of the scale-22 graph
             res["forms"] = {}
-            for name in ("ppr", "adjoint", "multi", "bfs", "wcc"):
+            for name in ("ppr", "adjoint", "multi", "bfs", "wcc", "scc"):
                 log("== form %s" % name)
                 t0 = time.perf_counter()
                 r = runners[name](args, dev)

@@ -180,12 +180,15 @@ struct pairs_of<P, std::void_t<decltype(P::kPairs)>> : std::bool_constant<P::kPa
 
 // Mixed-phase update (Alg. 7, Sec. III-B3) with host memory as the slower
 // tier: a PageRank program (plain or weighted) whose launch covers only the
-// source intervals [r_lo, r_hi) of each tile, and whose tiles do one of three
-// things with their sums: store them in a slot of g.partial (a shard hub, or a
-// resident tile's device accumulators), add them into such a slot, or apply the
-// update after adding hub slots [slot, slot + npieces). The apply reads the old
-// value from `own` (the values of the tile's vertices, wherever they live), so
-// a tile whose values are in host memory can gather resident sources.
+// source intervals [r_lo, r_hi) of each tile, and whose items do one of three
+// things with their sums: store them in a slot of g.partial (a shard hub in
+// host memory, or a resident tile's device accumulators), add them into such a
+// slot, or apply the update after adding hub slots [slot, slot + npieces).
+// When a store or add item is one of npieces > 1 pieces of a heavy tile, the
+// pieces add with device-scope atomics (a stored slot is cleared first).
+// The apply reads the old value from `own` (the values of the tile's vertices,
+// wherever they live), so a tile whose values are in host memory can gather
+// resident sources.
 constexpr int kMpuApply = 0, kMpuStore = 1, kMpuAdd = 2;
 template <class Base>
 struct ProgMPU : Base {
@@ -983,6 +986,11 @@ __device__ void iterate_item(const Geo& g, const Ctl& ctl, const Prog& prog, con
         // mixed-phase update: the tile's sums go to its slot (store or add), or
         // the hub slots after it are added and the update applied
         acc_t* hub = reinterpret_cast<acc_t*>(g.partial) + (int64_t)it.slot * g.T;
+        if (prog.mode != kMpuApply && it.npieces > 1) {
+            for (int64_t x = threadIdx.x; x < len; x += WG)
+                if (acc[x] != (acc_t)0) unsafeAtomicAdd(&hub[x], acc[x]);
+            return;
+        }
         if (prog.mode == kMpuStore) {
             for (int64_t x = threadIdx.x; x < len; x += WG) hub[x] = acc[x];
             return;
@@ -3067,6 +3075,13 @@ void* host_dev_ptr(const HostBuf& h) {
     return dp;
 }
 
+// Clears the FP64 slots [list[b] * T, list[b] * T + T) of `acc`, one workgroup each.
+__global__ __launch_bounds__(256) void k_zero_slots(const int32_t* __restrict__ list, double* __restrict__ acc,
+                                                    int64_t T) {
+    double* p = acc + (int64_t)list[blockIdx.x] * T;
+    for (int64_t x = threadIdx.x; x < T; x += 256) p[x] = 0.0;
+}
+
 template <typename V>
 nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     const Layout& L = g->fwd;
@@ -3099,9 +3114,6 @@ nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, n
     const int64_t Rv = std::min<int64_t>(R, n);                 // resident vertices
     const int64_t Qt = std::min<int64_t>(L.n_tiles, R / T);     // resident tiles
     const int64_t Nt = L.n_tiles - Qt, Nr = P - Q;              // non-resident tiles and rows
-    const int64_t hub_slots = Nt * Nr;
-    if (hub_slots * T * 8 > ((int64_t)16 << 30))
-        fail(NXG_EUNSUPPORTED, "shard hubs would exceed 16 GiB of host memory; raise the budget");
     // group word positions (host) -> chunk ranges of (tile, source rows [a, b))
     std::vector<int64_t> gw((size_t)L.n_tiles * P + 1);
     NXG_HIP(hipMemcpyAsync(gw.data(), L.group_word.p, sizeof(int64_t) * gw.size(), hipMemcpyDeviceToHost, s));
@@ -3120,41 +3132,115 @@ nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, n
         it.c0 = it.c1 = 0;
         return it;
     };
+    // Pieces: an item longer than pc chunks is cut into pieces of about pc
+    // chunks, so a heavy tile (natural ids of a skewed graph put a twentieth of
+    // the edges in the first tile) does not hold a launch for one workgroup.
+    // Pieces of a resident tile add into its accumulators atomically (npieces
+    // marks them; P1's are cleared first); pieces of a (non-resident tile, row)
+    // each store into a hub slot of their own.
+    const int cus = num_cus(g->device);
+    const int64_t pc_env = env_int("NXG_PIECE_CHUNKS", 0);
+    auto piece_len = [&](int64_t list_chunks) {
+        if (pc_env > 0) return pc_env;
+        return std::max<int64_t>(8, (list_chunks + 2 * cus - 1) / (2 * cus));
+    };
+    auto chunks_of = [&](int64_t tau, int64_t a, int64_t b) {
+        Item it;
+        range(tau, a, b, it);
+        return it.c1 - it.c0;
+    };
+    auto cut = [](const Item& it, int64_t pc, std::vector<Item>& out, bool own_slots) {
+        const int64_t nc = it.c1 - it.c0;
+        const int64_t k = nc > pc ? (nc + pc - 1) / pc : 1;
+        for (int64_t p = 0; p < k; ++p) {
+            Item q = it;
+            q.c0 = it.c0 + nc * p / k;
+            q.c1 = it.c0 + nc * (p + 1) / k;
+            if (own_slots)
+                q.slot = it.slot + (int32_t)p;
+            else
+                q.npieces = (int32_t)k;
+            out.push_back(q);
+        }
+        return k;
+    };
+    std::vector<int32_t> zero_tiles;  // resident tiles whose P1 pieces add atomically
     // item lists: P1, P2a(i), P2b(i) for each non-resident row, P3, P4
     std::vector<Item> items;
     std::vector<int64_t> off;  // first item of each list
     off.push_back((int64_t)items.size());
-    for (int64_t tau = 0; tau < Qt; ++tau) {  // P1
-        Item it = item(tau, tau, 1);
-        range(tau, 0, Q, it);
-        items.push_back(it);
+    {
+        int64_t lc = 0;
+        for (int64_t tau = 0; tau < Qt; ++tau) lc += chunks_of(tau, 0, Q);
+        const int64_t pc = piece_len(lc);
+        for (int64_t tau = 0; tau < Qt; ++tau) {  // P1: every resident tile's slot is written
+            Item it = item(tau, tau, 1);
+            range(tau, 0, Q, it);
+            if (cut(it, pc, items, false) > 1) zero_tiles.push_back((int32_t)tau);
+        }
     }
+    // hub slots of the non-resident tiles, tile-major: for tile tau the pieces
+    // of rows Q .. P-1 in order (at least one per row, empty ones store zeros)
+    std::vector<int64_t> tslot((size_t)Nt + 1, 0), row_slots((size_t)Nr, 0), row_pc((size_t)Nr, 1);
+    for (int64_t i = Q; i < P; ++i) {
+        int64_t lc = 0;
+        for (int64_t tau = Qt; tau < L.n_tiles; ++tau) lc += chunks_of(tau, i, i + 1);
+        row_pc[i - Q] = piece_len(lc);
+    }
+    for (int64_t tau = Qt; tau < L.n_tiles; ++tau) {
+        int64_t k = 0;
+        for (int64_t i = Q; i < P; ++i) {
+            const int64_t nc = chunks_of(tau, i, i + 1), pc = row_pc[i - Q];
+            const int64_t kk = nc > pc ? (nc + pc - 1) / pc : 1;
+            k += kk;
+            row_slots[i - Q] += kk;
+        }
+        tslot[tau - Qt + 1] = tslot[tau - Qt] + k;
+    }
+    const int64_t hub_slots = tslot[Nt];
+    if (hub_slots * T * 8 > ((int64_t)16 << 30))
+        fail(NXG_EUNSUPPORTED, "shard hubs would exceed 16 GiB of host memory; raise the budget");
+    if (hub_slots > INT32_MAX) fail(NXG_EUNSUPPORTED, "too many shard hub slots");
+    std::vector<int64_t> next_slot(tslot.begin(), tslot.end() - 1);
     for (int64_t i = Q; i < P; ++i) {
         off.push_back((int64_t)items.size());
-        for (int64_t tau = 0; tau < Qt; ++tau) {  // P2a: only tiles the row reaches
-            Item it = item(tau, tau, 1);
-            range(tau, i, i + 1, it);
-            if (it.c1 > it.c0) items.push_back(it);
+        {
+            int64_t lc = 0;
+            for (int64_t tau = 0; tau < Qt; ++tau) lc += chunks_of(tau, i, i + 1);
+            const int64_t pc = piece_len(lc);
+            for (int64_t tau = 0; tau < Qt; ++tau) {  // P2a: only tiles the row reaches
+                Item it = item(tau, tau, 1);
+                range(tau, i, i + 1, it);
+                if (it.c1 > it.c0) cut(it, pc, items, false);
+            }
         }
         off.push_back((int64_t)items.size());
         for (int64_t tau = Qt; tau < L.n_tiles; ++tau) {  // P2b: every hub slot is written
-            Item it = item(tau, (tau - Qt) * Nr + (i - Q), 1);
+            Item it = item(tau, next_slot[tau - Qt], 1);
             range(tau, i, i + 1, it);
-            items.push_back(it);
+            next_slot[tau - Qt] += cut(it, row_pc[i - Q], items, true);
         }
     }
     off.push_back((int64_t)items.size());
     for (int64_t tau = Qt; tau < L.n_tiles; ++tau) {  // P3
-        Item it = item(tau, (tau - Qt) * Nr, (int)Nr);
+        Item it = item(tau, tslot[tau - Qt], (int)(tslot[tau - Qt + 1] - tslot[tau - Qt]));
         range(tau, 0, Q, it);
         items.push_back(it);
     }
     off.push_back((int64_t)items.size());
     for (int64_t tau = 0; tau < Qt; ++tau) items.push_back(item(tau, tau, 1));  // P4
     off.push_back((int64_t)items.size());
+    // each launch takes its items heaviest first (every item names its own slot)
+    for (size_t l = 0; l + 1 < off.size(); ++l)
+        std::stable_sort(items.begin() + off[l], items.begin() + off[l + 1],
+                         [](const Item& a, const Item& b) { return a.c1 - a.c0 > b.c1 - b.c0; });
     // device and host memory of the run
-    DevBuf ditems, cur_d, nxt_d, acc_d, stage, tile_s, tile_flag, stats, done, zero, part;
+    DevBuf ditems, cur_d, nxt_d, acc_d, stage, tile_s, tile_flag, stats, done, zero, part, zslots;
     ditems.alloc(sizeof(Item) * std::max<size_t>(items.size(), 1), s);
+    zslots.alloc(sizeof(int32_t) * std::max<size_t>(zero_tiles.size(), 1), s);
+    if (!zero_tiles.empty())
+        NXG_HIP(hipMemcpyAsync(zslots.p, zero_tiles.data(), sizeof(int32_t) * zero_tiles.size(),
+                               hipMemcpyHostToDevice, s));
     NXG_HIP(hipMemcpyAsync(ditems.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s));
     cur_d.alloc(vb * std::max<int64_t>(Rv, 1), s);
     nxt_d.alloc(vb * std::max<int64_t>(Rv, 1), s);
@@ -3255,6 +3341,11 @@ nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, n
         Ctl rctl{stats.as<double>(), done.as<int32_t>(), k, d.tol};    // the scalar reduction
         V* xout = (d.tol > 0 || k == max_iters - 1) ? vals : nullptr;
         // P1: resident tiles, resident rows, sums stored in their accumulators
+        if (!zero_tiles.empty()) {
+            hipLaunchKernelGGL(k_zero_slots, dim3((unsigned)zero_tiles.size()), dim3(256), 0, s,
+                               zslots.as<int32_t>(), acc_d.as<double>(), T);
+            NXG_CHECK_LAUNCH();
+        }
         launch(0, cd, nullptr, nullptr, nullptr, 0u, (uint32_t)Q, kMpuStore, acc_d.p, ctl);
         // P2: the non-resident rows, one staged interval at a time
         for (int64_t i = Q; i < P; ++i) {
@@ -3265,7 +3356,7 @@ nxg_status run_pagerank_mpu(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, n
             const int l = 1 + 2 * (int)(i - Q);
             launch(l, sb, nullptr, nullptr, nullptr, (uint32_t)i, (uint32_t)(i + 1), kMpuAdd, acc_d.p, ctl);
             launch(l + 1, sb, nullptr, nullptr, nullptr, (uint32_t)i, (uint32_t)(i + 1), kMpuStore, hubd, ctl);
-            host_wr += Nt * T * 8;
+            host_wr += row_slots[i - Q] * T * 8;
         }
         // P3: non-resident tiles: resident rows, hub slots, update into host memory
         launch(list_p3, cd, ch - Rv, nh - Rv, xout, 0u, (uint32_t)Q, kMpuApply, hubd, ctl);

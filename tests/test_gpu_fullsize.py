@@ -100,7 +100,7 @@ def cfg2(gpu_device):
     roots = rmatgen.distinct_vertices(102, 16, n, eligible=deg > 0)
     # oracle results shared by the layouts below
     return {"src_d": src, "dst_d": dst, "src": src_h, "dst": dst_h, "n": n, "roots": roots,
-            "bfs": {}, "wcc": None}
+            "bfs": {}, "wcc": None, "scc": None}
 
 
 def _oracle_bfs(cfg, r):
@@ -136,6 +136,21 @@ def test_cfg2_wcc_bit_exact(gpu_device, cfg2, order, relabel, progress):
     lab, st = g.wcc()
     assert np.array_equal(lab.cpu().numpy(), ref)
     assert st["changed_rounds"] == rounds
+
+
+@pytest.mark.parametrize("order,relabel", [("src", True), ("dst", False)])
+def test_cfg2_scc_bit_exact(gpu_device, cfg2, order, relabel, progress):
+    n = cfg2["n"]
+    g = DSSS.build(cfg2["src_d"], cfg2["dst_d"], n, interval=n // 32, value_bytes=4, transpose=True,
+                   order=order, relabel=relabel)
+    progress("cfg2 scc order=%s relabel=%s" % (order, relabel))
+    if cfg2["scc"] is None:
+        cfg2["scc"] = oracle.scc(n, cfg2["src"], cfg2["dst"])
+    ref, k = cfg2["scc"]
+    lab, st = g.scc()
+    lab = lab.cpu().numpy()
+    assert np.array_equal(lab, ref)
+    assert len(np.unique(lab)) == k and st["converged"] == 1
 
 
 def test_cfg4_batched_ppr_64_seeds(gpu_device, progress):

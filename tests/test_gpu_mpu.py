@@ -35,7 +35,9 @@ def expected_host_bytes(n, I, T, P, Q, vb, iters):
 @pytest.mark.parametrize("dtype,order,Q", [
     (torch.float64, "dst", 0), (torch.float64, "dst", 4), (torch.float64, "src", 8),
     (torch.float64, "src", 16), (torch.float32, "dst", 5), (torch.float32, "src", 0)])
-def test_mpu_scale16(gpu_device, dtype, order, Q):
+def test_mpu_scale16(gpu_device, dtype, order, Q, monkeypatch):
+    # whole items (no pieces), so the host traffic is the schedule's count exactly
+    monkeypatch.setenv("NXG_PIECE_CHUNKS", "1000000")
     n, I, T = 1 << 16, 4096, 4096
     P = n // I
     src, dst = rmatgen.rmat_edges(16, 16, seed=81)
@@ -55,6 +57,34 @@ def test_mpu_scale16(gpu_device, dtype, order, Q):
     # the plain (all resident) run gives the same vector
     xp, _ = g.pagerank(iters, dtype=dtype)
     assert rel_l1(x.cpu().numpy(), xp.cpu().numpy()) <= (1e-13 if dtype == torch.float64 else 1e-6)
+
+
+@pytest.mark.parametrize("order,Q", [("dst", 0), ("dst", 5), ("src", 9), ("dst", 16)])
+def test_mpu_pieces(gpu_device, order, Q, monkeypatch):
+    # pieces of 2 chunks: resident tiles take many atomic adds into their
+    # accumulators, non-resident (tile, row) items spread over hub slots of
+    # their own, and the heavy first tile is split everywhere
+    monkeypatch.setenv("NXG_PIECE_CHUNKS", "2")
+    n, I, T = 1 << 16, 4096, 4096
+    P = n // I
+    src, dst = rmatgen.rmat_edges(16, 16, seed=84)
+    g = DSSS.build(to_dev(src, gpu_device), to_dev(dst, gpu_device), n, interval=I, tile=T, chunk=256,
+                   value_bytes=8, order=order)
+    iters = 8
+    x, st = g.pagerank(iters, dtype=torch.float64, mpu_budget=budget_for(Q, I, 8))
+    ref, _ = oracle.pagerank(n, src, dst, iters=iters)
+    e = rel_l1(x.cpu().numpy(), ref)
+    say("mpu pieces %s Q=%d: rel L1 %.2e, host read %d write %d" % (
+        order, st["resident_intervals"], e, st["host_read_bytes"], st["host_write_bytes"]))
+    assert st["resident_intervals"] == Q and e <= 1e-12
+    rd, wr = expected_host_bytes(n, I, T, P, Q, 8, iters)
+    # a piece of a non-resident tile writes (and the update reads) one more hub slot
+    assert st["host_read_bytes"] >= rd and st["host_write_bytes"] >= wr
+    assert (st["host_read_bytes"] - rd) % (T * 8) == 0 and (st["host_read_bytes"] - rd) == (st["host_write_bytes"] - wr)
+    if Q == P:
+        assert st["host_read_bytes"] == 0 and st["host_write_bytes"] == 0
+    x32, _ = g.pagerank(iters, dtype=torch.float32, mpu_budget=budget_for(Q, I, 4))
+    assert rel_l1(x32.cpu().numpy(), ref) <= 1e-5
 
 
 def test_mpu_weighted_ragged_teleport_tolerance_warm_start(gpu_device):
