@@ -2011,27 +2011,35 @@ __global__ __launch_bounds__(256) void k_init_batched(int32_t n, int B, const in
 
 // delta^0[b] = sum over dangling v of x^0[v][b]. One-hot columns read their
 // seed's degree; uniform columns all get (dangling vertices) / n, counted by
-// the workgroup's 1024 threads over coalesced strides and summed in LDS (an
-// integer count, so the order of the additions does not matter).
-__global__ __launch_bounds__(1024) void k_init_batched_delta(int32_t n, int B, const int32_t* __restrict__ deg,
-                                                             const int32_t* __restrict__ seeds,
-                                                             double* __restrict__ stats) {
+// k_count_dangling's fixed grid (per-workgroup counts, integers, so exact in any
+// order) and summed here in workgroup order.
+constexpr int kDangBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_count_dangling(int32_t n, const int32_t* __restrict__ deg,
+                                                        unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long red[4];
+    unsigned long long c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)kDangBlocks * 256)
+        c += deg[v] == 0 ? 1ull : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(64) void k_init_batched_delta(int32_t n, int B, const int32_t* __restrict__ deg,
+                                                           const int32_t* __restrict__ seeds,
+                                                           const unsigned long long* __restrict__ part,
+                                                           double* __restrict__ stats) {
+    if (threadIdx.x >= B) return;
     if (seeds) {
-        if (threadIdx.x < B) stats[threadIdx.x] = deg[seeds[threadIdx.x]] == 0 ? 1.0 : 0.0;
+        stats[threadIdx.x] = deg[seeds[threadIdx.x]] == 0 ? 1.0 : 0.0;
         return;
     }
-    __shared__ unsigned long long part[16];
-    unsigned long long cnt = 0;
-    for (int64_t v = threadIdx.x; v < n; v += 1024) cnt += deg[v] == 0 ? 1ull : 0ull;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x < B) {
-        unsigned long long tot = 0;
-        for (int w = 0; w < 16; ++w) tot += part[w];
-        stats[threadIdx.x] = (double)tot / n;
-    }
+    unsigned long long tot = 0;
+    for (int w = 0; w < kDangBlocks; ++w) tot += part[w];
+    stats[threadIdx.x] = (double)tot / n;
 }
 
 // Weights in stream order from weights in input order (words that hold an edge).
@@ -3668,23 +3676,30 @@ __global__ __launch_bounds__(256) void k_scc_init_bwd(int32_t n, const int32_t* 
 }
 
 // Round end: joined vertices take their colour as label; the others are
-// counted (one atomic per wave).
+// counted (one atomic per workgroup).
 __global__ __launch_bounds__(256) void k_scc_assign(int32_t n, int32_t* __restrict__ lab,
                                                     const int32_t* __restrict__ col,
                                                     const int32_t* __restrict__ q,
                                                     unsigned long long* __restrict__ left) {
+    __shared__ unsigned long long red[4];
     const int64_t n64 = n, stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0;
     for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n64; v0 += stride) {
         const int64_t v = v0 + threadIdx.x;
-        bool still = false;
         if (v < n64 && lab[v] < 0) {
             if (q[v] != kInf)
                 lab[v] = col[v];
             else
-                still = true;
+                ++cnt;
         }
-        const uint64_t m = __ballot(still);
-        if (lane_id() == 0 && m) atomicAdd(left, (unsigned long long)__popcll(m));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(left, t);
     }
 }
 
@@ -3958,6 +3973,7 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         NXG_HIP(hipMemsetAsync(w.done.p, 0, sizeof(int32_t), s));
         w.buf[0].alloc(sizeof(float) * (size_t)L.n * B, s);
         w.buf[1].alloc(sizeof(float) * (size_t)L.n * B, s);
+        w.bfsout.alloc(sizeof(unsigned long long) * kDangBlocks, s);  // dangling counts per workgroup
     }
     const int32_t* seeds = d.d_seeds;
     if (seeds) {
@@ -3990,8 +4006,14 @@ nxg_status run_batched(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         hipLaunchKernelGGL(k_init_batched, dim3(grid_for((int64_t)L.n * B, 256, 8192)), dim3(256), 0, cs,
                            L.n, B, L.outdeg.as<int32_t>(), seeds, w.buf[0].as<float>(), (double*)nullptr);
         NXG_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(1024), 0, cs, L.n, B, L.outdeg.as<int32_t>(),
-                           seeds, w.stats.as<double>());
+        if (!seeds) {
+            hipLaunchKernelGGL(k_count_dangling, dim3(kDangBlocks), dim3(256), 0, cs, L.n,
+                               L.outdeg.as<int32_t>(), w.bfsout.as<unsigned long long>());
+            NXG_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_init_batched_delta, dim3(1), dim3(64), 0, cs, L.n, B, L.outdeg.as<int32_t>(),
+                           seeds, (const unsigned long long*)w.bfsout.as<unsigned long long>(),
+                           w.stats.as<double>());
         NXG_CHECK_LAUNCH();
     };
     Geo geo = make_geo(L, *p, w, 8);
