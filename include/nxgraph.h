@@ -299,14 +299,19 @@ typedef struct nxg_run_desc {
     nxg_dtype dtype;        /* F32 or F64 for PageRank, I32 for BFS/WCC/SCC */
     int32_t batch;          /* B in [1, 64] value columns. B > 1 (or d_seeds set) runs batched
                                PageRank, FP32, values [n, B] row-major; the build needs
-                               value_bytes >= 8 * B (FP64 sums per column in LDS) */
+                               value_bytes >= 8 * B (FP64 sums per column in LDS).
+                               NXG_BFS with B in [2, 64] runs B searches at once, one per
+                               root (roots[B]): d_values [n, B] int32 levels, row-major; the
+                               set of roots reaching a vertex is one 64-bit mask, so the
+                               build needs value_bytes >= 8; stats: max_level and
+                               changed_rounds over all searches, reached_edges summed */
     double damping;         /* d in [0, 1) */
     int32_t max_iters;      /* upper bound on iterations (>= 0) */
     double tol;             /* PageRank: stop when ||x^{k+1}-x^k||_1 <= tol (per column);
                                <= 0 runs exactly max_iters. BFS/WCC ignore it and stop
                                when a round changes nothing (bounded by max_iters). */
     const void* d_teleport; /* [n, B] row-major, dtype of the run; NULL = uniform 1/n */
-    const int32_t* roots;   /* BFS: host [B] root ids */
+    const int32_t* roots;   /* BFS: host [B] root ids (caller ids, each in [0, n)) */
     void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC/SCC label) */
     uint32_t flags;         /* NXG_RUN_* */
     const int32_t* d_seeds; /* batched personalised PageRank: device [B] seed vertices;

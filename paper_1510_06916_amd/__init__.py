@@ -329,6 +329,19 @@ class DSSS:
                          d_values=lev.data_ptr(), flags=0)
         return lev, self._run(d)
 
+    def bfs_multi(self, roots, max_rounds=None):
+        """BFS from 2..64 roots at once: levels [n, B] int32 (column b from
+        roots[b]). The build needs value_bytes=8."""
+        roots = [int(r) for r in roots]
+        B = len(roots)
+        lev = torch.empty((self.n, B), dtype=torch.int32, device=self.device)
+        rr = (ctypes.c_int32 * B)(*roots)
+        d = _lib.RunDesc(program=_lib.NXG_BFS, dtype=_lib.NXG_I32, batch=B, damping=0.0,
+                         max_iters=int(max_rounds if max_rounds is not None else self.n + 1), tol=0.0,
+                         d_teleport=None, roots=ctypes.cast(rr, ctypes.c_void_p),
+                         d_values=lev.data_ptr(), flags=0)
+        return lev, self._run(d, allow=(_lib.NXG_ENOTCONV,))
+
     def wcc(self, max_rounds=None):
         n = self.n
         lab = torch.empty(n, dtype=torch.int32, device=self.device)

@@ -85,6 +85,10 @@ template <>
 __device__ inline double load_val<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+template <>
+__device__ inline uint64_t load_val<uint64_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return (uint64_t)__builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+}
 
 struct Geo {
     const uint32_t* words;
@@ -329,6 +333,48 @@ struct ProgWCC {
     __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
 };
 
+// Up to 64 BFS at once, one per root: a vertex's state is the set of roots
+// that have reached it (bit b: root b), gathered as a 64-bit mask and combined
+// by OR. Rounds are level-synchronous: in round r a vertex gains exactly the
+// roots at distance r (a root that reached an in-neighbour before round r - 1
+// would have reached the vertex before round r), so its new bits take level r.
+// Levels go to lev[v * B + b]; the mask is the monotone state of the ping-pong.
+struct ProgMSBFS {
+    using acc_t = uint64_t;
+    using val_t = uint64_t;
+    static constexpr bool kSum = false, kWeights = false, kActivity = true;
+    const uint64_t* cur;
+    uint64_t* nxt;
+    uint8_t* chg;
+    uint8_t* opn;  // unused
+    int32_t bs;
+    int32_t* lev;
+    int32_t B;
+    int32_t round;
+    uint64_t full;  // the mask of all B roots
+    __device__ acc_t identity() const { return 0ull; }
+    __device__ acc_t from_val(uint64_t m, float) const { return m; }
+    __device__ acc_t gather(uint32_t src, float w) const { return from_val(cur[src], w); }
+    __device__ bool row_active(uint32_t) const { return true; }
+    static __device__ bool converged(double, double, double) { return false; }
+    struct Ld {
+        uint64_t c;
+    };
+    __device__ Ld load(int64_t v) const { return Ld{cur[v]}; }
+    __device__ void apply(int64_t v, const Ld& l, acc_t acc, int32_t, double, int32_t, double*,
+                          int& flag) const {
+        const uint64_t o = l.c;
+        uint64_t nw = acc & ~o & full;
+        nxt[v] = o | nw;
+        flag = nw ? 1 : 0;
+        while (nw) {
+            lev[v * B + __builtin_ctzll(nw)] = round;
+            nw &= nw - 1;
+        }
+    }
+    __device__ void pass(int64_t v, int32_t) const { nxt[v] = cur[v]; }
+};
+
 // Strongly connected components (named among the targeted queries of
 // Sec. IV-D, with no algorithm given) by colouring, in rounds over the
 // vertices not yet assigned to a component:
@@ -456,6 +502,10 @@ __device__ inline void lds_combine(int32_t* p, int32_t v, bool sum) {
     else
         atomicMin(p, v);
 }
+// 64-bit accumulators are bit sets (one bit per BFS root), combined by OR.
+__device__ inline void lds_combine(uint64_t* p, uint64_t v, bool) {
+    if (v) atomicOr((unsigned long long*)p, (unsigned long long)v);
+}
 
 // Device-scope atomics on the hub of a split tile (native FP64 add, int min).
 __device__ inline void global_combine(double* p, double v, bool) { unsafeAtomicAdd(p, v); }
@@ -468,7 +518,9 @@ __device__ inline void global_combine(int32_t* p, int32_t v, bool sum) {
 
 template <bool kSum, typename A>
 __device__ inline A combine(A a, A b) {
-    if constexpr (kSum)
+    if constexpr (std::is_same<A, uint64_t>::value)
+        return a | b;  // bit sets
+    else if constexpr (kSum)
         return a + b;
     else
         return b < a ? b : a;
@@ -489,11 +541,15 @@ __device__ inline int32_t dpp_val(int32_t old, int32_t v) {
     return __builtin_amdgcn_update_dpp(old, v, kCtl, kRowMask, 0xF, false);
 }
 template <int kCtl, int kRowMask>
-__device__ inline double dpp_val(double old, double v) {
-    const uint64_t o = __builtin_bit_cast(uint64_t, old), x = __builtin_bit_cast(uint64_t, v);
+__device__ inline uint64_t dpp_val(uint64_t o, uint64_t x) {
     const uint32_t lo = dpp_u32<kCtl, kRowMask>((uint32_t)o, (uint32_t)x);
     const uint32_t hi = dpp_u32<kCtl, kRowMask>((uint32_t)(o >> 32), (uint32_t)(x >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int kCtl, int kRowMask>
+__device__ inline double dpp_val(double old, double v) {
+    return __builtin_bit_cast(double, dpp_val<kCtl, kRowMask>(__builtin_bit_cast(uint64_t, old),
+                                                              __builtin_bit_cast(uint64_t, v)));
 }
 
 // Segmented reduction across a wave: the lanes of every run (consecutive lanes
@@ -3718,14 +3774,15 @@ struct ActiveSweep {
     uint8_t* chg() const { return w.blk.as<uint8_t>(); }
     unsigned long long* streamed() const { return w.bfsout.as<unsigned long long>(); }
 
-    void init(nxg_dsss* g, Layout& Lr, int piece, int block_, hipStream_t s) {
+    // vb: bytes of a value (and of an LDS accumulator)
+    void init(nxg_dsss* g, Layout& Lr, int piece, int block_, hipStream_t s, size_t vb = 4) {
         ensure_chunk_ranges(Lr, s);
         L = &Lr;
         block = block_;
         p = get_plan(g, Lr, -piece, true, s);
-        alloc_common(w, Lr, *p, 4, block, s, true);
-        w.buf[0].alloc(sizeof(int32_t) * Lr.n, s);
-        w.buf[1].alloc(sizeof(int32_t) * Lr.n, s);
+        alloc_common(w, Lr, *p, vb, block, s, true);
+        w.buf[0].alloc(vb * Lr.n, s);
+        w.buf[1].alloc(vb * Lr.n, s);
         bs = std::min(6, Lr.t);
         nb = ((int64_t)Lr.n + (1 << bs) - 1) >> bs;
         seg = 4096;
@@ -3739,28 +3796,28 @@ struct ActiveSweep {
         w.bfsout.alloc(sizeof(unsigned long long), s);
         fill<int32_t>(w.ccount.as<int32_t>(), Lr.n_tiles, 0, s);
         fill<unsigned long long>(streamed(), 1, 0ull, s);
-        geo = make_geo(Lr, *p, w, 4);
+        geo = make_geo(Lr, *p, w, vb);
         geo.clist = w.clist.as<int64_t>();
         geo.ccount = w.ccount.as<int32_t>();
         geo.split_min = piece;
-        lds = iter_lds(geo, Lr, 4);
+        lds = iter_lds(geo, Lr, vb);
     }
 
     // Passes from the values in buf[0] until one changes nothing, at most
-    // `budget` of them in all (counted down). mk(cur, nxt) makes the program of
-    // a pass. Returns the buffer that holds the fixed point; *changed = passes
+    // `budget` of them in all (counted down). mk(cur, nxt, k) makes the program
+    // of pass k (from 0). Returns the buffer that holds the fixed point; *changed = passes
     // that changed a value. A monotone program changes a value in at most
     // n + 1 passes; more means the device state is broken (error, no loop).
     template <class Prog, class Make>
-    int32_t* settle(Make mk, int64_t& budget, int64_t* changed, bool* ok, hipStream_t s) {
+    void* settle(Make mk, int64_t& budget, int64_t* changed, bool* ok, hipStream_t s) {
         std::vector<double> hs(4 * (size_t)block);
         int64_t k = 0;
         for (;;) {
             if (k > (int64_t)L->n + 1 + block)
-                fail(NXG_EDEVICE, "SCC pass did not settle within n + 1 passes");
+                fail(NXG_EDEVICE, "a propagation did not settle within n + 1 passes");
             if (budget <= 0) {
                 *ok = false;
-                return w.buf[k & 1].as<int32_t>();
+                return w.buf[k & 1].p;
             }
             const int nb_ = (int)std::min<int64_t>(block, budget);
             for (int j = 0; j < nb_; ++j, ++k) {
@@ -3778,7 +3835,7 @@ struct ActiveSweep {
                     NXG_CHECK_LAUNCH();
                 }
                 Ctl ctl{w.stats.as<double>(), w.done.as<int32_t>(), j, 0.0};
-                const Prog pr = mk(w.buf[k & 1].as<int32_t>(), w.buf[(k + 1) & 1].as<int32_t>());
+                const Prog pr = mk(w.buf[k & 1].p, w.buf[(k + 1) & 1].p, k);
                 launch_iter<Prog, 1024>(geo, ctl, pr, *p, lds, s);
             }
             budget -= nb_;
@@ -3788,7 +3845,7 @@ struct ActiveSweep {
             for (int j = 0; j < nb_; ++j) {
                 if (hs[4 * j + 3] == 0.0) {
                     // a pass that changes nothing leaves both buffers equal
-                    return w.buf[k & 1].as<int32_t>();
+                    return w.buf[k & 1].p;
                 }
                 ++*changed;
             }
@@ -3853,17 +3910,21 @@ nxg_status run_scc(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_st
                            F.w.buf[0].as<int32_t>(), F.w.buf[1].as<int32_t>(), F.chg(), F.bs, left);
         NXG_CHECK_LAUNCH();
         const int bsf = F.bs;
-        int32_t* col = F.settle<ProgSCCF>(
-            [&](const int32_t* cu, int32_t* nx) { return ProgSCCF{cu, nx, F.chg(), nullptr, bsf}; }, budget,
-            &changed, &ok, s);
+        int32_t* col = (int32_t*)F.settle<ProgSCCF>(
+            [&](void* cu, void* nx, int64_t) {
+                return ProgSCCF{(const int32_t*)cu, (int32_t*)nx, F.chg(), nullptr, bsf};
+            },
+            budget, &changed, &ok, s);
         if (!ok) break;
         hipLaunchKernelGGL(k_scc_init_bwd, dim3(grid_for(n)), dim3(256), 0, s, n, (const int32_t*)lab, ids,
                            (const int32_t*)col, B.w.buf[0].as<int32_t>(), B.w.buf[1].as<int32_t>(), B.chg(),
                            B.bs);
         NXG_CHECK_LAUNCH();
         const int bsb = B.bs;
-        int32_t* q = B.settle<ProgSCCB>(
-            [&](const int32_t* cu, int32_t* nx) { return ProgSCCB{cu, nx, B.chg(), nullptr, bsb, col}; },
+        int32_t* q = (int32_t*)B.settle<ProgSCCB>(
+            [&](void* cu, void* nx, int64_t) {
+                return ProgSCCB{(const int32_t*)cu, (int32_t*)nx, B.chg(), nullptr, bsb, col};
+            },
             budget, &changed, &ok, s);
         if (!ok) break;
         hipLaunchKernelGGL(k_scc_assign, dim3(grid_for(n)), dim3(256), 0, s, n, lab, (const int32_t*)col,
@@ -3907,6 +3968,152 @@ nxg_status run_scc(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_st
         st->changed_rounds = (int32_t)std::min<int64_t>(changed, INT32_MAX);
         st->device_ms = ms;
         st->streamed_chunks = (int64_t)(strm[0] + strm[1]);
+    }
+    return ok ? NXG_OK : NXG_ENOTCONV;
+}
+
+// ---------------------------------------------------------------------------
+// Several BFS at once (ProgMSBFS), one per root, B <= 64.
+// ---------------------------------------------------------------------------
+// Roots (caller ids) into the masks and levels: bit b at root b's internal id
+// in both mask buffers, level 0, and its activity block flagged. A root that
+// degreeing dropped (internal id -1) reaches nothing.
+__global__ void k_msbfs_roots(int B, const int32_t* __restrict__ roots, const int32_t* __restrict__ o2n,
+                              uint64_t* __restrict__ m0, uint64_t* __restrict__ m1,
+                              int32_t* __restrict__ lev, uint8_t* __restrict__ chg, int bs) {
+    const int b = threadIdx.x;
+    if (b >= B) return;
+    const int32_t r = o2n ? o2n[roots[b]] : roots[b];
+    if (r < 0) return;
+    atomicOr((unsigned long long*)&m0[r], 1ull << b);
+    atomicOr((unsigned long long*)&m1[r], 1ull << b);
+    lev[(int64_t)r * B + b] = 0;
+    chg[r >> bs] = 1;
+}
+
+// Level 0 at each root's own row of the caller's output (for a root dropped by
+// degreeing, the map-out filled its row with unreached).
+__global__ void k_msbfs_root_rows(int B, const int32_t* __restrict__ roots, int32_t* __restrict__ out) {
+    const int b = threadIdx.x;
+    if (b < B) out[(int64_t)roots[b] * B + b] = 0;
+}
+
+// Edges reached over all searches: sum over v of |roots reaching v| * outdeg(v)
+// (integer, one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_msbfs_reached(int32_t n, const uint64_t* __restrict__ m,
+                                                       const int32_t* __restrict__ deg,
+                                                       unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long red[4];
+    unsigned long long c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256)
+        c += (unsigned long long)__popcll(m[v]) * (unsigned long long)deg[v];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(total, t);
+    }
+}
+
+struct MsbfsCache : Cached {
+    int piece = 0;
+    ActiveSweep f;
+    DevBuf lev, roots, reached;
+    int32_t B = 0;
+};
+
+nxg_status run_msbfs(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
+    const int B = d.batch;
+    if (B < 2 || B > 64) fail(NXG_EINVAL, "batched BFS takes 2 to 64 roots");
+    if (d.dtype != NXG_I32) fail(NXG_EINVAL, "BFS needs dtype I32");
+    if (!d.roots) fail(NXG_EINVAL, "BFS needs roots");
+    if (d.flags) fail(NXG_EINVAL, "batched BFS takes no run flags");
+    if (((size_t)g->fwd.T + kSpill) * 8 > (size_t)lds_budget_bytes(g->device))
+        fail(NXG_EINVAL, "batched BFS keeps 8-byte root sets per destination in LDS; build with value_bytes = 8");
+    const VMap vm = vmap_of(g);
+    const int64_t n_out = vm ? vm.n : g->fwd.n;
+    for (int b = 0; b < B; ++b)
+        if (d.roots[b] < 0 || d.roots[b] >= n_out) fail(NXG_EINVAL, "BFS root outside [0, n)");
+    Layout& L = g->fwd;
+    const int32_t n = L.n;
+    const int cus = num_cus(g->device);
+    int piece = env_int("NXG_PIECE_CHUNKS", 0);
+    if (piece <= 0) piece = default_piece(L.n_chunks, L.C, (size_t)L.T * 8, cus);
+    const int block = std::max(1, env_int("NXG_SYNC_BLOCK", 4));
+    MsbfsCache* c = nullptr;
+    for (Cached* x : g->cached) {
+        MsbfsCache* m = dynamic_cast<MsbfsCache*>(x);
+        if (m && m->piece == piece && m->f.block == block && m->B == B) c = m;
+    }
+    if (!c) {
+        c = new MsbfsCache();
+        g->cached.push_back(c);
+        PendingEntry pend(g, c);
+        c->piece = piece;
+        c->B = B;
+        c->f.init(g, L, piece, block, s, 8);
+        if (vm) c->lev.alloc(sizeof(int32_t) * (size_t)n * B, s);
+        c->roots.alloc(sizeof(int32_t) * B, s);
+        c->reached.alloc(sizeof(unsigned long long), s);
+        pend.commit();
+    } else {
+        touch_cached(g, c);
+        fill<unsigned long long>(c->f.streamed(), 1, 0ull, s);
+    }
+    ActiveSweep& F = c->f;
+    int32_t* lev = vm ? c->lev.as<int32_t>() : (int32_t*)d.d_values;
+    NXG_HIP(hipMemcpyAsync(c->roots.p, d.roots, sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+    Events ev;
+    NXG_HIP(hipEventRecord(ev.a, s));
+    fill<uint64_t>(F.w.buf[0].as<uint64_t>(), n, 0ull, s);
+    fill<uint64_t>(F.w.buf[1].as<uint64_t>(), n, 0ull, s);
+    fill<int32_t>(lev, (int64_t)n * B, kInf, s);
+    fill<uint8_t>(F.chg(), F.nb, (uint8_t)0, s);
+    fill<unsigned long long>(c->reached.as<unsigned long long>(), 1, 0ull, s);
+    hipLaunchKernelGGL(k_msbfs_roots, dim3(1), dim3(64), 0, s, B, (const int32_t*)c->roots.as<int32_t>(),
+                       vm.o2n, F.w.buf[0].as<uint64_t>(), F.w.buf[1].as<uint64_t>(), lev, F.chg(), F.bs);
+    NXG_CHECK_LAUNCH();
+    const uint64_t full = B == 64 ? ~0ull : ((1ull << B) - 1ull);
+    int64_t budget = d.max_iters, changed = 0;
+    bool ok = true;
+    const int bs = F.bs;
+    uint64_t* fin = (uint64_t*)F.settle<ProgMSBFS>(
+        [&](void* cu, void* nx, int64_t k) {
+            return ProgMSBFS{(const uint64_t*)cu, (uint64_t*)nx, F.chg(), nullptr, bs, lev, B, (int32_t)(k + 1),
+                             full};
+        },
+        budget, &changed, &ok, s);
+    hipLaunchKernelGGL(k_count_streamed, dim3(1), dim3(1024), 0, s, F.w.ccount.as<int32_t>(), L.n_tiles,
+                       F.streamed());
+    NXG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_msbfs_reached, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, n, (const uint64_t*)fin,
+                       L.outdeg.as<int32_t>(), c->reached.as<unsigned long long>());
+    NXG_CHECK_LAUNCH();
+    NXG_HIP(hipEventRecord(ev.b, s));
+    if (vm) {
+        permute_rows<int32_t>(lev, vm.o2n, vm.n, B, (int32_t*)d.d_values, s, 1, kInf, 0);
+        hipLaunchKernelGGL(k_msbfs_root_rows, dim3(1), dim3(64), 0, s, B, (const int32_t*)c->roots.as<int32_t>(),
+                           (int32_t*)d.d_values);
+        NXG_CHECK_LAUNCH();
+    }
+    unsigned long long out2[2] = {0, 0};
+    NXG_HIP(hipMemcpyAsync(&out2[0], F.streamed(), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipMemcpyAsync(&out2[1], c->reached.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    NXG_HIP(hipEventSynchronize(ev.b));
+    NXG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->iterations = (int32_t)std::min<int64_t>(changed + 1, INT32_MAX);
+        st->converged = ok ? 1 : 0;
+        st->changed_rounds = (int32_t)changed;
+        st->max_level = (int32_t)changed;  // round r sets level r
+        st->reached_edges = (int64_t)out2[1];
+        st->device_ms = ms;
+        st->streamed_chunks = (int64_t)out2[0];
     }
     return ok ? NXG_OK : NXG_ENOTCONV;
 }
@@ -4563,6 +4770,7 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
     if ((d.flags & NXG_RUN_MPU) &&
         ((d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED) || d.batch > 1 || d.d_seeds))
         fail(NXG_EUNSUPPORTED, "NXG_RUN_MPU runs single-column PageRank");
+    if (d.program == NXG_BFS && d.batch > 1 && !d.d_seeds) return run_msbfs(g, d, s, st);
     if (d.batch > 1 || d.d_seeds) {
         if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
         return run_batched(g, d, s, st);

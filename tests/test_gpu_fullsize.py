@@ -124,6 +124,25 @@ def test_cfg2_bfs_bit_exact(gpu_device, cfg2, order, relabel, nroots, progress):
         assert st["changed_rounds"] == rounds and st["max_level"] == mx
 
 
+def test_cfg2_bfs_all_roots_at_once(gpu_device, cfg2, progress):
+    # the 16 searches in one run (one 64-bit root set per vertex), in the layout
+    # the bench times them
+    n = cfg2["n"]
+    g = DSSS.build(cfg2["src_d"], cfg2["dst_d"], n, interval=n // 32, value_bytes=8, order="src",
+                   relabel=True)
+    roots = cfg2["roots"].tolist()
+    progress("cfg2 bfs, 16 roots at once")
+    lev, st = g.bfs_multi(roots)
+    lev = lev.cpu().numpy()
+    mx = 0
+    for b, r in enumerate(roots):
+        progress("cfg2 bfs column %d (root %d)" % (b, r))
+        ref, rounds, m = _oracle_bfs(cfg2, r)
+        assert np.array_equal(lev[:, b], ref)
+        mx = max(mx, m)
+    assert st["max_level"] == mx
+
+
 @pytest.mark.parametrize("order,relabel", [("src", True), ("dst", False)])
 def test_cfg2_wcc_bit_exact(gpu_device, cfg2, order, relabel, progress):
     n = cfg2["n"]
