@@ -78,3 +78,16 @@ def test_msbfs_refusals(gpu_device):
         g.bfs_multi(list(range(65)))
     lev, st = g.bfs_multi([0, 1], max_rounds=1)
     assert st["status"] in (_lib.NXG_OK, _lib.NXG_ENOTCONV)
+
+
+def test_msbfs_empty_graph(gpu_device):
+    e = torch.zeros(0, dtype=torch.int32, device=gpu_device)
+    n = 50
+    g = DSSS.build(e, e, n, interval=16, value_bytes=8)
+    roots = [3, 49, 3]
+    lev, st = g.bfs_multi(roots)
+    lev = lev.cpu().numpy()
+    want = np.full((n, 3), oracle.INF, dtype=np.int32)
+    for b, r in enumerate(roots):
+        want[r, b] = 0
+    assert np.array_equal(lev, want) and st["max_level"] == 0 and st["reached_edges"] == 0
