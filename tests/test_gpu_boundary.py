@@ -128,6 +128,41 @@ def test_enomem_at_every_run_allocation(gpu_device):
     assert rel_l1(x.cpu().numpy(), ref) <= 1e-12
 
 
+def test_enomem_at_every_scc_and_multi_root_bfs_allocation(gpu_device):
+    # each failure on a fresh handle (the first successful run keeps its
+    # workspace in the handle); after the refused run the handle is destroyed
+    # and nothing allocated through the hook may remain
+    n = 1 << 12
+    src, dst = rmatgen.rmat_edges(12, 8, seed=74)
+    s_d, d_d = to_dev(src, gpu_device), to_dev(dst, gpu_device)
+
+    def fresh():
+        return DSSS.build(s_d, d_d, n, interval=512, tile=1024, chunk=256, relabel=True, order="src",
+                          transpose=True, value_bytes=8)
+    runs = (("scc", lambda g: g.scc()), ("bfs_multi", lambda g: g.bfs_multi([0, 1, 2])))
+    for name, run in runs:
+        g = fresh()
+        with FailingAllocator() as probe:
+            run(g)
+            torch.cuda.synchronize()
+            total = probe.count
+        g.close()
+        say("%s run: %d allocations" % (name, total))
+        assert total >= 3
+        for k in range(total):
+            g = fresh()
+            with FailingAllocator(fail_at=k) as fa:
+                with pytest.raises(_lib.NxgError) as e:
+                    run(g)
+                torch.cuda.synchronize()
+                assert e.value.status == _lib.NXG_ENOMEM, (name, k)
+                g.close()
+                torch.cuda.synchronize()
+                assert fa.live == {}, "%s allocation %d failed: %d buffers left" % (name, k, len(fa.live))
+    g = fresh()
+    assert np.array_equal(g.scc()[0].cpu().numpy(), oracle.scc(n, src, dst)[0])
+
+
 @pytest.mark.parametrize("order,relabel", [("dst", False), ("src", True)])
 def test_shuffled_schedule(gpu_device, order, relabel, monkeypatch):
     # pieces of 2 chunks split the heavy tiles, so pieces, finishing segments
@@ -142,11 +177,17 @@ def test_shuffled_schedule(gpu_device, order, relabel, monkeypatch):
         gp = DSSS.build(s_d, d_d, n, value_bytes=8, shuffle_schedule=shuf, **kw)
         gb = DSSS.build(s_d, d_d, n, value_bytes=4, shuffle_schedule=shuf, **kw)
         gw = DSSS.build(s_d, d_d, n, value_bytes=4, symmetrize=True, shuffle_schedule=shuf, **kw)
+        gs = DSSS.build(s_d, d_d, n, value_bytes=8, transpose=True, shuffle_schedule=shuf, **kw)
         x, _ = gp.pagerank(10, dtype=torch.float64)
         lev, stb = gb.bfs(int(src[0]))
         lab, stw = gw.wcc()
-        res[shuf] = (x.cpu().numpy(), lev.cpu().numpy(), lab.cpu().numpy(), stb, stw)
-    (x0, l0, c0, b0, w0), (x1, l1, c1, b1, w1) = res[False], res[True]
+        scc, _ = gs.scc()
+        mlev, _ = gs.bfs_multi([int(src[0]), int(src[1]), 5])
+        res[shuf] = (x.cpu().numpy(), lev.cpu().numpy(), lab.cpu().numpy(), stb, stw, scc.cpu().numpy(),
+                     mlev.cpu().numpy())
+    (x0, l0, c0, b0, w0, s0, m0), (x1, l1, c1, b1, w1, s1, m1) = res[False], res[True]
+    assert np.array_equal(s1, s0) and np.array_equal(m1, m0)
+    assert np.array_equal(s1, oracle.scc(n, src, dst)[0])
     say("shuffled schedule %s: pagerank rel L1 %.2e" % (order, rel_l1(x1, x0)))
     assert rel_l1(x1, x0) <= 1e-14
     assert np.array_equal(l1, l0) and np.array_equal(c1, c0)
