@@ -166,7 +166,9 @@ typedef struct nxg_build_desc {
     int64_t m;              /* input edges, >= 0 (< 2^31, and < 2^30 with SYMMETRIZE) */
     const int32_t* d_src;   /* [m] source ids in [0, n) */
     const int32_t* d_dst;   /* [m] destination ids in [0, n) */
-    const float* d_weight;  /* [m] edge weights, or NULL (unweighted) */
+    const float* d_weight;  /* [m] edge weights, or NULL (unweighted); each finite, else NXG_EINVAL
+                               (checked on the device before the build; negative weights are
+                               accepted: the iteration is linear in them) */
     int32_t interval;       /* I, interval size; P = ceil(n / I). 0 = planner's choice */
     int32_t tile;           /* destination tile size T, a power of two (tiles are the
                                vertex ranges [k*T, (k+1)*T), any T relative to I);
@@ -310,7 +312,11 @@ typedef struct nxg_run_desc {
     double tol;             /* PageRank: stop when ||x^{k+1}-x^k||_1 <= tol (per column);
                                <= 0 runs exactly max_iters. BFS/WCC ignore it and stop
                                when a round changes nothing (bounded by max_iters). */
-    const void* d_teleport; /* [n, B] row-major, dtype of the run; NULL = uniform 1/n */
+    const void* d_teleport; /* [n, B] row-major, dtype of the run; NULL = uniform 1/n. Each value
+                               finite, else NXG_EINVAL: nxg_run checks a dense teleport on the
+                               device before the run, which synchronises the stream
+                               (nxg_run_noalloc does not check it). Negative entries are
+                               accepted: the iteration is linear in t */
     const int32_t* roots;   /* BFS: host [B] root ids (caller ids, each in [0, n)) */
     void* d_values;         /* [n, B] output values (PageRank x, BFS level, WCC/SCC label) */
     uint32_t flags;         /* NXG_RUN_* */
@@ -462,7 +468,9 @@ nxg_status nxg_multi_destroy(nxg_multi* mg); /* NULL accepted */
 
 /* Replaces the stored edge weights with d_weight [m] (input edge order, FP32)
  * in the forward and, if present, the reversed graph. Needs a build with
- * weights and NXG_BUILD_KEEP_PERM. Asynchronous. */
+ * weights and NXG_BUILD_KEEP_PERM. The weights the layout uses are checked
+ * first (finite, else NXG_EINVAL and the stored weights stay), which
+ * synchronises the stream; the update itself is asynchronous. */
 nxg_status nxg_dsss_set_weights(nxg_dsss* g, const float* d_weight, void* stream);
 
 typedef struct nxg_adjoint_desc {

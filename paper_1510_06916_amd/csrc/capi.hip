@@ -1,5 +1,6 @@
 // The C ABI (include/nxgraph.h): argument checks, the allocator hook, error
 // text, and handle lifetime. Every entry point converts failures into a status.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -115,6 +116,29 @@ nxg_status nxg_multi_destroy(nxg_multi* mg) {
 }  // extern "C"
 
 namespace nxg {
+// Sets *bad when an edge weight is not finite (NaN or infinite).
+__global__ void k_check_weights(const float* __restrict__ w, int64_t m, int32_t* __restrict__ bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = w[i];
+        if (!isfinite(v)) *bad = 1;
+    }
+}
+
+// Edge weights must be finite (NXG_EINVAL otherwise); synchronises s.
+void check_weights(const float* w, int64_t m, hipStream_t s) {
+    if (m <= 0) return;
+    DevBuf bad;
+    bad.alloc(sizeof(int32_t), s);
+    NXG_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    const int64_t blocks = std::min<int64_t>((m + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, m, bad.as<int32_t>());
+    NXG_CHECK_LAUNCH();
+    int32_t hb = 0;
+    NXG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    if (hb) fail(NXG_EINVAL, "edge weights must be finite");
+}
+
 nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
     {
         if (d.n < 1) fail(NXG_EINVAL, "n must be >= 1");
@@ -143,6 +167,7 @@ nxg_dsss* build_handle(const nxg_build_desc& d, hipStream_t s, bool spread) {
         if (sym && (d.d_weight || (d.flags & (NXG_BUILD_KEEP_PERM | NXG_BUILD_TRANSPOSE))))
             fail(NXG_EINVAL, "SYMMETRIZE cannot be combined with weights, KEEP_PERM or TRANSPOSE");
         if (d.interval < 0 || d.interval > d.n) fail(NXG_EINVAL, "interval outside [0, n]");
+        if (d.d_weight) check_weights(d.d_weight, d.m, s);
         nxg_dsss* g = new nxg_dsss();
         try {
             NXG_HIP(hipGetDevice(&g->device));

@@ -4711,12 +4711,38 @@ nxg_status run_adjoint(nxg_dsss* g, const nxg_adjoint_desc& d, hipStream_t s, nx
     return (tol > 0 && conv_at < 0) ? NXG_ENOTCONV : NXG_OK;
 }
 
+// Sets *bad when a weight the layout uses (the input index of a word) is not
+// finite.
+__global__ void k_check_used_weights(const int32_t* __restrict__ perm, int64_t n_words,
+                                     const float* __restrict__ win, int32_t* __restrict__ bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = perm[i];
+        if (e < 0) continue;
+        if (!isfinite(win[e])) *bad = 1;
+    }
+}
+
 void set_weights(nxg_dsss* g, const float* d_w, hipStream_t s) {
     if (g->fwd.host_stream) fail(NXG_EINVAL, "the weights of a HOST_STREAM handle are in host memory");
     for (Layout* L : {&g->fwd, &g->rev}) {
         if (L == &g->rev && !g->has_rev) continue;
         if (!L->has_weight || !L->has_perm)
             fail(NXG_EINVAL, "setting weights needs a build with weights and NXG_BUILD_KEEP_PERM");
+    }
+    // the new weights are checked before any is stored (finite)
+    DevBuf bad;
+    bad.alloc(sizeof(int32_t), s);
+    fill<int32_t>(bad.as<int32_t>(), 1, 0, s);
+    hipLaunchKernelGGL(k_check_used_weights, dim3(grid_for(g->fwd.n_words)), dim3(256), 0, s,
+                       g->fwd.perm.as<int32_t>(), g->fwd.n_words, d_w, bad.as<int32_t>());
+    NXG_CHECK_LAUNCH();
+    int32_t hb = 0;
+    NXG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    if (hb) fail(NXG_EINVAL, "edge weights must be finite");
+    for (Layout* L : {&g->fwd, &g->rev}) {
+        if (L == &g->rev && !g->has_rev) continue;
         hipLaunchKernelGGL(k_set_weights, dim3(grid_for(L->n_words)), dim3(256), 0, s,
                            L->perm.as<int32_t>(), L->n_words, d_w, L->weight.as<float>());
         NXG_CHECK_LAUNCH();
@@ -4745,6 +4771,38 @@ int lds_budget_bytes(int device) {
     return v - 1024;
 }
 
+// Sets *bad when a value is not finite (NaN or infinite).
+template <typename V>
+__global__ void k_check_finite(const V* __restrict__ x, int64_t n, int32_t* __restrict__ bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(x[i])) *bad = 1;
+}
+
+// A dense teleport vector (caller ids) must be finite (NXG_EINVAL); negative
+// entries are accepted, as the iteration is linear in t. Synchronises the
+// stream.
+void check_teleport(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s) {
+    const VMap vm = vmap_of(g);
+    const int64_t n = vm ? vm.n : g->fwd.n;
+    DevBuf bad;
+    bad.alloc(sizeof(int32_t), s);
+    fill<int32_t>(bad.as<int32_t>(), 1, 0, s);
+    if (d.dtype == NXG_F32)
+        hipLaunchKernelGGL(k_check_finite<float>, dim3(grid_for(n)), dim3(256), 0, s,
+                           (const float*)d.d_teleport, n, bad.as<int32_t>());
+    else if (d.dtype == NXG_F64)
+        hipLaunchKernelGGL(k_check_finite<double>, dim3(grid_for(n)), dim3(256), 0, s,
+                           (const double*)d.d_teleport, n, bad.as<int32_t>());
+    else
+        return;  // the dtype is refused by the run itself
+    NXG_CHECK_LAUNCH();
+    int32_t hb = 0;
+    NXG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    NXG_HIP(hipStreamSynchronize(s));
+    if (hb) fail(NXG_EINVAL, "teleport values must be finite");
+}
+
 nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_run_stats* st) {
     if (d.max_iters < 0) fail(NXG_EINVAL, "max_iters must be >= 0");
     if (!d.d_values) fail(NXG_EINVAL, "d_values is NULL");
@@ -4763,6 +4821,7 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         if (d.program != NXG_PAGERANK && d.program != NXG_PAGERANK_WEIGHTED)
             fail(NXG_EUNSUPPORTED, "NXG_RUN_SCATTER runs PageRank");
         if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+        if (d.d_teleport) check_teleport(g, d, s);
         if (d.dtype == NXG_F32) return run_scatter<float>(g, d, s, st);
         if (d.dtype == NXG_F64) return run_scatter<double>(g, d, s, st);
         fail(NXG_EINVAL, "PageRank needs dtype F32 or F64");
@@ -4780,6 +4839,7 @@ nxg_status run_program(nxg_dsss* g, const nxg_run_desc& d, hipStream_t s, nxg_ru
         case NXG_PAGERANK:
         case NXG_PAGERANK_WEIGHTED:
             if (!(d.damping >= 0.0 && d.damping < 1.0)) fail(NXG_EINVAL, "damping outside [0, 1)");
+            if (d.d_teleport) check_teleport(g, d, s);
             if (d.flags & NXG_RUN_MPU) {
                 if (d.dtype == NXG_F32) return run_pagerank_mpu<float>(g, d, s, st);
                 if (d.dtype == NXG_F64) return run_pagerank_mpu<double>(g, d, s, st);

@@ -272,3 +272,48 @@ def test_captured_runs_are_bounded(gpu_device):
     for o in (outs[0], outs[-1]):  # the oldest graph was released and is recorded again
         x, _ = g.pagerank(5, out=o, capture=True)
         assert rel_l1(x.cpu().numpy(), ref) <= 1e-5
+
+
+def test_non_finite_inputs_are_refused(gpu_device):
+    # NaN and infinite weights and teleport entries are refused; negative ones
+    # are accepted (the iteration is linear in both, and gradient checks
+    # perturb them below zero)
+    n = 1 << 10
+    src, dst = rmatgen.rmat_edges(10, 4, seed=75)
+    s_d, d_d = to_dev(src, gpu_device), to_dev(dst, gpu_device)
+    m = len(src)
+    w = torch.rand(m, device=gpu_device, dtype=torch.float32) + 0.1
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        wb = w.clone()
+        wb[m // 2] = bad
+        with pytest.raises(_lib.NxgError) as e:
+            DSSS.build(s_d, d_d, n, interval=256, weights=wb, keep_perm=True, value_bytes=8)
+        assert e.value.status == _lib.NXG_EINVAL
+    g = DSSS.build(s_d, d_d, n, interval=256, weights=w, keep_perm=True, value_bytes=8)
+    x_ok, _ = g.pagerank(5, dtype=torch.float64, weighted=True)
+    wb = w.clone()
+    wb[3] = float("nan")
+    with pytest.raises(_lib.NxgError) as e:
+        g.set_weights(wb)
+    assert e.value.status == _lib.NXG_EINVAL
+    # the refused weights were not stored (the LDS sums' order varies between
+    # runs, so the two agree to rounding)
+    x_again, _ = g.pagerank(5, dtype=torch.float64, weighted=True)
+    assert rel_l1(x_again.cpu().numpy(), x_ok.cpu().numpy()) <= 1e-13
+    t = torch.full((n,), 1.0 / n, dtype=torch.float64, device=gpu_device)
+    for bad in (float("nan"), float("inf")):
+        tb = t.clone()
+        tb[n - 1] = bad
+        with pytest.raises(_lib.NxgError) as e:
+            g.pagerank(5, dtype=torch.float64, teleport=tb)
+        assert e.value.status == _lib.NXG_EINVAL
+    # a teleport with a negative entry runs (and matches the oracle), also
+    # through the relabeled ids
+    tn = t.clone()
+    tn[7] = -2.0 / n
+    tn[8] = 3.0 / n
+    gr = DSSS.build(s_d, d_d, n, interval=256, relabel=True, value_bytes=8)
+    ref, _ = oracle.pagerank(n, src, dst, iters=5, t=tn.cpu().numpy())
+    for gg in (g, gr):
+        x, _ = gg.pagerank(5, dtype=torch.float64, teleport=tn)
+        assert np.abs(x.cpu().numpy() - ref).sum() / np.abs(ref).sum() <= 1e-12
