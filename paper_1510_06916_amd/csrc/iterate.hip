@@ -1249,12 +1249,14 @@ __global__ __launch_bounds__(256) void k_init_pr(int32_t n, const int32_t* __res
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// *out = the sum of part[0, nb), by one wave (64 threads): lane l sums
+// part[l], part[l + 64], ... in order, then the lanes are combined by a fixed
+// butterfly, so the result does not depend on scheduling.
 __global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[b];
-        *out = s;
-    }
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) s += part[b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) *out = s;
 }
 
 // ---------------------------------------------------------------------------
